@@ -1,0 +1,143 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module holds no arithmetic of the method: only voxel masks (geometry),
+material parameters and random current vectors.  Seeds follow
+``1000 + workload index``.  The structures stand in for the paper's examples
+(thin-film inductors, Sec. III.A; the 90-degree bend, Sec. III.C; a layered
+register subsystem, Sec. III.D), whose layouts are not available.
+
+Masks are uint8 arrays indexed [z, y, x] (x fastest in memory).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+MU0 = 4.0e-7 * np.pi
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+def random_currents(seed, shape, dtype=np.complex128):
+    """i.i.d. N(0,1) real and imaginary parts."""
+    g = rng(seed)
+    x = g.standard_normal(shape) + 1j * g.standard_normal(shape)
+    return x.astype(dtype)
+
+
+def full_box(Kx, Ky, Kz):
+    return np.ones((Kz, Ky, Kx), dtype=np.uint8)
+
+
+def random_mask(seed, Kx, Ky, Kz, fill=0.5):
+    """Random voxel occupancy (parity tests of the scatter/gather paths)."""
+    g = rng(seed)
+    m = (g.random((Kz, Ky, Kx)) < fill).astype(np.uint8)
+    if m.sum() == 0:
+        m[0, 0, 0] = 1
+    return m
+
+
+def meander(seed, Kx=64, Ky=64, Kz=16, width=4, thick=2, gap=4, z0=7):
+    """Meander thin-film inductor: ``n`` horizontal lanes joined alternately at
+    the left and right ends (5-7 lanes, seeded)."""
+    g = rng(seed)
+    m = np.zeros((Kz, Ky, Kx), dtype=np.uint8)
+    nl = int(g.integers(5, 8))
+    pitch = width + gap
+    x0, x1 = 4, Kx - 4
+    y0 = (Ky - (nl * pitch - gap)) // 2
+    for i in range(nl):
+        ys = y0 + i * pitch
+        m[z0:z0 + thick, ys:ys + width, x0:x1] = 1
+        if i + 1 < nl:
+            if i % 2 == 0:
+                m[z0:z0 + thick, ys:ys + pitch + width, x1 - width:x1] = 1
+            else:
+                m[z0:z0 + thick, ys:ys + pitch + width, x0:x0 + width] = 1
+    return m
+
+
+def ground_with_holes(g, m, z0, z1, nholes, hmin, hmax):
+    Kz, Ky, Kx = m.shape
+    m[z0:z1, :, :] = 1
+    for _ in range(nholes):
+        hx, hy = int(g.integers(hmin, hmax + 1)), int(g.integers(hmin, hmax + 1))
+        x, y = int(g.integers(0, Kx - hx)), int(g.integers(0, Ky - hy))
+        m[z0:z1, y:y + hy, x:x + hx] = 0
+
+
+def strips_over_ground(seed, Kx=128, Ky=128, Kz=64):
+    """Multi-strip inductor over a ground slab with 16 random rectangular holes;
+    16 strips (width 4, thickness 2) at z in [12,14), each shorted to ground
+    by a via at one end and ending in a via with a one-voxel port gap above
+    the ground at the other."""
+    g = rng(seed)
+    m = np.zeros((Kz, Ky, Kx), dtype=np.uint8)
+    ground_with_holes(g, m, 2, 6, 16, 4, 16)
+    for i in range(16):
+        y = 4 + i * (Ky - 8) // 16
+        length = int(g.integers(40, 101))
+        x = int(g.integers(2, Kx - length - 2))
+        m[12:14, y:y + 4, x:x + length] = 1
+        m[6:12, y:y + 4, x:x + 4] = 1             # shorted via
+        m[7:12, y:y + 4, x + length - 4:x + length] = 1  # port via, gap at z=6
+        m[2:6, y:y + 4, x:x + 4] = 1              # keep ground under the vias
+        m[2:6, y:y + 4, x + length - 4:x + length] = 1
+    return m
+
+
+def sharp_bend(seed, Kx=96, Ky=96, Kz=32, width=6, thick=2):
+    """90-degree sharp bend strip over a ground plane (Sec. III.C stand-in)."""
+    g = rng(seed)
+    m = np.zeros((Kz, Ky, Kx), dtype=np.uint8)
+    m[2:6, :, :] = 1
+    zs = 12
+    c = int(g.integers(40, 56))
+    m[zs:zs + thick, c:c + width, 8:c + width] = 1
+    m[zs:zs + thick, 8:c + width, c:c + width] = 1
+    m[6:zs, c:c + width, 8:8 + width] = 1          # shorted via
+    m[7:zs, 8:8 + width, c:c + width] = 1          # port via, gap at z=6
+    return m
+
+
+def manhattan_layer(g, m, z0, z1, fill, w=4):
+    Kz, Ky, Kx = m.shape
+    area = Kx * Ky
+    while m[z0].sum() < fill * area:
+        length = int(g.integers(16, max(17, Kx // 2)))
+        if g.random() < 0.5:
+            x = int(g.integers(0, Kx - length)); y = int(g.integers(0, Ky - w))
+            m[z0:z1, y:y + w, x:x + length] = 1
+        else:
+            x = int(g.integers(0, Kx - w)); y = int(g.integers(0, Ky - length))
+            m[z0:z1, y:y + length, x:x + w] = 1
+
+
+def layered_stack(seed, Kx=256, Ky=256, Kz=128):
+    """Three-layer stack: ground plane z in [4,12) with 64 holes and two wiring
+    layers z in [40,48) and [80,88) of random Manhattan traces at 20 % fill."""
+    g = rng(seed)
+    m = np.zeros((Kz, Ky, Kx), dtype=np.uint8)
+    ground_with_holes(g, m, 4, 12, 64, 4, 16)
+    manhattan_layer(g, m, 40, 48, 0.20)
+    manhattan_layer(g, m, 80, 88, 0.20)
+    return m
+
+
+# Workload table: grid, voxel size, material (sigma0 S/m, London depth m,
+# frequencies Hz), RHS count, and the mask generator.
+WORKLOADS = {
+    "c1_cube8": dict(K=(8, 8, 8), dx=1e-6, sigma0=1e7, lam=90e-9, freqs=[10e9], nrhs=1,
+                     mask=lambda: full_box(8, 8, 8), seed=1000),
+    "c2_meander": dict(K=(64, 64, 16), dx=0.25e-6, sigma0=1e7, lam=90e-9, freqs=[10e9], nrhs=1,
+                       mask=lambda: meander(1001), seed=1001),
+    "c3_strips": dict(K=(128, 128, 64), dx=0.25e-6, sigma0=1e7, lam=90e-9, freqs=[10e9], nrhs=16,
+                      mask=lambda: strips_over_ground(1002), seed=1002),
+    "c4_bend": dict(K=(96, 96, 32), dx=0.25e-6, sigma0=1e7, lam=90e-9, freqs=[10e9], nrhs=1,
+                    mask=lambda: sharp_bend(1003), seed=1003),
+    "c5_stack": dict(K=(256, 256, 128), dx=0.5e-6, sigma0=1e7, lam=90e-9,
+                     freqs=list(1e9 * 50.0 ** (np.arange(8) / 7.0)), nrhs=8,
+                     mask=lambda: layered_stack(1004), seed=1004),
+}
