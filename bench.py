@@ -1,0 +1,213 @@
+"""Benchmark of the batched FFT-VIE matrix-vector product on one MI355X.
+
+One step = one batched application of the operator (Tucker restoration of the
+circulant spectrum, then the five FFT / product passes and the diagonal term)
+to every right-hand side of the workload: the 256 x 256 x 128 three-layer
+stack, 8 ports x 8 frequencies = 64 right-hand sides, three current
+components each.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line (metric, value = FP32 matvecs/s, FP64 figures beside it,
+roofline of the dominant kernel, oracle CPU baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def pass_bytes(p, nvec, cs, ts, K, nzp):
+    """Algorithmic HBM bytes of each kernel for one launch over nvec vectors.
+
+    X  : read compact x, write the x-transformed planes (nzp * Ky * Lx)
+    Y  : read those, write nzp * Ly * Lx
+    Z  : read and write nzp * Ly * Lx, read the spectrum once (Lx Ly Lz)
+    Yi : read nzp * Ly * Lx, write nzp * Ky * Lx
+    Xi : read nzp * Ky * Lx and compact x and c/dx, write compact y
+    """
+    Lx, Ly, Lz = p.L
+    Ky = p.Ky
+    a = nzp * Ky * Lx * cs
+    b = nzp * Ly * Lx * cs
+    v = K * cs
+    return {
+        "pass_x": nvec * (v + a),
+        "pass_y": nvec * (a + b),
+        "pass_z_mul": nvec * 2 * b + Lx * Ly * Lz * ts,
+        "pass_yi": nvec * (b + a),
+        "pass_xi": nvec * (a + 3 * v),
+    }
+
+
+def cpu_baseline(mask, dx, x, fidx, freqs, sigma0, lam, budget_s=20.0):
+    """The oracle's dense row sum, timed on a bounded sample of observer voxels
+    (each gives all components of all right-hand sides)."""
+    from oracle import green
+    from oracle import operator as op
+    P = op.voxel_coords(mask)
+    K = P.shape[0]
+    nrhs = x.shape[0]
+    rng = np.random.default_rng(7)
+    rows = rng.choice(K, size=64, replace=False)
+    done = 0
+    t0 = time.perf_counter()
+    while done < len(rows) and time.perf_counter() - t0 < budget_s:
+        l = rows[done]
+        Tl = green.family_values("M0", P - P[l])
+        for r in range(nrhs):
+            f = fidx[r]
+            w = 2 * np.pi * freqs[f]
+            c = op.material_c(freqs[f], sigma0, lam)
+            for b in range(3):
+                _ = 1j * w * op.MU0 * dx * (Tl @ x[r, b]) + c / dx * x[r, b, l]
+        done += 1
+    dt = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0))
+    # one observer voxel = 3 * nrhs of the 3K outputs of nrhs matvecs
+    mv_per_s = done * nrhs / K / dt
+    return {"value": mv_per_s, "unit": "matvecs/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} observer voxels x 3 components x {nrhs} RHS of the dense O(N^2) row sum "
+                      f"(K={K}), {dt:.1f} s; numpy threads={os.environ.get('OMP_NUM_THREADS', 'default')}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c5_stack")
+    ap.add_argument("--nrhs", type=int, default=64)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--fp64-steps", type=int, default=5)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is not built "
+                                   "(--gpus must be 1)"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2105_08627_amd as svh
+    import workloads as wl
+
+    dev = torch.device("cuda:0")
+    cfg = wl.WORKLOADS[args.workload]
+    mask = cfg["mask"]()
+    dx, freqs, sigma0, lam = cfg["dx"], cfg["freqs"], cfg["sigma0"], cfg["lam"]
+    nrhs = args.nrhs
+    nf = len(freqs)
+    fidx = [r % nf for r in range(nrhs)]
+    log(f"[bench] workload {args.workload} grid {mask.shape[::-1]} K={int(mask.sum())} nrhs={nrhs}")
+    t = time.perf_counter()
+    p = svh.Problem(mask, dx)
+    p.set_material(freqs, sigma0, lam)
+    p.setup_tensors()
+    ranks, terr = p.tucker_compress(args.tol)
+    log(f"[bench] setup {time.perf_counter() - t:.1f}s  L={p.L} tucker ranks {ranks} bound {terr:.2e}")
+    K = p.K
+    nzp = int(np.count_nonzero(mask.reshape(mask.shape[0], -1).any(axis=1)))
+    x64_h = wl.random_currents(cfg["seed"], (nrhs, 3, K))
+    x64 = torch.from_numpy(x64_h).to(dev)
+    x32 = x64.to(torch.complex64)
+    y32 = torch.empty_like(x32)
+    y64 = torch.empty_like(x64)
+    torch.cuda.synchronize()
+
+    # FP32 (production path), timed
+    for _ in range(args.warmup):
+        p.matvec(x32, fidx, out=y32)
+    torch.cuda.synchronize()
+    p.profile(True)
+    p.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        p.matvec(x32, fidx, out=y32)
+    torch.cuda.synchronize()
+    dt32 = time.perf_counter() - t0
+    prof32, ncall = p.profile_read()
+    p.profile(False)
+    log(f"[bench] fp32 {args.steps} steps {dt32 * 1e3 / args.steps:.3f} ms/step  per-kernel ms/call "
+        + " ".join(f"{k}={v / max(ncall, 1):.3f}" for k, v in prof32.items()))
+
+    # FP64 path
+    for _ in range(1):
+        p.matvec(x64, fidx, out=y64)
+    torch.cuda.synchronize()
+    p.profile(True)
+    p.profile_read()
+    t0 = time.perf_counter()
+    for _ in range(args.fp64_steps):
+        p.matvec(x64, fidx, out=y64)
+    torch.cuda.synchronize()
+    dt64 = time.perf_counter() - t0
+    prof64, ncall64 = p.profile_read()
+    p.profile(False)
+    log(f"[bench] fp64 {args.fp64_steps} steps {dt64 * 1e3 / args.fp64_steps:.3f} ms/step")
+    rel = (torch.linalg.vector_norm((y32.to(torch.complex128) - y64).flatten())
+           / torch.linalg.vector_norm(y64.flatten())).item()
+
+    mv32 = nrhs * args.steps / dt32
+    mv64 = nrhs * args.fp64_steps / dt64
+    nvec = 3 * nrhs
+    by32 = pass_bytes(p, nvec, 8, 4, K, nzp)
+    per_call = {k: v / max(ncall, 1) for k, v in prof32.items()}
+    dom = max(by32, key=lambda k: per_call[k])
+    ach = by32[dom] / (per_call[dom] * 1e-3) / 1e9
+    total_bytes = sum(by32.values())
+    kern_ms = sum(per_call[k] for k in by32)
+    # Tucker restoration: FLOPs of the three mode products
+    d1, d2, d3 = ranks
+    Lx, Ly, Lz = p.L
+    tflops = 2.0 * (Lx * d1 * d2 * d3 + Lx * Ly * d2 * d3 + Lx * Ly * Lz * d3)
+    tk_ms = per_call["tucker_restore"]
+    out = {
+        "metric": "FFT-VIE matvecs/s (FP32 operator inside FP64 refinement; FP64 beside it)",
+        "value": mv32,
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt32 * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 (FFT, product); f64 Tucker restoration",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {mask.shape[2]}x{mask.shape[1]}x{mask.shape[0]} grid, "
+                               f"K={K} voxels, 3 components, {nrhs} RHS (8 ports x {nf} frequencies), "
+                               f"Tucker tol {args.tol:g}",
+                   "fft_grid": list(p.L), "tucker_ranks": list(ranks), "occupied_z_planes": nzp},
+        "fp64": {"value": mv64, "unit": "matvecs/s", "ms_per_step": dt64 * 1e3 / args.fp64_steps},
+        "rel_err_fp32_vs_fp64": rel,
+        "voxel_matvecs_per_s": {"fp32_Kt": mv32 * mask.size, "fp32_K": mv32 * K,
+                                "fp64_Kt": mv64 * mask.size},
+        "kernels_ms_per_step": per_call,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "all_passes_frac": total_bytes / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "tucker_restore": {"ms": tk_ms, "tflops": tflops / (tk_ms * 1e-3) / 1e12 if tk_ms > 0 else None,
+                           "mfma_frac": (tflops / (tk_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS) if tk_ms > 0 else None},
+    }
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(mask, dx, x64_h, fidx, freqs, sigma0, lam)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

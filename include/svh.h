@@ -1,0 +1,148 @@
+/*
+ * svh.h -- C ABI of the MI355X FFT-accelerated voxel VIE operator library.
+ *
+ * The library applies the Galerkin operator of the voxel volume integral
+ * equation for superconducting structures (SuperVoxHenry, arXiv 2105.08627):
+ * eq. 1 (VIE with the two-fluid conductivity of eq. 3), discretised with the
+ * piecewise-constant basis of eq. 4 (three current components per voxel),
+ * whose block matrix (eq. 8) is applied through the FFT product of eq. 9 with
+ * the circulant tensors rebuilt from their Tucker factors (eqs. 10-11,
+ * Algorithm 1, Sec. II.B.2).
+ *
+ * Conventions used by every entry point
+ *  - Voxels of the Kx x Ky x Kz grid are indexed x fastest, then y, then z.
+ *    The K non-empty voxels (mask != 0) are numbered in that order.
+ *  - Complex numbers are interleaved (re, im); FP64 entry points take
+ *    double pairs, FP32 entry points float pairs.
+ *  - A current vector holds C = 3 components, component-major:
+ *    [I^x (K values); I^y (K); I^z (K)] (eq. 7).  A batch of nrhs vectors is
+ *    stored back to back: element (rhs, comp, k) at (rhs*C + comp)*K + k.
+ *  - Basis functions carry total current (f^x = x_hat / dx^2), so that the
+ *    voxel self term is c/dx with c = 1/sigma (text under eq. 9, eqs. 16, 22-23)
+ *    and the coupling is j*w*mu0*dx times the unit-voxel Green integral
+ *    (App. B scaling with the basis normalisation); mu0 = 4*pi*1e-7 H/m.
+ *  - Pointers named *_dev are device pointers (hipMalloc or torch CUDA
+ *    tensors); *_host are host pointers read during the call only.  The
+ *    library owns the problem object and its tensors; the caller owns every
+ *    buffer it passes and must keep device buffers alive until the stream has
+ *    passed the work enqueued on them.
+ *  - Errors: every call returns an svh_status; on failure the problem's
+ *    svh_last_error() text says why.  No call aborts the process.
+ */
+#ifndef SVH_H
+#define SVH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SVH_OK = 0,
+  SVH_EINVAL = -1,   /* bad argument (sizes, null pointers, ranges)            */
+  SVH_ENOMEM = -2,   /* device or host allocation failed                       */
+  SVH_EHIP = -3,     /* a HIP runtime call failed                               */
+  SVH_ENOTCONV = -4, /* iterative method stopped before its tolerance           */
+  SVH_ESTATE = -5    /* call made in the wrong order (e.g. matvec before setup) */
+} svh_status;
+
+typedef enum { SVH_FP64 = 0, SVH_FP32 = 1 } svh_prec;
+
+typedef struct svh_problem svh_problem;
+
+/* Create a problem on the current HIP device.
+ * Kx, Ky, Kz >= 1: voxel counts per axis (Sec. II.A: Kt = Kx*Ky*Kz).
+ * dx_m > 0: voxel edge length in metres.
+ * basis: 3 (piecewise-constant basis f^x, f^y, f^z of eq. 4).
+ * mask_host: Kt bytes, x fastest; non-zero marks a non-empty voxel.  At least
+ *   one voxel must be non-empty.
+ * The FFT grid is L_i = 2 K_i when 2 K_i factors into 2s and 3s, else the
+ * smallest such length >= 2 K_i - 1 (the circulant embedding of Sec. II.A
+ * needs L_i >= 2 K_i - 1).  On success *out receives the new problem. */
+svh_status svh_create(svh_problem** out, int Kx, int Ky, int Kz, double dx_m,
+                      int basis, const uint8_t* mask_host);
+
+/* Number of non-empty voxels K, and the FFT grid L (any pointer may be NULL). */
+svh_status svh_get_sizes(const svh_problem* p, int* K, int* Lx, int* Ly, int* Lz);
+
+/* Two-fluid material for nfreq frequencies (eq. 3; a, b of eqs. 22-23).
+ * f_hz_host[nfreq] > 0; sigma0_host (S/m, >= 0) and lambda_host (London depth
+ * in m, > 0) hold either one value each (per_voxel = 0) or K values each
+ * (per_voxel = 1, compact voxel order).  Stores c = 1/sigma per frequency and
+ * voxel on the device and the coupling scalar j*w*mu0*dx per frequency.
+ * May be called again to replace the material. */
+svh_status svh_set_material(svh_problem* p, int nfreq, const double* f_hz_host,
+                            const double* sigma0_host, const double* lambda_host,
+                            int per_voxel);
+
+/* Toeplitz tensor of the unit-voxel Green integral (eq. 19 with the App. B
+ * scaling, positive sign) for offsets [0,Kx) x [0,Ky) x [0,Kz), its circulant
+ * embedding (Sec. II.A) and the real spectrum of that circulant (the tensor
+ * Z of eq. 9 divided by j*w*mu0*dx), kept on the device in FP64.
+ * stream: a hipStream_t (NULL = default stream); the call returns after the
+ * spectrum is complete. */
+svh_status svh_setup_tensors(svh_problem* p, void* stream);
+
+/* Host-only: the unit-voxel Green integral of eq. 19 (positive sign, App. B
+ * with dx = 1) for offsets [0,Kx) x [0,Ky) x [0,Kz), written to T_host
+ * (Kt doubles, offsets x fastest).  Evaluated from the closed-form Coulomb
+ * box-box potential in binary128 arithmetic.  Touches no GPU. */
+svh_status svh_green_toeplitz(int Kx, int Ky, int Kz, double* T_host);
+
+/* Copy the Toeplitz tensor computed by svh_setup_tensors to the host
+ * (Kt doubles, offsets x fastest). */
+svh_status svh_get_toeplitz(const svh_problem* p, double* T_host);
+
+/* Tucker-compress the circulant spectrum (Algorithm 1, Sec. II.B.2) with
+ * relative Frobenius tolerance tol >= 0 (tol/sqrt(3) per mode).  After this
+ * call every matvec restores the spectrum from the Tucker factors (eq. 10)
+ * instead of keeping it resident, and the dense spectrum is freed.
+ * ranks_out (3 ints, may be NULL): multilinear ranks d1, d2, d3.
+ * relerr_out (may be NULL): bound-level estimate sqrt(sum of discarded
+ * squared singular values) / ||Z||_F summed over the three modes. */
+svh_status svh_tucker_compress(svh_problem* p, double tol, int32_t* ranks_out,
+                               double* relerr_out);
+
+/* Bytes of device workspace svh_matvec needs for nrhs right-hand sides. */
+size_t svh_workspace_bytes(const svh_problem* p, svh_prec prec, int nrhs);
+
+/* y = Z x for nrhs right-hand sides (eq. 9 plus the diagonal z^beta I^beta).
+ * prec: SVH_FP64 (x, y complex double) or SVH_FP32 (complex float; the
+ *   Tucker restoration still accumulates in FP64 and is rounded once).
+ * freq_idx_host[nrhs]: frequency slot (from svh_set_material) per RHS, or -1
+ *   for the bare unit-voxel convolution y = T * x (no j*w*mu0*dx factor and
+ *   no diagonal term).
+ * x_dev, y_dev: nrhs*3*K complex values each (layout above); must not
+ *   overlap.  ws_dev: at least svh_workspace_bytes(p, prec, nrhs) bytes.
+ * stream: hipStream_t on which all work is enqueued; the call does not
+ *   synchronise. */
+svh_status svh_matvec(svh_problem* p, svh_prec prec, int nrhs,
+                      const int32_t* freq_idx_host, const void* x_dev, void* y_dev,
+                      void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Per-kernel timing of svh_matvec with HIP events recorded on the call's
+ * stream (for measurement; off by default).  While enabled every matvec
+ * records events around each kernel. */
+#define SVH_NPROF 6
+svh_status svh_profile_enable(svh_problem* p, int enable);
+
+/* Sum, over the matvec calls since the last read, of the kernel durations in
+ * milliseconds: ms_out[SVH_NPROF] = {Tucker restoration, X pass, Y pass,
+ * Z pass (forward z FFT, spectrum product, inverse z FFT), inverse Y pass,
+ * inverse X pass with the diagonal term}.  ncalls_out (may be NULL) receives
+ * the number of kernel sequences summed.  Waits for the recorded events. */
+svh_status svh_profile_read(svh_problem* p, double* ms_out, int* ncalls_out);
+
+/* Text of the last error on this problem (never NULL). */
+const char* svh_last_error(const svh_problem* p);
+
+/* Release the problem and all library-owned device memory. */
+void svh_destroy(svh_problem* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SVH_H */

@@ -1,0 +1,189 @@
+"""Python binding of libsvh (the MI355X FFT-accelerated voxel VIE operator).
+
+Argument marshalling only: every step of the operator runs in the HIP
+library.  PyTorch supplies device memory and the current stream.  The
+binding fails loudly when the library has not been built; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsvh.so")
+
+SVH_FP64, SVH_FP32 = 0, 1
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "ESTATE"}
+
+EXPORTED = [
+    "svh_create", "svh_get_sizes", "svh_set_material", "svh_setup_tensors", "svh_green_toeplitz",
+    "svh_get_toeplitz", "svh_tucker_compress", "svh_workspace_bytes", "svh_matvec",
+    "svh_profile_enable", "svh_profile_read", "svh_last_error", "svh_destroy",
+]
+PROF_NAMES = ["tucker_restore", "pass_x", "pass_y", "pass_z_mul", "pass_yi", "pass_xi"]
+
+_lib = None
+
+
+class SvhError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libsvh.so (built in-tree by ``paper_2105_08627_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise SvhError(f"{LIB_PATH} is missing: build it with `python -m paper_2105_08627_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    L.svh_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, dbl, i32, vp]
+    L.svh_get_sizes.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                ctypes.POINTER(i32)]
+    L.svh_set_material.argtypes = [vp, i32, vp, vp, vp, i32]
+    L.svh_setup_tensors.argtypes = [vp, vp]
+    L.svh_green_toeplitz.argtypes = [i32, i32, i32, vp]
+    L.svh_get_toeplitz.argtypes = [vp, vp]
+    L.svh_tucker_compress.argtypes = [vp, dbl, vp, vp]
+    L.svh_workspace_bytes.argtypes = [vp, i32, i32]
+    L.svh_workspace_bytes.restype = sz
+    L.svh_matvec.argtypes = [vp, i32, i32, vp, vp, vp, vp, sz, vp]
+    L.svh_profile_enable.argtypes = [vp, i32]
+    L.svh_profile_read.argtypes = [vp, vp, vp]
+    L.svh_last_error.argtypes = [vp]
+    L.svh_last_error.restype = ctypes.c_char_p
+    L.svh_destroy.argtypes = [vp]
+    L.svh_destroy.restype = None
+    for name in EXPORTED:
+        if name not in ("svh_workspace_bytes", "svh_last_error", "svh_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def green_toeplitz(Kx, Ky, Kz):
+    """Host-only closed-form unit-voxel Green integral, array [Kz, Ky, Kx]."""
+    T = np.zeros((Kz, Ky, Kx))
+    st = lib().svh_green_toeplitz(Kx, Ky, Kz, _ptr(T))
+    if st != 0:
+        raise SvhError(f"svh_green_toeplitz: {_STATUS.get(st, st)}")
+    return T
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Problem:
+    """One voxel grid with its material and circulant tensors (svh_problem)."""
+
+    def __init__(self, mask, dx, basis=3):
+        mask = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        if mask.ndim != 3:
+            raise ValueError("mask must be [Kz, Ky, Kx]")
+        self.Kz, self.Ky, self.Kx = mask.shape
+        self.C = basis
+        self._h = ctypes.c_void_p()
+        st = lib().svh_create(ctypes.byref(self._h), self.Kx, self.Ky, self.Kz, float(dx), basis, _ptr(mask))
+        if st != 0:
+            raise SvhError(f"svh_create: {_STATUS.get(st, st)}")
+        K, Lx, Ly, Lz = (ctypes.c_int() for _ in range(4))
+        lib().svh_get_sizes(self._h, ctypes.byref(K), ctypes.byref(Lx), ctypes.byref(Ly), ctypes.byref(Lz))
+        self.K = K.value
+        self.L = (Lx.value, Ly.value, Lz.value)
+        self._ws = {}
+
+    def _check(self, st, what):
+        if st != 0:
+            msg = lib().svh_last_error(self._h).decode()
+            raise SvhError(f"{what}: {_STATUS.get(st, st)}: {msg}")
+
+    def set_material(self, freqs, sigma0, lam, per_voxel=False):
+        f = np.ascontiguousarray(np.atleast_1d(np.asarray(freqs, dtype=np.float64)))
+        s0 = np.ascontiguousarray(np.atleast_1d(np.asarray(sigma0, dtype=np.float64)))
+        la = np.ascontiguousarray(np.atleast_1d(np.asarray(lam, dtype=np.float64)))
+        self._check(lib().svh_set_material(self._h, f.size, _ptr(f), _ptr(s0), _ptr(la), int(per_voxel)),
+                    "svh_set_material")
+
+    def setup_tensors(self, stream=None):
+        self._check(lib().svh_setup_tensors(self._h, _stream_handle(stream)), "svh_setup_tensors")
+
+    def toeplitz(self):
+        T = np.zeros((self.Kz, self.Ky, self.Kx))
+        self._check(lib().svh_get_toeplitz(self._h, _ptr(T)), "svh_get_toeplitz")
+        return T
+
+    def tucker_compress(self, tol):
+        ranks = np.zeros(3, dtype=np.int32)
+        err = np.zeros(1)
+        self._check(lib().svh_tucker_compress(self._h, float(tol), _ptr(ranks), _ptr(err)), "svh_tucker_compress")
+        self._ws.clear()
+        return tuple(int(r) for r in ranks), float(err[0])
+
+    def workspace_bytes(self, prec, nrhs):
+        return int(lib().svh_workspace_bytes(self._h, prec, nrhs))
+
+    def workspace(self, prec, nrhs, device):
+        import torch
+        key = (prec, nrhs)
+        need = self.workspace_bytes(prec, nrhs)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(need, dtype=torch.uint8, device=device)
+            self._ws[key] = ws
+        return ws
+
+    def matvec(self, x, freq_idx, out=None, stream=None):
+        """y = Z x for x of shape (nrhs, C, K), complex128 (FP64) or complex64
+        (FP32), on a CUDA device.  freq_idx: one slot per RHS (-1: bare)."""
+        import torch
+        if not x.is_cuda:
+            raise ValueError("x must be a device tensor")
+        if x.dtype == torch.complex128:
+            prec = SVH_FP64
+        elif x.dtype == torch.complex64:
+            prec = SVH_FP32
+        else:
+            raise TypeError("x must be complex128 or complex64")
+        if x.dim() != 3 or x.shape[1] != self.C or x.shape[2] != self.K or not x.is_contiguous():
+            raise ValueError(f"x must be contiguous (nrhs, {self.C}, {self.K})")
+        nrhs = x.shape[0]
+        fi = np.ascontiguousarray(np.broadcast_to(np.asarray(freq_idx, dtype=np.int32), (nrhs,)))
+        y = out if out is not None else torch.empty_like(x)
+        ws = self.workspace(prec, nrhs, x.device)
+        st = lib().svh_matvec(self._h, prec, nrhs, _ptr(fi), ctypes.c_void_p(x.data_ptr()),
+                              ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                              _stream_handle(stream))
+        self._check(st, "svh_matvec")
+        return y
+
+    def profile(self, enable=True):
+        self._check(lib().svh_profile_enable(self._h, int(enable)), "svh_profile_enable")
+
+    def profile_read(self):
+        """Per-kernel summed milliseconds since the last read, and call count."""
+        ms = np.zeros(len(PROF_NAMES))
+        n = np.zeros(1, dtype=np.int32)
+        self._check(lib().svh_profile_read(self._h, _ptr(ms), _ptr(n)), "svh_profile_read")
+        return dict(zip(PROF_NAMES, ms.tolist())), int(n[0])
+
+    def close(self):
+        if self._h:
+            lib().svh_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,431 @@
+// C ABI entry points (include/svh.h).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "host_math.h"
+#include "svh_internal.h"
+
+namespace svh {
+bool make_plan(int L, FftPlan& p) {
+  p = FftPlan();
+  p.L = L;
+  int n = L;
+  const int rad[4] = {8, 4, 2, 3};
+  for (int q = 0; q < 4; ++q) {
+    const int r = rad[q];
+    while (n % r == 0) {
+      if (r == 2 && n % 4 == 0) break;
+      if (p.ns >= kMaxStages) return false;
+      p.r[p.ns++] = r;
+      n /= r;
+    }
+  }
+  if (n != 1 || p.ns == 0) return false;
+  p.tp = L;
+  for (int s = 0; s < p.ns; ++s) p.tp = std::min(p.tp, L / p.r[s]);
+  return true;
+}
+
+FftPlan reversed(const FftPlan& p) {
+  FftPlan q = p;
+  for (int s = 0; s < p.ns; ++s) q.r[s] = p.r[p.ns - 1 - s];
+  return q;
+}
+
+bool supported_length(int L) {
+  if (L < 2 || L > 1024) return false;
+  int n = L;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+}  // namespace svh
+
+using namespace svh;
+
+namespace {
+
+svh_status fail(svh_problem* p, svh_status st, const std::string& msg) {
+  if (p) p->err = msg;
+  return st;
+}
+
+#define HIPCHK(call)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(p, e_ == hipErrorOutOfMemory ? SVH_ENOMEM : SVH_EHIP,                    \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                      \
+  } while (0)
+
+template <typename T>
+hipError_t upload(T** dst, const T* src, size_t n) {
+  if (*dst) {
+    hipFree(*dst);
+    *dst = nullptr;
+  }
+  if (n == 0) return hipSuccess;
+  hipError_t e = hipMalloc(dst, n * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+}
+
+template <typename T>
+void dfree(T*& ptr) {
+  if (ptr) hipFree(ptr);
+  ptr = nullptr;
+}
+
+int choose_length(int K) {
+  if (supported_length(2 * K)) return 2 * K;
+  for (int L = std::max(2, 2 * K - 1);; ++L)
+    if (supported_length(L)) return L;
+}
+
+void free_tucker(svh_problem* p) {
+  dfree(p->tk.core);
+  for (int a = 0; a < 3; ++a) dfree(p->tk.F[a]);
+  p->tk = DevTucker();
+  p->tucker = false;
+}
+
+size_t vec_bytes_AB(const svh_problem* p, size_t csize) {
+  const size_t nzp = p->zlist.size();
+  return nzp * ((size_t)p->K[1] + p->L[1]) * p->L[0] * csize;
+}
+
+int chunk_rhs(const svh_problem* p, int nrhs) {
+  const int maxr = kMaxVecsPerChunk / p->C;
+  return std::max(1, std::min(nrhs, maxr));
+}
+
+}  // namespace
+
+extern "C" {
+
+svh_status svh_create(svh_problem** out, int Kx, int Ky, int Kz, double dx_m, int basis,
+                      const uint8_t* mask_host) {
+  if (!out) return SVH_EINVAL;
+  *out = nullptr;
+  if (Kx < 1 || Ky < 1 || Kz < 1 || !(dx_m > 0) || !mask_host) return SVH_EINVAL;
+  if (basis != 3) return SVH_EINVAL;
+  if (Kx > 512 || Ky > 512 || Kz > 512) return SVH_EINVAL;
+  std::unique_ptr<svh_problem> up(new svh_problem());
+  svh_problem* p = up.get();
+  p->K[0] = Kx;
+  p->K[1] = Ky;
+  p->K[2] = Kz;
+  p->dx = dx_m;
+  p->basis = basis;
+  p->C = 3;
+  HIPCHK(hipGetDevice(&p->device));
+  const size_t Kt = (size_t)Kx * Ky * Kz;
+  p->vidx.assign(Kt, -1);
+  int n = 0;
+  std::vector<char> zocc(Kz, 0);
+  for (int z = 0; z < Kz; ++z)
+    for (int y = 0; y < Ky; ++y)
+      for (int x = 0; x < Kx; ++x) {
+        const size_t i = ((size_t)z * Ky + y) * Kx + x;
+        if (mask_host[i]) {
+          p->vidx[i] = n++;
+          zocc[z] = 1;
+        }
+      }
+  if (n == 0) return SVH_EINVAL;
+  p->nvox = n;
+  for (int a = 0; a < 3; ++a) {
+    p->L[a] = choose_length(p->K[a]);
+    if (!make_plan(p->L[a], p->plan[a])) return SVH_EINVAL;
+  }
+  for (int z = 0; z < Kz; ++z)
+    if (zocc[z]) p->zlist.push_back(z);
+  p->zslot.assign(p->L[2], -1);
+  for (size_t s = 0; s < p->zlist.size(); ++s) p->zslot[p->zlist[s]] = (int32_t)s;
+  HIPCHK(upload(&p->d_vidx, p->vidx.data(), Kt));
+  HIPCHK(upload(&p->d_zlist, p->zlist.data(), p->zlist.size()));
+  HIPCHK(upload(&p->d_zslot, p->zslot.data(), p->zslot.size()));
+  for (int a = 0; a < 3; ++a) {
+    const int L = p->L[a];
+    std::vector<double2> t64(L);
+    std::vector<float2> t32(L);
+    for (int m = 0; m < L; ++m) {
+      const long double ang = 2.0L * 3.141592653589793238462643383279502884L * m / L;
+      t64[m] = make_double2((double)cosl(ang), (double)-sinl(ang));
+      t32[m] = make_float2((float)cosl(ang), (float)-sinl(ang));
+    }
+    HIPCHK(upload(&p->d_tw64[a], t64.data(), L));
+    HIPCHK(upload(&p->d_tw32[a], t32.data(), L));
+  }
+  *out = up.release();
+  return SVH_OK;
+}
+
+svh_status svh_get_sizes(const svh_problem* p, int* K, int* Lx, int* Ly, int* Lz) {
+  if (!p) return SVH_EINVAL;
+  if (K) *K = p->nvox;
+  if (Lx) *Lx = p->L[0];
+  if (Ly) *Ly = p->L[1];
+  if (Lz) *Lz = p->L[2];
+  return SVH_OK;
+}
+
+svh_status svh_set_material(svh_problem* p, int nfreq, const double* f_hz, const double* sigma0,
+                            const double* lambda, int per_voxel) {
+  if (!p) return SVH_EINVAL;
+  if (nfreq < 1 || !f_hz || !sigma0 || !lambda) return fail(p, SVH_EINVAL, "set_material: bad arguments");
+  const int K = p->nvox;
+  std::vector<double2> cd64((size_t)nfreq * K);
+  std::vector<float2> cd32((size_t)nfreq * K);
+  std::vector<double2> s64(nfreq);
+  std::vector<float2> s32(nfreq);
+  p->sconv.assign(nfreq, 0);
+  for (int f = 0; f < nfreq; ++f) {
+    if (!(f_hz[f] > 0)) return fail(p, SVH_EINVAL, "set_material: frequency must be > 0");
+    const double w = 2 * M_PI * f_hz[f];
+    const std::complex<double> s(0.0, w * kMu0 * p->dx);
+    p->sconv[f] = s;
+    s64[f] = make_double2(s.real(), s.imag());
+    s32[f] = make_float2((float)s.real(), (float)s.imag());
+    for (int k = 0; k < K; ++k) {
+      const double s0 = sigma0[per_voxel ? k : 0];
+      const double lam = lambda[per_voxel ? k : 0];
+      if (!(s0 >= 0) || !(lam > 0)) return fail(p, SVH_EINVAL, "set_material: need sigma0 >= 0, lambda > 0");
+      // eq. 3: sigma = sigma0 - j / (w mu lam^2); c = 1 / sigma
+      const std::complex<double> sigma(s0, -1.0 / (w * kMu0 * lam * lam));
+      const std::complex<double> c = 1.0 / sigma / p->dx;
+      cd64[(size_t)f * K + k] = make_double2(c.real(), c.imag());
+      cd32[(size_t)f * K + k] = make_float2((float)c.real(), (float)c.imag());
+    }
+  }
+  HIPCHK(upload(&p->d_cdiag64, cd64.data(), cd64.size()));
+  HIPCHK(upload(&p->d_cdiag32, cd32.data(), cd32.size()));
+  HIPCHK(upload(&p->d_sconv64, s64.data(), s64.size()));
+  HIPCHK(upload(&p->d_sconv32, s32.data(), s32.size()));
+  p->nfreq = nfreq;
+  return SVH_OK;
+}
+
+svh_status svh_setup_tensors(svh_problem* p, void* stream) {
+  if (!p) return SVH_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t Kt = (size_t)p->K[0] * p->K[1] * p->K[2];
+  p->T.assign(Kt, 0.0);
+  green_toeplitz_m0(p->K[0], p->K[1], p->K[2], p->T.data());
+  free_tucker(p);
+  dfree(p->d_zhat64);
+  dfree(p->d_zhat32);
+  const size_t Lt = (size_t)p->L[0] * p->L[1] * p->L[2];
+  double *dT = nullptr, *t1 = nullptr, *t2 = nullptr;
+  HIPCHK(hipMalloc(&p->d_zhat64, Lt * sizeof(double)));
+  HIPCHK(hipMalloc(&p->d_zhat32, Lt * sizeof(float)));
+  HIPCHK(hipMalloc(&dT, Kt * sizeof(double)));
+  const size_t n1 = (size_t)p->K[2] * p->K[1] * p->L[0];
+  const size_t n2 = (size_t)p->K[2] * p->L[1] * p->L[0];
+  hipError_t e = hipMalloc(&t1, n1 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&t2, n2 * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpyAsync(dT, p->T.data(), Kt * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_even_spectrum(p, dT, p->d_zhat64, t1, t2, s);
+  if (e == hipSuccess) e = launch_to_f32(p->d_zhat64, p->d_zhat32, Lt, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(dT);
+  if (t1) hipFree(t1);
+  if (t2) hipFree(t2);
+  HIPCHK(e);
+  return SVH_OK;
+}
+
+svh_status svh_green_toeplitz(int Kx, int Ky, int Kz, double* T_host) {
+  if (Kx < 1 || Ky < 1 || Kz < 1 || Kx > 4096 || Ky > 4096 || Kz > 4096 || !T_host) return SVH_EINVAL;
+  green_toeplitz_m0(Kx, Ky, Kz, T_host);
+  return SVH_OK;
+}
+
+svh_status svh_get_toeplitz(const svh_problem* p, double* T_host) {
+  if (!p || !T_host) return SVH_EINVAL;
+  if (p->T.empty()) return SVH_ESTATE;
+  std::memcpy(T_host, p->T.data(), p->T.size() * sizeof(double));
+  return SVH_OK;
+}
+
+svh_status svh_tucker_compress(svh_problem* p, double tol, int32_t* ranks_out, double* relerr_out) {
+  if (!p) return SVH_EINVAL;
+  if (!(tol >= 0)) return fail(p, SVH_EINVAL, "tucker_compress: tol must be >= 0");
+  if (p->T.empty()) return fail(p, SVH_ESTATE, "tucker_compress: call svh_setup_tensors first");
+  TuckerFactors tf;
+  if (tucker_even_circulant(p->K, p->L, p->T.data(), tol, tf) != 0)
+    return fail(p, SVH_EINVAL, "tucker_compress: zero tensor");
+  free_tucker(p);
+  p->tk.d[0] = tf.d[0];
+  p->tk.d[1] = tf.d[1];
+  p->tk.d[2] = tf.d[2];
+  HIPCHK(upload(&p->tk.core, tf.core.data(), tf.core.size()));
+  for (int a = 0; a < 3; ++a) HIPCHK(upload(&p->tk.F[a], tf.F[a].data(), tf.F[a].size()));
+  p->tucker = true;
+  dfree(p->d_zhat64);
+  dfree(p->d_zhat32);
+  if (ranks_out)
+    for (int a = 0; a < 3; ++a) ranks_out[a] = tf.d[a];
+  if (relerr_out) *relerr_out = tf.relerr;
+  return SVH_OK;
+}
+
+size_t svh_workspace_bytes(const svh_problem* p, svh_prec prec, int nrhs) {
+  if (!p || nrhs < 1) return 0;
+  const size_t cs = prec == SVH_FP64 ? sizeof(double2) : sizeof(float2);
+  const int cr = chunk_rhs(p, nrhs);
+  size_t b = (size_t)cr * p->C * vec_bytes_AB(p, cs);
+  if (p->tucker) {
+    const size_t Lt = (size_t)p->L[0] * p->L[1] * p->L[2];
+    b += Lt * (prec == SVH_FP64 ? sizeof(double) : sizeof(float));
+    b += tucker_scratch_doubles(p) * sizeof(double);
+  }
+  return b + 1024;
+}
+
+svh_status svh_matvec(svh_problem* p, svh_prec prec, int nrhs, const int32_t* freq_idx, const void* x,
+                      void* y, void* ws, size_t ws_bytes, void* stream) {
+  if (!p) return SVH_EINVAL;
+  if (nrhs < 1 || !freq_idx || !x || !y || !ws) return fail(p, SVH_EINVAL, "matvec: bad arguments");
+  if (prec != SVH_FP64 && prec != SVH_FP32) return fail(p, SVH_EINVAL, "matvec: bad precision");
+  if (!p->tucker && !p->d_zhat64) return fail(p, SVH_ESTATE, "matvec: call svh_setup_tensors first");
+  for (int r = 0; r < nrhs; ++r) {
+    if (freq_idx[r] < -1 || freq_idx[r] >= p->nfreq)
+      return fail(p, SVH_EINVAL, "matvec: frequency index out of range (set the material first)");
+  }
+  const size_t need = svh_workspace_bytes(p, prec, nrhs);
+  if (ws_bytes < need) return fail(p, SVH_EINVAL, "matvec: workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool dbl = prec == SVH_FP64;
+  const size_t cs = dbl ? sizeof(double2) : sizeof(float2);
+  const size_t vecb = (size_t)p->nvox * cs;
+  // overlap check of x and y
+  const size_t tot = (size_t)nrhs * p->C * vecb;
+  const char* xb = static_cast<const char*>(x);
+  const char* yb = static_cast<const char*>(y);
+  if (xb < yb + tot && yb < xb + tot) return fail(p, SVH_EINVAL, "matvec: x and y overlap");
+  char* w = static_cast<char*>(ws);
+  auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const int cr = chunk_rhs(p, nrhs);
+  const size_t nzp = p->zlist.size();
+  const size_t Abytes = align((size_t)cr * p->C * nzp * p->K[1] * p->L[0] * cs);
+  const size_t Bbytes = (size_t)cr * p->C * nzp * p->L[1] * p->L[0] * cs;
+  char* A = w;
+  char* B = w + Abytes;
+  const void* zhat = dbl ? (const void*)p->d_zhat64 : (const void*)p->d_zhat32;
+  std::vector<hipEvent_t> evs;
+  if (p->prof) {
+    const int nchunk = (nrhs + cr - 1) / cr;
+    for (int i = 0; i < 8 * nchunk; ++i) {
+      hipEvent_t e;
+      if (!p->prof_pool.empty()) {
+        e = p->prof_pool.back();
+        p->prof_pool.pop_back();
+      } else {
+        HIPCHK(hipEventCreate(&e));
+      }
+      evs.push_back(e);
+    }
+    HIPCHK(hipEventRecord(evs[0], s));
+  }
+  if (p->tucker) {
+    char* zb = B + align(Bbytes);
+    const size_t Lt = (size_t)p->L[0] * p->L[1] * p->L[2];
+    double* V = reinterpret_cast<double*>(zb + align(Lt * (dbl ? 8 : 4)));
+    double* Wt = V + (size_t)p->L[0] * p->tk.d[1] * p->tk.d[2];
+    if (reinterpret_cast<char*>(Wt + (size_t)p->L[0] * p->L[1] * p->tk.d[2]) > w + ws_bytes)
+      return fail(p, SVH_EINVAL, "matvec: workspace too small");
+    HIPCHK(launch_tucker_rebuild(p, !dbl, zb, V, Wt, s));
+    zhat = zb;
+  } else if (!dbl && !p->d_zhat32) {
+    return fail(p, SVH_ESTATE, "matvec: no FP32 spectrum");
+  }
+  if (p->prof) HIPCHK(hipEventRecord(evs[1], s));
+  for (int r0 = 0; r0 < nrhs; r0 += cr) {
+    const int nr = std::min(cr, nrhs - r0);
+    hipEvent_t* ev = nullptr;
+    if (p->prof) {
+      ev = &evs[8 * (r0 / cr) + 2];
+      if (r0 > 0) {
+        HIPCHK(hipEventRecord(evs[8 * (r0 / cr)], s));
+        HIPCHK(hipEventRecord(evs[8 * (r0 / cr) + 1], s));
+      }
+    }
+    EpiParams ep;
+    ep.C = p->C;
+    ep.K = p->nvox;
+    ep.vec0 = 0;
+    for (int i = 0; i < kMaxVecsPerChunk; ++i) ep.fidx[i] = -1;
+    for (int i = 0; i < nr; ++i) ep.fidx[i] = freq_idx[r0 + i];
+    const char* xc = xb + (size_t)r0 * p->C * vecb;
+    char* yc = static_cast<char*>(y) + (size_t)r0 * p->C * vecb;
+    hipError_t e = dbl ? launch_matvec_chunk<double>(p, nr * p->C, ep, xc, yc, A, B, zhat, s, ev)
+                       : launch_matvec_chunk<float>(p, nr * p->C, ep, xc, yc, A, B, zhat, s, ev);
+    HIPCHK(e);
+  }
+  for (size_t i = 0; i < evs.size(); i += 8)
+    p->prof_events.push_back(std::vector<hipEvent_t>(evs.begin() + i, evs.begin() + i + 8));
+  return SVH_OK;
+}
+
+svh_status svh_profile_enable(svh_problem* p, int enable) {
+  if (!p) return SVH_EINVAL;
+  p->prof = enable != 0;
+  return SVH_OK;
+}
+
+svh_status svh_profile_read(svh_problem* p, double* ms_out, int* ncalls_out) {
+  if (!p || !ms_out) return SVH_EINVAL;
+  for (int i = 0; i < SVH_NPROF; ++i) ms_out[i] = 0;
+  int n = 0;
+  for (auto& set : p->prof_events) {
+    HIPCHK(hipEventSynchronize(set[7]));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, set[0], set[1]));
+    ms_out[0] += ms;
+    for (int k = 0; k < 5; ++k) {
+      HIPCHK(hipEventElapsedTime(&ms, set[2 + k], set[3 + k]));
+      ms_out[1 + k] += ms;
+    }
+    for (hipEvent_t e : set) p->prof_pool.push_back(e);
+    ++n;
+  }
+  p->prof_events.clear();
+  if (ncalls_out) *ncalls_out = n;
+  return SVH_OK;
+}
+
+const char* svh_last_error(const svh_problem* p) {
+  if (!p) return "null problem";
+  return p->err.c_str();
+}
+
+void svh_destroy(svh_problem* p) {
+  if (!p) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(p->device);
+  dfree(p->d_vidx);
+  dfree(p->d_zlist);
+  dfree(p->d_zslot);
+  for (int a = 0; a < 3; ++a) {
+    dfree(p->d_tw64[a]);
+    dfree(p->d_tw32[a]);
+  }
+  dfree(p->d_sconv64);
+  dfree(p->d_sconv32);
+  dfree(p->d_cdiag64);
+  dfree(p->d_cdiag32);
+  dfree(p->d_zhat64);
+  dfree(p->d_zhat32);
+  free_tucker(p);
+  for (auto& set : p->prof_events)
+    for (hipEvent_t e : set) (void)hipEventDestroy(e);
+  for (hipEvent_t e : p->prof_pool) (void)hipEventDestroy(e);
+  (void)hipSetDevice(cur);
+  delete p;
+}
+
+}  // extern "C"

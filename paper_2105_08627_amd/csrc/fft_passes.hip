@@ -1,0 +1,558 @@
+// FFT convolution passes of the VIE matrix-vector product (eq. 9), gfx950.
+//
+// y = s * IFFT3( Zhat .* FFT3( pad(x) ) )[crop] / (Lx Ly Lz) + (c/dx) x
+//
+// The 3D transforms run as five HBM passes over pencils, each a batched 1D
+// mixed-radix Stockham FFT staged through LDS:
+//   X  : gather compact x into zero-padded x-pencils, forward FFT along x
+//   Y  : forward FFT along y (input half is zero: only y < Ky is read)
+//   Z  : forward FFT along z, multiply by the real spectrum, inverse FFT
+//        along z, all in one kernel (the last forward and the first inverse
+//        butterfly stage share registers)
+//   Yi : inverse FFT along y, keep y < Ky
+//   Xi : inverse FFT along x, keep x < Kx, scale, add the diagonal term and
+//        scatter to the compact output
+// Only z planes that hold at least one non-empty voxel are stored between
+// passes (the others are zero on input and not needed on output).
+//
+// Stockham stage with radix R after Ns previous points (natural order out):
+//   in  v_r = src[j + r L/R],  twiddle  v_r *= w_L^(r (j mod Ns) L/(Ns R))
+//   R-point DFT, out dst[(j / Ns) Ns R + (j mod Ns) + r Ns].
+#include "svh_internal.h"
+
+namespace svh {
+
+template <typename T> struct CT;
+template <> struct CT<double> { typedef double2 t; };
+template <> struct CT<float> { typedef float2 t; };
+
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename C, typename T> __device__ __forceinline__ C cscale(C a, T s) { return C{a.x * s, a.y * s}; }
+// multiply by DIR * i
+template <int DIR, typename C> __device__ __forceinline__ C mul_i(C a) {
+  return DIR < 0 ? C{a.y, -a.x} : C{-a.y, a.x};
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft2(C* v) {
+  const C a = v[0];
+  v[0] = cadd(a, v[1]);
+  v[1] = csub(a, v[1]);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft4(C& v0, C& v1, C& v2, C& v3) {
+  const C a0 = cadd(v0, v2), a1 = csub(v0, v2), a2 = cadd(v1, v3);
+  const C a3 = mul_i<DIR>(csub(v1, v3));
+  v0 = cadd(a0, a2);
+  v2 = csub(a0, a2);
+  v1 = cadd(a1, a3);
+  v3 = csub(a1, a3);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft4(C* v) { dft4<DIR>(v[0], v[1], v[2], v[3]); }
+
+template <int DIR, typename C> __device__ __forceinline__ void dft8(C* v) {
+  typedef decltype(v[0].x) T;
+  C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<DIR>(e0, e1, e2, e3);
+  dft4<DIR>(o0, o1, o2, o3);
+  const T h = (T)0.70710678118654752440;
+  // o1 *= w^1, o2 *= w^2 = DIR i, o3 *= w^3 with w = exp(DIR i pi / 4)
+  o1 = C{h * (o1.x - DIR * o1.y), h * (o1.y + DIR * o1.x)};
+  o2 = mul_i<DIR>(o2);
+  o3 = C{h * (-o3.x - DIR * o3.y), h * (-o3.y + DIR * o3.x)};
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1);
+  v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2);
+  v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3);
+  v[7] = csub(e3, o3);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void dft3(C* v) {
+  typedef decltype(v[0].x) T;
+  const T s3 = (T)0.86602540378443864676;
+  const C t1 = cadd(v[1], v[2]);
+  const C t2 = C{v[0].x - (T)0.5 * t1.x, v[0].y - (T)0.5 * t1.y};
+  const C d = mul_i<DIR>(cscale(csub(v[1], v[2]), s3));
+  v[0] = cadd(v[0], t1);
+  v[1] = cadd(t2, d);
+  v[2] = csub(t2, d);
+}
+
+template <int R, int DIR, typename C> __device__ __forceinline__ void dft(C* v) {
+  if constexpr (R == 2) dft2<DIR>(v);
+  else if constexpr (R == 3) dft3<DIR>(v);
+  else if constexpr (R == 4) dft4<DIR>(v);
+  else dft8<DIR>(v);
+}
+
+template <int R> struct NbMax { static constexpr int v = R == 8 ? 1 : R == 4 ? 2 : R == 3 ? 3 : 4; };
+
+// LDS accessors.  Strided layout: element (n, w) at n * W + w.  Pencil
+// layout: element (n, w) at w * Lp + n.
+template <typename C, bool STRIDED> struct Lds {
+  C* base;
+  int W, Lp, w;
+  __device__ __forceinline__ C ld(int n) const { return STRIDED ? base[n * W + w] : base[w * Lp + n]; }
+  __device__ __forceinline__ void st(int n, C v) const {
+    if (STRIDED) base[n * W + w] = v;
+    else base[w * Lp + n] = v;
+  }
+};
+
+template <typename C, int R, int DIR, bool SYNC_MID, class Src, class Dst>
+__device__ __forceinline__ void stage_r(int L, int Ns, int j0, int TP, const Src& src, const Dst& dst,
+                                        const C* __restrict__ tw) {
+  constexpr int NB = NbMax<R>::v;
+  const int LR = L / R;
+  C v[NB][R];
+#pragma unroll
+  for (int it = 0; it < NB; ++it) {
+    const int j = j0 + it * TP;
+    if (j < LR) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[it][r] = src.ld(j + r * LR);
+    }
+  }
+  if (SYNC_MID) __syncthreads();
+#pragma unroll
+  for (int it = 0; it < NB; ++it) {
+    const int j = j0 + it * TP;
+    if (j < LR) {
+      const int k = j % Ns;
+      if (Ns > 1) {
+        const int step = L / (Ns * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          C t = tw[r * k * step];
+          if (DIR > 0) t.y = -t.y;
+          v[it][r] = cmul(v[it][r], t);
+        }
+      }
+      dft<R, DIR>(v[it]);
+      const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst.st(base + r * Ns, v[it][r]);
+    }
+  }
+}
+
+template <typename C, int DIR, bool SYNC_MID, class Src, class Dst>
+__device__ __forceinline__ void stage_any(int R, int L, int Ns, int j0, int TP, const Src& src,
+                                          const Dst& dst, const C* tw) {
+  switch (R) {
+    case 8: stage_r<C, 8, DIR, SYNC_MID>(L, Ns, j0, TP, src, dst, tw); break;
+    case 4: stage_r<C, 4, DIR, SYNC_MID>(L, Ns, j0, TP, src, dst, tw); break;
+    case 3: stage_r<C, 3, DIR, SYNC_MID>(L, Ns, j0, TP, src, dst, tw); break;
+    default: stage_r<C, 2, DIR, SYNC_MID>(L, Ns, j0, TP, src, dst, tw); break;
+  }
+}
+
+// One full 1D transform of a group of pencils: global -> (LDS stages) -> global.
+template <typename C, int DIR, bool STRIDED, class GIn, class GOut>
+__device__ __forceinline__ void fft_group(const FftPlan& pl, int j0, const GIn& gin, const GOut& gout,
+                                          const Lds<C, STRIDED>& lds, const C* tw) {
+  const int L = pl.L, TP = pl.tp;
+  if (pl.ns == 1) {
+    stage_any<C, DIR, false>(pl.r[0], L, 1, j0, TP, gin, gout, tw);
+    return;
+  }
+  int Ns = 1;
+  stage_any<C, DIR, false>(pl.r[0], L, Ns, j0, TP, gin, lds, tw);
+  Ns *= pl.r[0];
+  __syncthreads();
+  for (int s = 1; s < pl.ns - 1; ++s) {
+    stage_any<C, DIR, true>(pl.r[s], L, Ns, j0, TP, lds, lds, tw);
+    Ns *= pl.r[s];
+    __syncthreads();
+  }
+  stage_any<C, DIR, false>(pl.r[pl.ns - 1], L, Ns, j0, TP, lds, gout, tw);
+}
+
+// ----------------------------------------------------------------- X pass --
+template <typename C> struct XIn {
+  const C* __restrict__ x;       // compact vector of this component
+  const int32_t* __restrict__ vrow;  // voxel index row (Kx entries)
+  int Kx;
+  bool valid;
+  __device__ __forceinline__ C ld(int n) const {
+    if (!valid || n >= Kx) return C{0, 0};
+    const int k = vrow[n];
+    return k >= 0 ? x[k] : C{0, 0};
+  }
+};
+template <typename C> struct RowOut {
+  C* __restrict__ row;
+  int lim;
+  bool valid;
+  __device__ __forceinline__ void st(int n, C v) const {
+    if (valid && n < lim) row[n] = v;
+  }
+};
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_pass_x(FftPlan pl, int WX, int Kx, int Ky, int nzp, int K,
+                                                 const int32_t* __restrict__ zlist,
+                                                 const int32_t* __restrict__ vidx,
+                                                 const typename CT<T>::t* __restrict__ x,
+                                                 typename CT<T>::t* __restrict__ A,
+                                                 const typename CT<T>::t* __restrict__ tw) {
+  typedef typename CT<T>::t C;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int t = threadIdx.x;
+  const int j0 = t % pl.tp, w = t / pl.tp;
+  const int vec = blockIdx.y;
+  const int P = nzp * Ky;
+  const int pen = blockIdx.x * WX + w;
+  const bool valid = pen < P;
+  const int pc = valid ? pen : 0;
+  const int y = pc % Ky, zp = pc / Ky;
+  const int z = zlist[zp];
+  const int Lx = pl.L;
+  XIn<C> gin{x + (size_t)vec * K, vidx + ((size_t)z * Ky + y) * Kx, Kx, valid};
+  RowOut<C> gout{A + (((size_t)vec * nzp + zp) * Ky + y) * Lx, Lx, valid};
+  Lds<C, false> acc{lds, WX, Lx + 1, w};
+  fft_group<C, -1, false>(pl, j0, gin, gout, acc, tw);
+}
+
+// ------------------------------------------------------------ Y passes ----
+template <typename C> struct ColIn {
+  const C* __restrict__ base;  // plane start + kx
+  int stride, lim;
+  bool valid;
+  __device__ __forceinline__ C ld(int n) const {
+    return (valid && n < lim) ? base[(size_t)n * stride] : C{0, 0};
+  }
+};
+template <typename C> struct ColOut {
+  C* __restrict__ base;
+  int stride, lim;
+  bool valid;
+  __device__ __forceinline__ void st(int n, C v) const {
+    if (valid && n < lim) base[(size_t)n * stride] = v;
+  }
+};
+
+// DIR = -1: A[vec][zp][y < Ky][kx] -> B[vec][zp][ky < Ly][kx]
+// DIR = +1: B -> A (crop to y < Ky)
+template <typename T, int DIR>
+__global__ void __launch_bounds__(1024) k_pass_y(FftPlan pl, int W, int Lx, int Ky, int nzp,
+                                                 const typename CT<T>::t* __restrict__ in,
+                                                 typename CT<T>::t* __restrict__ out,
+                                                 const typename CT<T>::t* __restrict__ tw) {
+  typedef typename CT<T>::t C;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int t = threadIdx.x;
+  const int w = t % W, j0 = t / W;
+  const int vec = blockIdx.y;
+  const int ntile = (Lx + W - 1) / W;
+  const int tile = blockIdx.x % ntile, zp = blockIdx.x / ntile;
+  const int kx = tile * W + w;
+  const bool valid = kx < Lx;
+  const int kxc = valid ? kx : 0;
+  const int Ly = pl.L;
+  const int rows_in = DIR < 0 ? Ky : Ly;
+  const int rows_out = DIR < 0 ? Ly : Ky;
+  const C* ib = in + ((size_t)vec * nzp + zp) * rows_in * Lx + kxc;
+  C* ob = out + ((size_t)vec * nzp + zp) * rows_out * Lx + kxc;
+  ColIn<C> gin{ib, Lx, DIR < 0 ? Ky : Ly, valid};
+  ColOut<C> gout{ob, Lx, DIR < 0 ? Ly : Ky, valid};
+  Lds<C, true> acc{lds, W, 0, w};
+  fft_group<C, DIR, true>(pl, j0, gin, gout, acc, tw);
+}
+
+// ---------------------------------------------------------------- Z pass --
+template <typename C> struct ZIn {
+  const C* __restrict__ base;  // B + ky*Lx + kx  (vector start)
+  const int32_t* __restrict__ zslot;
+  size_t plane;  // Ly * Lx
+  bool valid;
+  __device__ __forceinline__ C ld(int n) const {
+    const int s = zslot[n];
+    return (valid && s >= 0) ? base[(size_t)s * plane] : C{0, 0};
+  }
+};
+template <typename C> struct ZOut {
+  C* __restrict__ base;
+  const int32_t* __restrict__ zslot;
+  size_t plane;
+  bool valid;
+  __device__ __forceinline__ void st(int n, C v) const {
+    const int s = zslot[n];
+    if (valid && s >= 0) base[(size_t)s * plane] = v;
+  }
+};
+
+// Last forward stage (Ns = L/R), multiply by the real spectrum, first inverse
+// stage (Ns = 1, same radix): butterfly j keeps the elements j + r L/R.
+template <typename C, typename T, int R, class Src, class Dst>
+__device__ __forceinline__ void fused_mul_r(int L, int j0, int TP, const Src& src, const Dst& dst,
+                                            const C* __restrict__ tw, const T (&zv)[12], bool sync_mid) {
+  constexpr int NB = NbMax<R>::v;
+  const int LR = L / R;
+  const int Ns = LR;
+  C v[NB][R];
+#pragma unroll
+  for (int it = 0; it < NB; ++it) {
+    const int j = j0 + it * TP;
+    if (j < LR) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[it][r] = src.ld(j + r * LR);
+    }
+  }
+  if (sync_mid) __syncthreads();
+#pragma unroll
+  for (int it = 0; it < NB; ++it) {
+    const int j = j0 + it * TP;
+    if (j < LR) {
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], tw[r * j]);  // step = 1, k = j
+      }
+      dft<R, -1>(v[it]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[it][r] = cscale(v[it][r], zv[it * R + r]);
+      dft<R, +1>(v[it]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst.st(j * R + r, v[it][r]);
+    }
+  }
+}
+
+template <typename C, typename T, class Src, class Dst>
+__device__ __forceinline__ void fused_mul(int R, int L, int j0, int TP, const Src& src, const Dst& dst,
+                                          const C* tw, const T (&zv)[12], bool sync_mid) {
+  switch (R) {
+    case 8: fused_mul_r<C, T, 8>(L, j0, TP, src, dst, tw, zv, sync_mid); break;
+    case 4: fused_mul_r<C, T, 4>(L, j0, TP, src, dst, tw, zv, sync_mid); break;
+    case 3: fused_mul_r<C, T, 3>(L, j0, TP, src, dst, tw, zv, sync_mid); break;
+    default: fused_mul_r<C, T, 2>(L, j0, TP, src, dst, tw, zv, sync_mid); break;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_pass_z(FftPlan pl, FftPlan ipl, int W, int Lx, int Ly, int nzp,
+                                                 int nvec, int vpb, const int32_t* __restrict__ zslot,
+                                                 const T* __restrict__ zhat,
+                                                 typename CT<T>::t* __restrict__ B,
+                                                 const typename CT<T>::t* __restrict__ tw) {
+  typedef typename CT<T>::t C;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int t = threadIdx.x;
+  const int w = t % W, j0 = t / W;
+  const int ntile = (Lx + W - 1) / W;
+  const int tile = blockIdx.x % ntile, ky = blockIdx.x / ntile;
+  const int kx = tile * W + w;
+  const bool valid = kx < Lx;
+  const int kxc = valid ? kx : 0;
+  const int L = pl.L, TP = pl.tp;
+  const int Rl = pl.r[pl.ns - 1];
+  const int LR = L / Rl;
+  // spectrum values for the elements this thread holds in the fused stage
+  T zv[12];
+  const size_t plane = (size_t)Ly * Lx;
+  {
+    const int nb = NbMax<8>::v;  // placeholder to keep the array size fixed
+    (void)nb;
+    int q = 0;
+    const int NB = Rl == 8 ? 1 : Rl == 4 ? 2 : Rl == 3 ? 3 : 4;
+    for (int it = 0; it < NB; ++it)
+      for (int r = 0; r < Rl; ++r, ++q) {
+        const int j = j0 + it * TP;
+        const int n = j + r * LR;
+        zv[q] = (valid && j < LR) ? zhat[(size_t)n * plane + (size_t)ky * Lx + kxc] : (T)0;
+      }
+    for (; q < 12; ++q) zv[q] = (T)0;
+  }
+  Lds<C, true> acc{lds, W, 0, w};
+  const int v0 = blockIdx.y * vpb;
+  const int v1 = min(nvec, v0 + vpb);
+  for (int vec = v0; vec < v1; ++vec) {
+    C* vb = B + (size_t)vec * nzp * plane + (size_t)ky * Lx + kxc;
+    ZIn<C> gin{vb, zslot, plane, valid};
+    ZOut<C> gout{vb, zslot, plane, valid};
+    if (pl.ns == 1) {
+      fused_mul<C, T>(Rl, L, j0, TP, gin, gout, tw, zv, false);
+    } else {
+      int Ns = 1;
+      stage_any<C, -1, false>(pl.r[0], L, Ns, j0, TP, gin, acc, tw);
+      Ns *= pl.r[0];
+      __syncthreads();
+      for (int s = 1; s < pl.ns - 1; ++s) {
+        stage_any<C, -1, true>(pl.r[s], L, Ns, j0, TP, acc, acc, tw);
+        Ns *= pl.r[s];
+        __syncthreads();
+      }
+      fused_mul<C, T>(Rl, L, j0, TP, acc, acc, tw, zv, true);
+      __syncthreads();
+      Ns = Rl;
+      for (int s = 1; s < ipl.ns - 1; ++s) {
+        stage_any<C, +1, true>(ipl.r[s], L, Ns, j0, TP, acc, acc, tw);
+        Ns *= ipl.r[s];
+        __syncthreads();
+      }
+      stage_any<C, +1, false>(ipl.r[ipl.ns - 1], L, Ns, j0, TP, acc, gout, tw);
+      __syncthreads();
+    }
+  }
+}
+
+// --------------------------------------------------------------- Xi pass --
+template <typename C, typename T> struct XOut {
+  C* __restrict__ y;                 // compact output of this component
+  const C* __restrict__ x;           // compact input (diagonal term)
+  const C* __restrict__ cd;          // c/dx per voxel (nullptr: bare)
+  const int32_t* __restrict__ vrow;
+  C scale;
+  int Kx;
+  bool valid;
+  __device__ __forceinline__ void st(int n, C v) const {
+    if (!valid || n >= Kx) return;
+    const int k = vrow[n];
+    if (k < 0) return;
+    C o = cmul(v, scale);
+    if (cd) o = cadd(o, cmul(cd[k], x[k]));
+    y[k] = o;
+  }
+};
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_pass_xi(FftPlan pl, int WX, int Kx, int Ky, int nzp, int K,
+                                                  EpiParams ep, const int32_t* __restrict__ zlist,
+                                                  const int32_t* __restrict__ vidx,
+                                                  const typename CT<T>::t* __restrict__ A,
+                                                  const typename CT<T>::t* __restrict__ x,
+                                                  typename CT<T>::t* __restrict__ y,
+                                                  const typename CT<T>::t* __restrict__ sconv,
+                                                  const typename CT<T>::t* __restrict__ cdiag,
+                                                  T inv_n,
+                                                  const typename CT<T>::t* __restrict__ tw) {
+  typedef typename CT<T>::t C;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int t = threadIdx.x;
+  const int j0 = t % pl.tp, w = t / pl.tp;
+  const int vec = blockIdx.y;
+  const int P = nzp * Ky;
+  const int pen = blockIdx.x * WX + w;
+  const bool valid = pen < P;
+  const int pc = valid ? pen : 0;
+  const int yy = pc % Ky, zp = pc / Ky;
+  const int z = zlist[zp];
+  const int Lx = pl.L;
+  const int f = ep.fidx[vec / ep.C];
+  C scale = f >= 0 ? cscale(sconv[f], inv_n) : C{inv_n, 0};
+  const C* cd = f >= 0 ? cdiag + (size_t)f * K : nullptr;
+  ColIn<C> gin{A + (((size_t)vec * nzp + zp) * Ky + yy) * Lx, 1, Lx, valid};
+  XOut<C, T> gout{y + (size_t)vec * K, x + (size_t)vec * K, cd, vidx + ((size_t)z * Ky + yy) * Kx,
+                  scale, Kx, valid};
+  Lds<C, false> acc{lds, WX, Lx + 1, w};
+  fft_group<C, +1, false>(pl, j0, gin, gout, acc, tw);
+}
+
+// ------------------------------------------------------------- launcher ---
+static int pencils_per_block_x(int tp) {
+  int w = 256 / tp;
+  return w < 1 ? 1 : w;
+}
+
+// Columns per block of the strided passes: full 128-byte rows of x-adjacent
+// elements when possible, within 1024 threads and 64 KiB of LDS.
+static int cols_per_block(int tp, int L, size_t csize) {
+  int W = csize == 16 ? 8 : 16;
+  while (W > 1 && (W * tp > 1024 || (size_t)W * L * csize > 65536)) W /= 2;
+  return W;
+}
+
+template <typename T>
+hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& ep, const void* xv,
+                               void* yv, void* Av, void* Bv, const void* zhat, hipStream_t s,
+                               hipEvent_t* ev) {
+  typedef typename CT<T>::t C;
+  const bool dbl = sizeof(T) == 8;
+  const C* x = static_cast<const C*>(xv);
+  C* y = static_cast<C*>(yv);
+  C* A = static_cast<C*>(Av);
+  C* B = static_cast<C*>(Bv);
+  const C* tw[3];
+  for (int a = 0; a < 3; ++a)
+    tw[a] = dbl ? reinterpret_cast<const C*>(p->d_tw64[a]) : reinterpret_cast<const C*>(p->d_tw32[a]);
+  const int Kx = p->K[0], Ky = p->K[1];
+  const int Lx = p->L[0], Ly = p->L[1];
+  const int nzp = (int)p->zlist.size();
+  const int K = p->nvox;
+  if (ev) hipEventRecord(ev[0], s);
+  // X
+  {
+    const FftPlan& pl = p->plan[0];
+    const int WX = pencils_per_block_x(pl.tp);
+    const int P = nzp * Ky;
+    dim3 grid((P + WX - 1) / WX, nvec);
+    const size_t sh = (size_t)WX * (Lx + 1) * sizeof(C);
+    hipLaunchKernelGGL(k_pass_x<T>, grid, dim3(WX * pl.tp), sh, s, pl, WX, Kx, Ky, nzp, K, p->d_zlist,
+                       p->d_vidx, x, A, tw[0]);
+  }
+  if (ev) hipEventRecord(ev[1], s);
+  // Y forward
+  {
+    const FftPlan& pl = p->plan[1];
+    const int W = cols_per_block(pl.tp, pl.L, sizeof(C));
+    dim3 grid(((Lx + W - 1) / W) * nzp, nvec);
+    const size_t sh = (size_t)W * Ly * sizeof(C);
+    hipLaunchKernelGGL((k_pass_y<T, -1>), grid, dim3(W * pl.tp), sh, s, pl, W, Lx, Ky, nzp, A, B, tw[1]);
+  }
+  if (ev) hipEventRecord(ev[2], s);
+  // Z multiply
+  {
+    const FftPlan& pl = p->plan[2];
+    const int W = cols_per_block(pl.tp, pl.L, sizeof(C));
+    const FftPlan ipl = reversed(pl);
+    const int vpb = nvec < 4 ? nvec : 4;
+    dim3 grid(((Lx + W - 1) / W) * Ly, (nvec + vpb - 1) / vpb);
+    const size_t sh = (size_t)W * pl.L * sizeof(C);
+    hipLaunchKernelGGL(k_pass_z<T>, grid, dim3(W * pl.tp), sh, s, pl, ipl, W, Lx, Ly, nzp, nvec, vpb,
+                       p->d_zslot, static_cast<const T*>(zhat), B, tw[2]);
+  }
+  if (ev) hipEventRecord(ev[3], s);
+  // Y inverse
+  {
+    const FftPlan& pl = p->plan[1];
+    const int W = cols_per_block(pl.tp, pl.L, sizeof(C));
+    dim3 grid(((Lx + W - 1) / W) * nzp, nvec);
+    const size_t sh = (size_t)W * Ly * sizeof(C);
+    hipLaunchKernelGGL((k_pass_y<T, +1>), grid, dim3(W * pl.tp), sh, s, pl, W, Lx, Ky, nzp, B, A, tw[1]);
+  }
+  if (ev) hipEventRecord(ev[4], s);
+  // X inverse + epilogue
+  {
+    const FftPlan& pl = p->plan[0];
+    const int WX = pencils_per_block_x(pl.tp);
+    const int P = nzp * Ky;
+    dim3 grid((P + WX - 1) / WX, nvec);
+    const size_t sh = (size_t)WX * (Lx + 1) * sizeof(C);
+    const T inv_n = (T)(1.0 / ((double)p->L[0] * p->L[1] * p->L[2]));
+    const C* sc = dbl ? reinterpret_cast<const C*>(p->d_sconv64) : reinterpret_cast<const C*>(p->d_sconv32);
+    const C* cd = dbl ? reinterpret_cast<const C*>(p->d_cdiag64) : reinterpret_cast<const C*>(p->d_cdiag32);
+    hipLaunchKernelGGL(k_pass_xi<T>, grid, dim3(WX * pl.tp), sh, s, pl, WX, Kx, Ky, nzp, K, ep,
+                       p->d_zlist, p->d_vidx, A, x, y, sc, cd, inv_n, tw[0]);
+  }
+  if (ev) hipEventRecord(ev[5], s);
+  return hipGetLastError();
+}
+
+template hipError_t launch_matvec_chunk<double>(const svh_problem*, int, const EpiParams&, const void*,
+                                                void*, void*, void*, const void*, hipStream_t, hipEvent_t*);
+template hipError_t launch_matvec_chunk<float>(const svh_problem*, int, const EpiParams&, const void*,
+                                               void*, void*, void*, const void*, hipStream_t, hipEvent_t*);
+
+}  // namespace svh

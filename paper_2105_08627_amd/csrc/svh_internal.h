@@ -1,0 +1,99 @@
+// Internal declarations of the SVH library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/svh.h"
+
+namespace svh {
+
+constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;  // H/m (mu = mu0, Sec. II.A)
+constexpr int kMaxVecsPerChunk = 256;  // component vectors per pass launch
+constexpr int kMaxStages = 8;
+
+// Mixed-radix Stockham plan: L = prod r[s], radices in {8, 4, 2, 3}.
+struct FftPlan {
+  int L = 0;
+  int ns = 0;
+  int r[kMaxStages] = {0};
+  int tp = 0;  // threads per pencil = min_s L / r[s]
+};
+bool make_plan(int L, FftPlan& p);
+FftPlan reversed(const FftPlan& p);
+bool supported_length(int L);
+
+// Device-side Tucker representation of one spectrum.
+struct DevTucker {
+  int d[3] = {0, 0, 0};
+  double* core = nullptr;  // [c][b][a]
+  double* F[3] = {nullptr, nullptr, nullptr};  // [k][c]
+};
+
+// Per-call kernel parameters of the final (x-inverse) pass.
+struct EpiParams {
+  int C;              // components per right-hand side
+  int K;              // non-empty voxels
+  int vec0;           // first component-vector of this chunk
+  int fidx[kMaxVecsPerChunk];  // frequency slot per RHS of the chunk (-1 = bare)
+};
+
+}  // namespace svh
+
+struct svh_problem {
+  int K[3] = {0, 0, 0};
+  int L[3] = {0, 0, 0};
+  double dx = 0;
+  int basis = 3;
+  int C = 3;
+  int nvox = 0;
+  int device = 0;
+  std::vector<int32_t> vidx;       // dense -> compact index or -1, [z][y][x]
+  std::vector<int32_t> zlist;      // occupied z planes
+  std::vector<int32_t> zslot;      // z -> plane slot or -1 (size L[2])
+  int32_t* d_vidx = nullptr;
+  int32_t* d_zlist = nullptr;
+  int32_t* d_zslot = nullptr;
+  svh::FftPlan plan[3];
+  double2* d_tw64[3] = {nullptr, nullptr, nullptr};  // e^{-2 pi i m / L}
+  float2* d_tw32[3] = {nullptr, nullptr, nullptr};
+  // material
+  int nfreq = 0;
+  std::vector<std::complex<double>> sconv;  // j w mu0 dx per frequency
+  double2* d_sconv64 = nullptr;             // [nfreq]
+  float2* d_sconv32 = nullptr;
+  double2* d_cdiag64 = nullptr;  // [nfreq][K] c / dx
+  float2* d_cdiag32 = nullptr;
+  // tensors
+  std::vector<double> T;        // Toeplitz tensor, host [Kz][Ky][Kx]
+  double* d_zhat64 = nullptr;   // dense spectrum [Lz][Ly][Lx] (real)
+  float* d_zhat32 = nullptr;
+  bool tucker = false;
+  svh::DevTucker tk;
+  // per-kernel timing: one event set per enqueued chunk while enabled
+  bool prof = false;
+  std::vector<std::vector<hipEvent_t>> prof_events;  // [tucker0, tucker1, x, y, z, yi, xi, end]
+  std::vector<hipEvent_t> prof_pool;
+  std::string err;
+};
+
+namespace svh {
+// device launchers (return hipError_t)
+hipError_t launch_even_spectrum(const svh_problem* p, const double* d_T, double* d_out,
+                                double* d_tmp1, double* d_tmp2, hipStream_t s);
+hipError_t launch_tucker_rebuild(const svh_problem* p, bool fp32_out, void* d_out,
+                                 double* d_V, double* d_W, hipStream_t s);
+size_t tucker_scratch_doubles(const svh_problem* p);
+hipError_t launch_to_f32(const double* in, float* out, size_t n, hipStream_t s);
+
+template <typename T>
+hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& ep,
+                               const void* x, void* y, void* A, void* B, const void* zhat,
+                               hipStream_t s, hipEvent_t* ev);
+}  // namespace svh

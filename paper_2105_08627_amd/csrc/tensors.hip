@@ -1,0 +1,154 @@
+// Circulant spectrum construction and Tucker restoration kernels (gfx950).
+//
+//  * k_even_axis: one axis of the real spectrum of the even circulant
+//    embedding (Sec. II.A): out[k] = sum_{n<K} w_n T[n] cos(2 pi k n / L),
+//    w_0 = 1, w_n = 2 (the entries at n and L - n of the embedding).
+//  * k_gemm_f64_mfma: strided batched FP64 GEMM on the matrix cores
+//    (v_mfma_f64_16x16x4f64), used for the three mode products of the Tucker
+//    restoration Z = core x1 F1 x2 F2 x3 F3 (eqs. 10-11).  The last product
+//    writes the restored spectrum in the precision of the matvec (FP64
+//    accumulation in both cases).
+#include "svh_internal.h"
+
+namespace svh {
+
+__global__ void k_even_axis(const double* __restrict__ in, double* __restrict__ out, int nouter, int Kin,
+                            int L, int ninner, const double* __restrict__ cosT) {
+  const size_t total = (size_t)nouter * L * ninner;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < total;
+       id += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(id % ninner);
+    const size_t rest = id / ninner;
+    const int k = (int)(rest % L);
+    const size_t o = rest / L;
+    const double* src = in + o * (size_t)Kin * ninner + i;
+    double s = src[0];
+    long long m = 0;
+    for (int n = 1; n < Kin; ++n) {
+      m += k;
+      if (m >= L) m -= L;
+      s += 2.0 * src[(size_t)n * ninner] * cosT[m];
+    }
+    out[id] = s;
+  }
+}
+
+__global__ void k_f64_to_f32(const double* __restrict__ in, float* __restrict__ out, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = (float)in[i];
+}
+
+hipError_t launch_to_f32(const double* in, float* out, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_f64_to_f32, dim3(1024), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+struct GemmArgs {
+  int M, N, Kd;
+  const double* A;
+  long long sam, sak, sab;
+  const double* B;
+  long long sbk, sbn, sbb;
+  void* C;
+  long long scm, scn, scb;
+};
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// One wavefront per 16-column tile; it walks all 16-row tiles of its column.
+// Operand layout of v_mfma_f64_16x16x4f64 (wave64): lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; the result register r of lane l
+// is D[l / 16 + 4 r][l % 16] (checked on the device against a host product).
+template <typename TOut>
+__global__ void __launch_bounds__(256) k_gemm_f64_mfma(GemmArgs g) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int tiles_n = (g.N + 15) / 16;
+  const int tn = blockIdx.x * 4 + wave;
+  if (tn >= tiles_n) return;
+  const long long b = blockIdx.y;
+  const double* A = g.A + b * g.sab;
+  const double* Bm = g.B + b * g.sbb;
+  TOut* C = static_cast<TOut*>(g.C) + b * g.scb;
+  const int col = tn * 16 + (lane & 15);
+  const int kq = lane >> 4;
+  const int tiles_m = (g.M + 15) / 16;
+  for (int tm = 0; tm < tiles_m; ++tm) {
+    const int row = tm * 16 + (lane & 15);
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < g.Kd; k0 += 4) {
+      const int kk = k0 + kq;
+      const double a = (row < g.M && kk < g.Kd) ? A[row * g.sam + kk * g.sak] : 0.0;
+      const double bv = (col < g.N && kk < g.Kd) ? Bm[kk * g.sbk + col * g.sbn] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int orow = tm * 16 + kq + 4 * r;
+      if (orow < g.M && col < g.N) C[orow * g.scm + col * g.scn] = (TOut)acc[r];
+    }
+  }
+}
+
+static hipError_t gemm(const GemmArgs& g, int batch, bool f32out, hipStream_t s) {
+  const int tiles_n = (g.N + 15) / 16;
+  dim3 grid((tiles_n + 3) / 4, batch);
+  if (f32out) hipLaunchKernelGGL(k_gemm_f64_mfma<float>, grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL(k_gemm_f64_mfma<double>, grid, dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_even_spectrum(const svh_problem* p, const double* d_T, double* d_out, double* d_tmp1,
+                                double* d_tmp2, hipStream_t s) {
+  // cos tables are built per call (setup only)
+  const int Kx = p->K[0], Ky = p->K[1], Kz = p->K[2];
+  const int Lx = p->L[0], Ly = p->L[1], Lz = p->L[2];
+  std::vector<double> tab;
+  double* d_cos = nullptr;
+  const int Lmax = std::max(Lx, std::max(Ly, Lz));
+  hipError_t e = hipMalloc(&d_cos, sizeof(double) * 3 * Lmax);
+  if (e != hipSuccess) return e;
+  tab.assign(3 * (size_t)Lmax, 0.0);
+  for (int a = 0; a < 3; ++a)
+    for (int m = 0; m < p->L[a]; ++m)
+      tab[(size_t)a * Lmax + m] = (double)cosl(2.0L * 3.141592653589793238462643383279502884L * m / p->L[a]);
+  e = hipMemcpyAsync(d_cos, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    // x: [Kz][Ky][Kx] -> [Kz][Ky][Lx]
+    hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, d_T, d_tmp1, Kz * Ky, Kx, Lx, 1, d_cos);
+    // y: [Kz][Ky][Lx] -> [Kz][Ly][Lx]
+    hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, d_tmp1, d_tmp2, Kz, Ky, Ly, Lx,
+                       d_cos + Lmax);
+    // z: [Kz][Ly][Lx] -> [Lz][Ly][Lx]
+    hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, d_tmp2, d_out, 1, Kz, Lz, Ly * Lx,
+                       d_cos + 2 * Lmax);
+    e = hipGetLastError();
+  }
+  hipError_t e2 = hipStreamSynchronize(s);
+  hipFree(d_cos);
+  return e != hipSuccess ? e : e2;
+}
+
+size_t tucker_scratch_doubles(const svh_problem* p) {
+  const DevTucker& t = p->tk;
+  return (size_t)p->L[0] * t.d[1] * t.d[2] + (size_t)p->L[0] * p->L[1] * t.d[2];
+}
+
+hipError_t launch_tucker_rebuild(const svh_problem* p, bool fp32_out, void* d_out, double* d_V, double* d_W,
+                                 hipStream_t s) {
+  const DevTucker& t = p->tk;
+  const int L1 = p->L[0], L2 = p->L[1], L3 = p->L[2];
+  const int d1 = t.d[0], d2 = t.d[1], d3 = t.d[2];
+  hipError_t e;
+  // V[kx][c][b] = sum_a F1[kx][a] core[c][b][a]
+  GemmArgs g1{L1, d2 * d3, d1, t.F[0], d1, 1, 0, t.core, 1, d1, 0, d_V, (long long)d2 * d3, 1, 0};
+  if ((e = gemm(g1, 1, false, s)) != hipSuccess) return e;
+  // W[ky][kx][c] = sum_b F2[ky][b] V[kx][c][b]   (batched over kx)
+  GemmArgs g2{L2, d3, d2, t.F[1], d2, 1, 0, d_V, 1, d2, (long long)d2 * d3, d_W, (long long)L1 * d3, 1, d3};
+  if ((e = gemm(g2, L1, false, s)) != hipSuccess) return e;
+  // Z[kz][ky][kx] = sum_c F3[kz][c] W[ky][kx][c]
+  GemmArgs g3{L3, L1 * L2, d3, t.F[2], d3, 1, 0, d_W, 1, d3, 0, d_out, (long long)L1 * L2, 1, 0};
+  return gemm(g3, 1, fp32_out, s);
+}
+
+}  // namespace svh
