@@ -135,6 +135,20 @@ svh_status svh_profile_enable(svh_problem* p, int enable);
  * the number of kernel sequences summed.  Waits for the recorded events. */
 svh_status svh_profile_read(svh_problem* p, double* ms_out, int* ncalls_out);
 
+/* Choice of the z-direction step of the product (all choices give the same
+ * operator up to rounding):
+ *  SVH_ZSTEP_AUTO   (default) direct sum when at most 32 z planes hold voxels,
+ *                   else the FFT along z;
+ *  SVH_ZSTEP_FFT    zero-padded FFT along z, product with the circulant
+ *                   spectrum, inverse FFT (eq. 9 literally);
+ *  SVH_ZSTEP_DIRECT after the x and y transforms, the Toeplitz sum along z
+ *                   over the occupied planes with the inverse z transform of
+ *                   the circulant spectrum (EINVAL if more than 32 planes). */
+#define SVH_ZSTEP_AUTO 0
+#define SVH_ZSTEP_FFT 1
+#define SVH_ZSTEP_DIRECT 2
+svh_status svh_set_zstep(svh_problem* p, int mode);
+
 /* Text of the last error on this problem (never NULL). */
 const char* svh_last_error(const svh_problem* p);
 

@@ -16,12 +16,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsvh.so")
 
 SVH_FP64, SVH_FP32 = 0, 1
+ZSTEP = {"auto": 0, "fft": 1, "direct": 2}
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "ESTATE"}
 
 EXPORTED = [
     "svh_create", "svh_get_sizes", "svh_set_material", "svh_setup_tensors", "svh_green_toeplitz",
     "svh_get_toeplitz", "svh_tucker_compress", "svh_workspace_bytes", "svh_matvec",
-    "svh_profile_enable", "svh_profile_read", "svh_last_error", "svh_destroy",
+    "svh_set_zstep", "svh_profile_enable", "svh_profile_read", "svh_last_error", "svh_destroy",
 ]
 PROF_NAMES = ["tucker_restore", "pass_x", "pass_y", "pass_z_mul", "pass_yi", "pass_xi"]
 
@@ -52,6 +53,7 @@ def lib():
     L.svh_workspace_bytes.argtypes = [vp, i32, i32]
     L.svh_workspace_bytes.restype = sz
     L.svh_matvec.argtypes = [vp, i32, i32, vp, vp, vp, vp, sz, vp]
+    L.svh_set_zstep.argtypes = [vp, i32]
     L.svh_profile_enable.argtypes = [vp, i32]
     L.svh_profile_read.argtypes = [vp, vp, vp]
     L.svh_last_error.argtypes = [vp]
@@ -166,6 +168,11 @@ class Problem:
                               _stream_handle(stream))
         self._check(st, "svh_matvec")
         return y
+
+    def set_zstep(self, mode):
+        """'auto', 'fft' (padded z FFT) or 'direct' (z-space sum over occupied planes)."""
+        self._check(lib().svh_set_zstep(self._h, ZSTEP[mode]), "svh_set_zstep")
+        self._ws.clear()
 
     def profile(self, enable=True):
         self._check(lib().svh_profile_enable(self._h, int(enable)), "svh_profile_enable")

@@ -86,6 +86,7 @@ int choose_length(int K) {
 
 void free_tucker(svh_problem* p) {
   dfree(p->tk.core);
+  dfree(p->tk.Fz);
   for (int a = 0; a < 3; ++a) dfree(p->tk.F[a]);
   p->tk = DevTucker();
   p->tucker = false;
@@ -217,22 +218,27 @@ svh_status svh_setup_tensors(svh_problem* p, void* stream) {
   free_tucker(p);
   dfree(p->d_zhat64);
   dfree(p->d_zhat32);
+  dfree(p->d_g64);
+  dfree(p->d_g32);
   const size_t Lt = (size_t)p->L[0] * p->L[1] * p->L[2];
-  double *dT = nullptr, *t1 = nullptr, *t2 = nullptr;
-  HIPCHK(hipMalloc(&p->d_zhat64, Lt * sizeof(double)));
-  HIPCHK(hipMalloc(&p->d_zhat32, Lt * sizeof(float)));
-  HIPCHK(hipMalloc(&dT, Kt * sizeof(double)));
+  double *dT = nullptr, *t1 = nullptr;
   const size_t n1 = (size_t)p->K[2] * p->K[1] * p->L[0];
   const size_t n2 = (size_t)p->K[2] * p->L[1] * p->L[0];
+  HIPCHK(hipMalloc(&p->d_zhat64, Lt * sizeof(double)));
+  HIPCHK(hipMalloc(&p->d_zhat32, Lt * sizeof(float)));
+  HIPCHK(hipMalloc(&p->d_g64, n2 * sizeof(double)));
+  HIPCHK(hipMalloc(&p->d_g32, n2 * sizeof(float)));
+  HIPCHK(hipMalloc(&dT, Kt * sizeof(double)));
   hipError_t e = hipMalloc(&t1, n1 * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&t2, n2 * sizeof(double));
   if (e == hipSuccess) e = hipMemcpyAsync(dT, p->T.data(), Kt * sizeof(double), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = launch_even_spectrum(p, dT, p->d_zhat64, t1, t2, s);
+  // the x and y axes of the spectrum give the z-space kernel; the z axis
+  // then gives the full circulant spectrum
+  if (e == hipSuccess) e = launch_even_spectrum(p, dT, p->d_zhat64, t1, p->d_g64, s);
   if (e == hipSuccess) e = launch_to_f32(p->d_zhat64, p->d_zhat32, Lt, s);
+  if (e == hipSuccess) e = launch_to_f32(p->d_g64, p->d_g32, n2, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   hipFree(dT);
   if (t1) hipFree(t1);
-  if (t2) hipFree(t2);
   HIPCHK(e);
   return SVH_OK;
 }
@@ -263,9 +269,28 @@ svh_status svh_tucker_compress(svh_problem* p, double tol, int32_t* ranks_out, d
   p->tk.d[2] = tf.d[2];
   HIPCHK(upload(&p->tk.core, tf.core.data(), tf.core.size()));
   for (int a = 0; a < 3; ++a) HIPCHK(upload(&p->tk.F[a], tf.F[a].data(), tf.F[a].size()));
+  // z-space third factor: inverse z transform of F3 at offsets dz < Kz
+  // (F3 columns are real and even in kz, so the transform is a cosine sum)
+  {
+    const int Lz = p->L[2], Kz = p->K[2], d3 = tf.d[2];
+    std::vector<double> Fz((size_t)Kz * d3);
+    for (int dz = 0; dz < Kz; ++dz)
+      for (int c = 0; c < d3; ++c) {
+        long double acc = 0;
+        for (int kz = 0; kz < Lz; ++kz) {
+          const long long m = ((long long)kz * dz) % Lz;
+          acc += (long double)tf.F[2][(size_t)kz * d3 + c] *
+                 cosl(2.0L * 3.141592653589793238462643383279502884L * m / Lz);
+        }
+        Fz[(size_t)dz * d3 + c] = (double)(acc / Lz);
+      }
+    HIPCHK(upload(&p->tk.Fz, Fz.data(), Fz.size()));
+  }
   p->tucker = true;
   dfree(p->d_zhat64);
   dfree(p->d_zhat32);
+  dfree(p->d_g64);
+  dfree(p->d_g32);
   if (ranks_out)
     for (int a = 0; a < 3; ++a) ranks_out[a] = tf.d[a];
   if (relerr_out) *relerr_out = tf.relerr;
@@ -278,7 +303,7 @@ size_t svh_workspace_bytes(const svh_problem* p, svh_prec prec, int nrhs) {
   const int cr = chunk_rhs(p, nrhs);
   size_t b = (size_t)cr * p->C * vec_bytes_AB(p, cs);
   if (p->tucker) {
-    const size_t Lt = (size_t)p->L[0] * p->L[1] * p->L[2];
+    const size_t Lt = (size_t)p->L[0] * p->L[1] * (use_zdirect(p) ? p->K[2] : p->L[2]);
     b += Lt * (prec == SVH_FP64 ? sizeof(double) : sizeof(float));
     b += tucker_scratch_doubles(p) * sizeof(double);
   }
@@ -314,7 +339,9 @@ svh_status svh_matvec(svh_problem* p, svh_prec prec, int nrhs, const int32_t* fr
   const size_t Bbytes = (size_t)cr * p->C * nzp * p->L[1] * p->L[0] * cs;
   char* A = w;
   char* B = w + Abytes;
-  const void* zhat = dbl ? (const void*)p->d_zhat64 : (const void*)p->d_zhat32;
+  const bool zdirect = use_zdirect(p);
+  const void* zhat = zdirect ? (dbl ? (const void*)p->d_g64 : (const void*)p->d_g32)
+                             : (dbl ? (const void*)p->d_zhat64 : (const void*)p->d_zhat32);
   std::vector<hipEvent_t> evs;
   if (p->prof) {
     const int nchunk = (nrhs + cr - 1) / cr;
@@ -332,15 +359,15 @@ svh_status svh_matvec(svh_problem* p, svh_prec prec, int nrhs, const int32_t* fr
   }
   if (p->tucker) {
     char* zb = B + align(Bbytes);
-    const size_t Lt = (size_t)p->L[0] * p->L[1] * p->L[2];
+    const size_t Lt = (size_t)p->L[0] * p->L[1] * (zdirect ? p->K[2] : p->L[2]);
     double* V = reinterpret_cast<double*>(zb + align(Lt * (dbl ? 8 : 4)));
     double* Wt = V + (size_t)p->L[0] * p->tk.d[1] * p->tk.d[2];
     if (reinterpret_cast<char*>(Wt + (size_t)p->L[0] * p->L[1] * p->tk.d[2]) > w + ws_bytes)
       return fail(p, SVH_EINVAL, "matvec: workspace too small");
-    HIPCHK(launch_tucker_rebuild(p, !dbl, zb, V, Wt, s));
+    HIPCHK(launch_tucker_rebuild(p, !dbl, zdirect, zb, V, Wt, s));
     zhat = zb;
-  } else if (!dbl && !p->d_zhat32) {
-    return fail(p, SVH_ESTATE, "matvec: no FP32 spectrum");
+  } else if (!zhat) {
+    return fail(p, SVH_ESTATE, "matvec: no spectrum");
   }
   if (p->prof) HIPCHK(hipEventRecord(evs[1], s));
   for (int r0 = 0; r0 < nrhs; r0 += cr) {
@@ -367,6 +394,16 @@ svh_status svh_matvec(svh_problem* p, svh_prec prec, int nrhs, const int32_t* fr
   }
   for (size_t i = 0; i < evs.size(); i += 8)
     p->prof_events.push_back(std::vector<hipEvent_t>(evs.begin() + i, evs.begin() + i + 8));
+  return SVH_OK;
+}
+
+svh_status svh_set_zstep(svh_problem* p, int mode) {
+  if (!p) return SVH_EINVAL;
+  if (mode != SVH_ZSTEP_AUTO && mode != SVH_ZSTEP_FFT && mode != SVH_ZSTEP_DIRECT)
+    return fail(p, SVH_EINVAL, "set_zstep: unknown mode");
+  if (mode == SVH_ZSTEP_DIRECT && (int)p->zlist.size() > kMaxDirectPlanes)
+    return fail(p, SVH_EINVAL, "set_zstep: direct z sum supports at most 32 occupied planes");
+  p->zstep = mode;
   return SVH_OK;
 }
 
@@ -420,6 +457,8 @@ void svh_destroy(svh_problem* p) {
   dfree(p->d_cdiag32);
   dfree(p->d_zhat64);
   dfree(p->d_zhat32);
+  dfree(p->d_g64);
+  dfree(p->d_g32);
   free_tucker(p);
   for (auto& set : p->prof_events)
     for (hipEvent_t e : set) (void)hipEventDestroy(e);

@@ -407,6 +407,64 @@ __global__ void __launch_bounds__(1024) k_pass_z(FftPlan pl, FftPlan ipl, int W,
   }
 }
 
+// ------------------------------------------------- Z step, direct sum ----
+// Same z-direction product as k_pass_z, written in z space: after the x and y
+// transforms, pencil (kx, ky) needs y[z_i] = sum_j g(kx, ky, |z_i - z_j|) x[z_j]
+// over the occupied planes only, where g is the inverse z transform of the
+// circulant spectrum (real and even in the offset because the spectrum is
+// real and even).  Exact for any plane set; used when few planes are occupied
+// (the padded z FFT then spends almost all of its work on zeros).
+// Block: W adjacent kx of one ky; thread (w, lane) owns pencil w for the
+// vectors lane, lane + nlanes, ...: it holds all of one vector's z values in
+// registers, so the in-place update needs no barrier.
+template <typename T, int NZ>
+__global__ void __launch_bounds__(256) k_zdirect(int W, int Lx, int Ly, int Kz, int nzp, int nvec, int vpb,
+                                                 const int32_t* __restrict__ zlist,
+                                                 const T* __restrict__ g,
+                                                 typename CT<T>::t* __restrict__ B) {
+  typedef typename CT<T>::t C;
+  extern __shared__ unsigned char smem_raw[];
+  T* gs = reinterpret_cast<T*>(smem_raw);            // [Kz][W]
+  int* zl = reinterpret_cast<int*>(gs + (size_t)Kz * W);
+  const int t = threadIdx.x;
+  const int ntile = (Lx + W - 1) / W;
+  const int tile = blockIdx.x % ntile, ky = blockIdx.x / ntile;
+  for (int i = t; i < Kz * W; i += blockDim.x) {
+    const int dz = i / W, w = i % W, kx = tile * W + w;
+    gs[i] = kx < Lx ? g[((size_t)dz * Ly + ky) * Lx + kx] : (T)0;
+  }
+  for (int i = t; i < nzp; i += blockDim.x) zl[i] = zlist[i];
+  __syncthreads();
+  const int w = t % W, lane = t / W, nl = blockDim.x / W;
+  const int kx = tile * W + w;
+  if (kx >= Lx) return;
+  const size_t plane = (size_t)Ly * Lx;
+  const int v0 = blockIdx.y * vpb, v1 = min(nvec, v0 + vpb);
+  for (int vec = v0 + lane; vec < v1; vec += nl) {
+    C* base = B + (size_t)vec * nzp * plane + (size_t)ky * Lx + kx;
+    C xv[NZ];
+#pragma unroll
+    for (int j = 0; j < NZ; ++j)
+      if (j < nzp) xv[j] = base[(size_t)j * plane];
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) {
+      if (i >= nzp) break;
+      const int zi = zl[i];
+      T ar = 0, ai = 0;
+#pragma unroll
+      for (int j = 0; j < NZ; ++j) {
+        if (j < nzp) {
+          const int d = zi - zl[j];
+          const T gv = gs[(d < 0 ? -d : d) * W + w];
+          ar += gv * xv[j].x;
+          ai += gv * xv[j].y;
+        }
+      }
+      base[(size_t)i * plane] = C{ar, ai};
+    }
+  }
+}
+
 // --------------------------------------------------------------- Xi pass --
 template <typename C, typename T> struct XOut {
   C* __restrict__ y;                 // compact output of this component
@@ -461,6 +519,13 @@ __global__ void __launch_bounds__(1024) k_pass_xi(FftPlan pl, int WX, int Kx, in
 }
 
 // ------------------------------------------------------------- launcher ---
+bool use_zdirect(const svh_problem* p) {
+  const int nzp = (int)p->zlist.size();
+  if (p->zstep == SVH_ZSTEP_FFT) return false;
+  if (p->zstep == SVH_ZSTEP_DIRECT) return nzp <= kMaxDirectPlanes;
+  return nzp <= kMaxDirectPlanes;
+}
+
 static int pencils_per_block_x(int tp) {
   int w = 256 / tp;
   return w < 1 ? 1 : w;
@@ -512,8 +577,26 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     hipLaunchKernelGGL((k_pass_y<T, -1>), grid, dim3(W * pl.tp), sh, s, pl, W, Lx, Ky, nzp, A, B, tw[1]);
   }
   if (ev) hipEventRecord(ev[2], s);
-  // Z multiply
-  {
+  // Z step: padded FFT along z with the spectrum product, or the direct sum
+  const bool zdirect = use_zdirect(p);
+  if (zdirect) {
+    int W = dbl ? 16 : 32;
+    while (W > 1 && (size_t)p->K[2] * W * sizeof(T) + (size_t)nzp * sizeof(int) > 65536) W /= 2;
+    const int nl = 256 / W;
+    const int vpb = nvec <= nl * 8 ? nvec : nl * 8;
+    dim3 grid(((Lx + W - 1) / W) * Ly, (nvec + vpb - 1) / vpb);
+    const size_t sh = (size_t)p->K[2] * W * sizeof(T) + (size_t)nzp * sizeof(int);
+    const int Kz = p->K[2];
+    if (nzp <= 8)
+      hipLaunchKernelGGL((k_zdirect<T, 8>), grid, dim3(256), sh, s, W, Lx, Ly, Kz, nzp, nvec, vpb, p->d_zlist,
+                         static_cast<const T*>(zhat), B);
+    else if (nzp <= 16)
+      hipLaunchKernelGGL((k_zdirect<T, 16>), grid, dim3(256), sh, s, W, Lx, Ly, Kz, nzp, nvec, vpb, p->d_zlist,
+                         static_cast<const T*>(zhat), B);
+    else
+      hipLaunchKernelGGL((k_zdirect<T, 32>), grid, dim3(256), sh, s, W, Lx, Ly, Kz, nzp, nvec, vpb, p->d_zlist,
+                         static_cast<const T*>(zhat), B);
+  } else {
     const FftPlan& pl = p->plan[2];
     const int W = cols_per_block(pl.tp, pl.L, sizeof(C));
     const FftPlan ipl = reversed(pl);
@@ -540,7 +623,9 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const int P = nzp * Ky;
     dim3 grid((P + WX - 1) / WX, nvec);
     const size_t sh = (size_t)WX * (Lx + 1) * sizeof(C);
-    const T inv_n = (T)(1.0 / ((double)p->L[0] * p->L[1] * p->L[2]));
+    // the direct z sum uses the z-space kernel, so only the x and y
+    // transforms leave a factor to divide out
+    const T inv_n = (T)(1.0 / ((double)p->L[0] * p->L[1] * (zdirect ? 1.0 : (double)p->L[2])));
     const C* sc = dbl ? reinterpret_cast<const C*>(p->d_sconv64) : reinterpret_cast<const C*>(p->d_sconv32);
     const C* cd = dbl ? reinterpret_cast<const C*>(p->d_cdiag64) : reinterpret_cast<const C*>(p->d_cdiag32);
     hipLaunchKernelGGL(k_pass_xi<T>, grid, dim3(WX * pl.tp), sh, s, pl, WX, Kx, Ky, nzp, K, ep,

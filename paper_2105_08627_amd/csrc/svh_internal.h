@@ -17,6 +17,7 @@ namespace svh {
 constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;  // H/m (mu = mu0, Sec. II.A)
 constexpr int kMaxVecsPerChunk = 256;  // component vectors per pass launch
 constexpr int kMaxStages = 8;
+constexpr int kMaxDirectPlanes = 32;  // direct z sum when at most this many planes are occupied
 
 // Mixed-radix Stockham plan: L = prod r[s], radices in {8, 4, 2, 3}.
 struct FftPlan {
@@ -34,6 +35,7 @@ struct DevTucker {
   int d[3] = {0, 0, 0};
   double* core = nullptr;  // [c][b][a]
   double* F[3] = {nullptr, nullptr, nullptr};  // [k][c]
+  double* Fz = nullptr;  // [dz][c], dz < Kz: inverse z transform of F[2] (z-space factor)
 };
 
 // Per-call kernel parameters of the final (x-inverse) pass.
@@ -74,6 +76,9 @@ struct svh_problem {
   std::vector<double> T;        // Toeplitz tensor, host [Kz][Ky][Kx]
   double* d_zhat64 = nullptr;   // dense spectrum [Lz][Ly][Lx] (real)
   float* d_zhat32 = nullptr;
+  double* d_g64 = nullptr;      // dense z-space kernel [Kz][Ly][Lx] (real)
+  float* d_g32 = nullptr;
+  int zstep = 0;                // SVH_ZSTEP_AUTO / _FFT / _DIRECT
   bool tucker = false;
   svh::DevTucker tk;
   // per-kernel timing: one event set per enqueued chunk while enabled
@@ -87,8 +92,9 @@ namespace svh {
 // device launchers (return hipError_t)
 hipError_t launch_even_spectrum(const svh_problem* p, const double* d_T, double* d_out,
                                 double* d_tmp1, double* d_tmp2, hipStream_t s);
-hipError_t launch_tucker_rebuild(const svh_problem* p, bool fp32_out, void* d_out,
+hipError_t launch_tucker_rebuild(const svh_problem* p, bool fp32_out, bool zspace, void* d_out,
                                  double* d_V, double* d_W, hipStream_t s);
+bool use_zdirect(const svh_problem* p);
 size_t tucker_scratch_doubles(const svh_problem* p);
 hipError_t launch_to_f32(const double* in, float* out, size_t n, hipStream_t s);
 

@@ -116,7 +116,7 @@ hipError_t launch_even_spectrum(const svh_problem* p, const double* d_T, double*
   if (e == hipSuccess) {
     // x: [Kz][Ky][Kx] -> [Kz][Ky][Lx]
     hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, d_T, d_tmp1, Kz * Ky, Kx, Lx, 1, d_cos);
-    // y: [Kz][Ky][Lx] -> [Kz][Ly][Lx]
+    // y: [Kz][Ky][Lx] -> [Kz][Ly][Lx]  (this is the z-space kernel)
     hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, d_tmp1, d_tmp2, Kz, Ky, Ly, Lx,
                        d_cos + Lmax);
     // z: [Kz][Ly][Lx] -> [Lz][Ly][Lx]
@@ -134,8 +134,8 @@ size_t tucker_scratch_doubles(const svh_problem* p) {
   return (size_t)p->L[0] * t.d[1] * t.d[2] + (size_t)p->L[0] * p->L[1] * t.d[2];
 }
 
-hipError_t launch_tucker_rebuild(const svh_problem* p, bool fp32_out, void* d_out, double* d_V, double* d_W,
-                                 hipStream_t s) {
+hipError_t launch_tucker_rebuild(const svh_problem* p, bool fp32_out, bool zspace, void* d_out, double* d_V,
+                                 double* d_W, hipStream_t s) {
   const DevTucker& t = p->tk;
   const int L1 = p->L[0], L2 = p->L[1], L3 = p->L[2];
   const int d1 = t.d[0], d2 = t.d[1], d3 = t.d[2];
@@ -146,8 +146,10 @@ hipError_t launch_tucker_rebuild(const svh_problem* p, bool fp32_out, void* d_ou
   // W[ky][kx][c] = sum_b F2[ky][b] V[kx][c][b]   (batched over kx)
   GemmArgs g2{L2, d3, d2, t.F[1], d2, 1, 0, d_V, 1, d2, (long long)d2 * d3, d_W, (long long)L1 * d3, 1, d3};
   if ((e = gemm(g2, L1, false, s)) != hipSuccess) return e;
-  // Z[kz][ky][kx] = sum_c F3[kz][c] W[ky][kx][c]
-  GemmArgs g3{L3, L1 * L2, d3, t.F[2], d3, 1, 0, d_W, 1, d3, 0, d_out, (long long)L1 * L2, 1, 0};
+  // Z[kz][ky][kx] = sum_c F3[kz][c] W[ky][kx][c]; in z space the third
+  // factor is its inverse z transform and only offsets dz < Kz are restored
+  const int M3 = zspace ? p->K[2] : L3;
+  GemmArgs g3{M3, L1 * L2, d3, zspace ? t.Fz : t.F[2], d3, 1, 0, d_W, 1, d3, 0, d_out, (long long)L1 * L2, 1, 0};
   return gemm(g3, 1, fp32_out, s);
 }
 

@@ -84,11 +84,13 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("zstep", ["fft", "direct"])
 @pytest.mark.parametrize("K,fill,seed", CASES)
-def test_random_masks_multi_rhs(K, fill, seed, dev):
+def test_random_masks_multi_rhs(K, fill, seed, zstep, dev):
     mask = wl.random_mask(seed, *K, fill=fill)
     dx = 0.25e-6
     p = _problem(mask, dx)
+    p.set_zstep(zstep)
     fidx = [0, 1, -1]
     x = wl.random_currents(seed + 1, (3, 3, p.K))
     ref = _oracle(mask, dx, x, fidx)
@@ -96,12 +98,13 @@ def test_random_masks_multi_rhs(K, fill, seed, dev):
     e64 = _relerr(y64, ref)
     y32 = _run(p, x, fidx, dev, torch.complex64)
     e32 = _relerr(y32, ref)
-    print(K, p.L, "fp64", e64, "fp32", e32)
+    print(K, p.L, zstep, "fp64", e64, "fp32", e32)
     assert np.all(e64 <= 1e-12)
     assert np.all(e32 <= 1e-5)
 
 
-def test_empty_planes_pruned(dev):
+@pytest.mark.parametrize("zstep", ["fft", "direct"])
+def test_empty_planes_pruned(dev, zstep):
     """Only z planes 0, 4 and 9 hold voxels; the others are skipped."""
     mask = np.zeros((10, 12, 16), dtype=np.uint8)
     g = np.random.default_rng(3)
@@ -109,6 +112,7 @@ def test_empty_planes_pruned(dev):
         mask[z] = (g.random((12, 16)) < 0.5)
     dx = 0.5e-6
     p = _problem(mask, dx)
+    p.set_zstep(zstep)
     fidx = [0, 1]
     x = wl.random_currents(7, (2, 3, p.K))
     ref = _oracle(mask, dx, x, fidx)
@@ -116,13 +120,15 @@ def test_empty_planes_pruned(dev):
     assert np.all(err <= 1e-12), err
 
 
+@pytest.mark.parametrize("zstep", ["fft", "direct"])
 @pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)])
-def test_tucker_full_rank_matches_exact(dev, dtype, tol):
+def test_tucker_full_rank_matches_exact(dev, dtype, tol, zstep):
     """Untruncated Tucker factors restore the spectrum exactly (eq. 10), so the
     restored-per-matvec product equals the exact operator."""
     mask = wl.random_mask(21, 12, 10, 6, fill=0.7)
     dx = 0.25e-6
     p = _problem(mask, dx)
+    p.set_zstep(zstep)
     ranks, rel = p.tucker_compress(0.0)
     fidx = [0, -1]
     x = wl.random_currents(22, (2, 3, p.K))
@@ -132,19 +138,21 @@ def test_tucker_full_rank_matches_exact(dev, dtype, tol):
     assert np.all(err <= tol)
 
 
+@pytest.mark.parametrize("zstep", ["fft", "direct"])
 @pytest.mark.parametrize("ttol", [1e-4, 1e-6, 1e-8])
-def test_tucker_truncated_error_tracks_tolerance(dev, ttol):
+def test_tucker_truncated_error_tracks_tolerance(dev, ttol, zstep):
     """Truncated factors (Algorithm 1 at tol): the operator error stays at the
     level of the tolerance (bound used: 30 tol), and ranks are compressed."""
     mask = wl.full_box(16, 16, 8)
     dx = 0.25e-6
     p = _problem(mask, dx)
+    p.set_zstep(zstep)
     ranks, rel = p.tucker_compress(ttol)
     fidx = [-1]
     x = wl.random_currents(23, (1, 3, p.K))
     ref = _oracle(mask, dx, x, fidx)
     err = _relerr(_run(p, x, fidx, dev, torch.complex128), ref)
-    print("tucker", ttol, ranks, rel, err)
+    print("tucker", zstep, ttol, ranks, rel, err)
     assert rel <= ttol
     assert max(ranks) < 32
     assert np.all(err <= 30 * ttol)
