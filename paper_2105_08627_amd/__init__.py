@@ -22,7 +22,7 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: 
 EXPORTED = [
     "svh_create", "svh_get_sizes", "svh_set_material", "svh_setup_tensors", "svh_green_toeplitz",
     "svh_get_toeplitz", "svh_tucker_compress", "svh_workspace_bytes", "svh_matvec",
-    "svh_set_zstep", "svh_profile_enable", "svh_profile_read", "svh_last_error", "svh_destroy",
+    "svh_set_zstep", "svh_autotune", "svh_profile_enable", "svh_profile_read", "svh_last_error", "svh_destroy",
 ]
 PROF_NAMES = ["tucker_restore", "pass_x", "pass_y", "pass_z_mul", "pass_yi", "pass_xi"]
 
@@ -54,6 +54,7 @@ def lib():
     L.svh_workspace_bytes.restype = sz
     L.svh_matvec.argtypes = [vp, i32, i32, vp, vp, vp, vp, sz, vp]
     L.svh_set_zstep.argtypes = [vp, i32]
+    L.svh_autotune.argtypes = [vp, i32, i32, vp, vp, vp, vp, sz, vp, vp]
     L.svh_profile_enable.argtypes = [vp, i32]
     L.svh_profile_read.argtypes = [vp, vp, vp]
     L.svh_last_error.argtypes = [vp]
@@ -173,6 +174,20 @@ class Problem:
         """'auto', 'fft' (padded z FFT) or 'direct' (z-space sum over occupied planes)."""
         self._check(lib().svh_set_zstep(self._h, ZSTEP[mode]), "svh_set_zstep")
         self._ws.clear()
+
+    def autotune(self, x, freq_idx, stream=None):
+        """Pick the fastest launch shapes for this batch; returns tuned ms/matvec."""
+        import torch
+        prec = SVH_FP64 if x.dtype == torch.complex128 else SVH_FP32
+        nrhs = x.shape[0]
+        fi = np.ascontiguousarray(np.broadcast_to(np.asarray(freq_idx, dtype=np.int32), (nrhs,)))
+        y = torch.empty_like(x)
+        ws = self.workspace(prec, nrhs, x.device)
+        ms = np.zeros(1)
+        self._check(lib().svh_autotune(self._h, prec, nrhs, _ptr(fi), ctypes.c_void_p(x.data_ptr()),
+                                       ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                       _stream_handle(stream), _ptr(ms)), "svh_autotune")
+        return float(ms[0])
 
     def profile(self, enable=True):
         self._check(lib().svh_profile_enable(self._h, int(enable)), "svh_profile_enable")

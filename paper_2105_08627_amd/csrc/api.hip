@@ -122,6 +122,7 @@ svh_status svh_create(svh_problem** out, int Kx, int Ky, int Kz, double dx_m, in
   p->basis = basis;
   p->C = 3;
   HIPCHK(hipGetDevice(&p->device));
+  HIPCHK(hipDeviceGetAttribute(&p->ncu, hipDeviceAttributeMultiprocessorCount, p->device));
   const size_t Kt = (size_t)Kx * Ky * Kz;
   p->vidx.assign(Kt, -1);
   int n = 0;
@@ -394,6 +395,53 @@ svh_status svh_matvec(svh_problem* p, svh_prec prec, int nrhs, const int32_t* fr
   }
   for (size_t i = 0; i < evs.size(); i += 8)
     p->prof_events.push_back(std::vector<hipEvent_t>(evs.begin() + i, evs.begin() + i + 8));
+  return SVH_OK;
+}
+
+svh_status svh_autotune(svh_problem* p, svh_prec prec, int nrhs, const int32_t* freq_idx, const void* x, void* y,
+                        void* ws, size_t ws_bytes, void* stream, double* ms_out) {
+  if (!p) return SVH_EINVAL;
+  if (prec != SVH_FP64 && prec != SVH_FP32) return fail(p, SVH_EINVAL, "autotune: bad precision");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool was_prof = p->prof;
+  Tune best;
+  double best_ms[4] = {1e30, 1e30, 1e30, 1e30};
+  svh_status st = SVH_OK;
+  p->prof = true;
+  for (int c = 0; c < 4 && st == SVH_OK; ++c) {
+    for (int i = 0; i < 4; ++i) p->tune[prec].grid_mult[i] = kTuneCandidates[c];
+    st = svh_matvec(p, prec, nrhs, freq_idx, x, y, ws, ws_bytes, stream);  // warm-up
+    double ms[SVH_NPROF];
+    int n = 0;
+    if (st == SVH_OK) st = svh_profile_read(p, ms, &n);
+    for (int rep = 0; rep < 2 && st == SVH_OK; ++rep)
+      st = svh_matvec(p, prec, nrhs, freq_idx, x, y, ws, ws_bytes, stream);
+    if (st == SVH_OK) st = svh_profile_read(p, ms, &n);
+    if (st != SVH_OK) break;
+    for (int i = 0; i < 4; ++i) {
+      const double t = ms[1 + (i == 0 ? 0 : i == 1 ? 1 : i == 2 ? 3 : 4)];  // X, Y, Yi, Xi slots
+      if (t < best_ms[i]) {
+        best_ms[i] = t;
+        best.grid_mult[i] = kTuneCandidates[c];
+      }
+    }
+  }
+  p->prof = was_prof;
+  p->tune[prec] = best;
+  if (st != SVH_OK) return st;
+  HIPCHK(hipStreamSynchronize(s));
+  if (ms_out) {
+    double ms[SVH_NPROF];
+    int n = 0;
+    p->prof = true;
+    st = svh_matvec(p, prec, nrhs, freq_idx, x, y, ws, ws_bytes, stream);
+    if (st == SVH_OK) st = svh_profile_read(p, ms, &n);
+    p->prof = was_prof;
+    if (st != SVH_OK) return st;
+    double tot = 0;
+    for (int i = 0; i < SVH_NPROF; ++i) tot += ms[i];
+    *ms_out = tot;
+  }
   return SVH_OK;
 }
 

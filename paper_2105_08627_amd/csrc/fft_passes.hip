@@ -18,6 +18,8 @@
 // Stockham stage with radix R after Ns previous points (natural order out):
 //   in  v_r = src[j + r L/R],  twiddle  v_r *= w_L^(r (j mod Ns) L/(Ns R))
 //   R-point DFT, out dst[(j / Ns) Ns R + (j mod Ns) + r Ns].
+#include <utility>
+
 #include "svh_internal.h"
 
 namespace svh {
@@ -96,14 +98,18 @@ template <int R, int DIR, typename C> __device__ __forceinline__ void dft(C* v) 
 template <int R> struct NbMax { static constexpr int v = R == 8 ? 1 : R == 4 ? 2 : R == 3 ? 3 : 4; };
 
 // LDS accessors.  Strided layout: element (n, w) at n * W + w.  Pencil
-// layout: element (n, w) at w * Lp + n.
+// layout: element (n, w) at w * Lp + n + n / 8 (one pad slot every eight
+// elements keeps the stride-R writes of the first stages off a single bank).
+__host__ __device__ constexpr int pencil_pitch(int L) { return L + L / 8 + 1; }
 template <typename C, bool STRIDED> struct Lds {
   C* base;
   int W, Lp, w;
-  __device__ __forceinline__ C ld(int n) const { return STRIDED ? base[n * W + w] : base[w * Lp + n]; }
+  __device__ __forceinline__ C ld(int n) const {
+    return STRIDED ? base[n * W + w] : base[w * Lp + n + (n >> 3)];
+  }
   __device__ __forceinline__ void st(int n, C v) const {
     if (STRIDED) base[n * W + w] = v;
-    else base[w * Lp + n] = v;
+    else base[w * Lp + n + (n >> 3)] = v;
   }
 };
 
@@ -176,6 +182,166 @@ __device__ __forceinline__ void fft_group(const FftPlan& pl, int j0, const GIn& 
   stage_any<C, DIR, false>(pl.r[pl.ns - 1], L, Ns, j0, TP, lds, gout, tw);
 }
 
+// First stage split into its global loads and the rest (Ns = 1: no twiddles),
+// so that a block can issue the loads of its next item before it runs the
+// LDS stages of the current one.
+template <typename C, int R, class Src>
+__device__ __forceinline__ void load0_r(int L, int j0, int TP, const Src& src, C (&v)[12]) {
+  constexpr int NB = NbMax<R>::v;
+  const int LR = L / R;
+#pragma unroll
+  for (int it = 0; it < NB; ++it) {
+    const int j = j0 + it * TP;
+    if (j < LR) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[it * R + r] = src.ld(j + r * LR);
+    }
+  }
+}
+template <typename C, int R, int DIR, class Dst>
+__device__ __forceinline__ void fin0_r(int L, int j0, int TP, C (&v)[12], const Dst& dst) {
+  constexpr int NB = NbMax<R>::v;
+  const int LR = L / R;
+#pragma unroll
+  for (int it = 0; it < NB; ++it) {
+    const int j = j0 + it * TP;
+    if (j < LR) {
+      dft<R, DIR>(&v[it * R]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst.st(j * R + r, v[it * R + r]);
+    }
+  }
+}
+template <typename C, class Src>
+__device__ __forceinline__ void load0(int R, int L, int j0, int TP, const Src& src, C (&v)[12]) {
+  switch (R) {
+    case 8: load0_r<C, 8>(L, j0, TP, src, v); break;
+    case 4: load0_r<C, 4>(L, j0, TP, src, v); break;
+    case 3: load0_r<C, 3>(L, j0, TP, src, v); break;
+    default: load0_r<C, 2>(L, j0, TP, src, v); break;
+  }
+}
+template <typename C, int DIR, class Dst>
+__device__ __forceinline__ void fin0(int R, int L, int j0, int TP, C (&v)[12], const Dst& dst) {
+  switch (R) {
+    case 8: fin0_r<C, 8, DIR>(L, j0, TP, v, dst); break;
+    case 4: fin0_r<C, 4, DIR>(L, j0, TP, v, dst); break;
+    case 3: fin0_r<C, 3, DIR>(L, j0, TP, v, dst); break;
+    default: fin0_r<C, 2, DIR>(L, j0, TP, v, dst); break;
+  }
+}
+
+// Persistent loop over items (groups of pencils): item i's first-stage loads
+// are issued while item i-1 runs its LDS stages and stores.
+template <typename C, int DIR, bool STRIDED, class MkIn, class MkOut>
+__device__ __forceinline__ void fft_items(const FftPlan& pl, int j0, int nitems, const MkIn& mk_in,
+                                          const MkOut& mk_out, const Lds<C, STRIDED>& lds, const C* tw) {
+  const int L = pl.L, TP = pl.tp;
+  C v[12];
+  int item = blockIdx.x;
+  if (item < nitems) load0(pl.r[0], L, j0, TP, mk_in(item), v);
+  for (; item < nitems; item += gridDim.x) {
+    const int next = item + gridDim.x;
+    if (pl.ns == 1) {
+      fin0<C, DIR>(pl.r[0], L, j0, TP, v, mk_out(item));
+      if (next < nitems) load0(pl.r[0], L, j0, TP, mk_in(next), v);
+      continue;
+    }
+    fin0<C, DIR>(pl.r[0], L, j0, TP, v, lds);
+    __syncthreads();
+    if (next < nitems) load0(pl.r[0], L, j0, TP, mk_in(next), v);
+    int Ns = pl.r[0];
+    for (int s = 1; s < pl.ns - 1; ++s) {
+      stage_any<C, DIR, true>(pl.r[s], L, Ns, j0, TP, lds, lds, tw);
+      Ns *= pl.r[s];
+      __syncthreads();
+    }
+    stage_any<C, DIR, false>(pl.r[pl.ns - 1], L, Ns, j0, TP, lds, mk_out(item), tw);
+    __syncthreads();
+  }
+}
+
+// Compile-time plans for the common lengths: all radices, strides and trip
+// counts are constants, which keeps every stage in registers (the runtime
+// plan above is the fallback for other lengths).
+__host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
+template <int R0, int R1 = 1, int R2 = 1, int R3 = 1>
+struct PlanC {
+  static constexpr bool rt = false;
+  static constexpr int ns = R1 == 1 ? 1 : R2 == 1 ? 2 : R3 == 1 ? 3 : 4;
+  static constexpr int L = R0 * R1 * R2 * R3;
+  static constexpr int r(int s) { return s == 0 ? R0 : s == 1 ? R1 : s == 2 ? R2 : R3; }
+  static constexpr int tp = cmin(cmin(L / R0, R1 > 1 ? L / R1 : L), cmin(R2 > 1 ? L / R2 : L, R3 > 1 ? L / R3 : L));
+  __host__ __device__ static constexpr int Lof(const FftPlan&) { return L; }
+  __host__ __device__ static constexpr int tpof(const FftPlan&) { return tp; }
+};
+struct PlanRT {
+  static constexpr bool rt = true;
+  __host__ __device__ static int Lof(const FftPlan& p) { return p.L; }
+  __host__ __device__ static int tpof(const FftPlan& p) { return p.tp; }
+};
+
+template <class P, typename C, int DIR, bool STRIDED, class MkIn, class MkOut>
+__device__ __forceinline__ void fft_items_c(int j0, int nitems, const MkIn& mk_in, const MkOut& mk_out,
+                                            const Lds<C, STRIDED>& lds, const C* tw) {
+  constexpr int L = P::L, TP = P::tp;
+  constexpr int R0 = P::r(0);
+  C v[12];
+  int item = blockIdx.x;
+  if (item < nitems) load0_r<C, R0>(L, j0, TP, mk_in(item), v);
+  for (; item < nitems; item += gridDim.x) {
+    const int next = item + gridDim.x;
+    if constexpr (P::ns == 1) {
+      fin0_r<C, R0, DIR>(L, j0, TP, v, mk_out(item));
+      if (next < nitems) load0_r<C, R0>(L, j0, TP, mk_in(next), v);
+    } else {
+      fin0_r<C, R0, DIR>(L, j0, TP, v, lds);
+      __syncthreads();
+      if (next < nitems) load0_r<C, R0>(L, j0, TP, mk_in(next), v);
+      constexpr int N1 = R0;
+      if constexpr (P::ns == 2) {
+        stage_r<C, P::r(1), DIR, false>(L, N1, j0, TP, lds, mk_out(item), tw);
+      } else {
+        stage_r<C, P::r(1), DIR, true>(L, N1, j0, TP, lds, lds, tw);
+        __syncthreads();
+        constexpr int N2 = N1 * P::r(1);
+        if constexpr (P::ns == 3) {
+          stage_r<C, P::r(2), DIR, false>(L, N2, j0, TP, lds, mk_out(item), tw);
+        } else {
+          stage_r<C, P::r(2), DIR, true>(L, N2, j0, TP, lds, lds, tw);
+          __syncthreads();
+          constexpr int N3 = N2 * P::r(2);
+          stage_r<C, P::r(3), DIR, false>(L, N3, j0, TP, lds, mk_out(item), tw);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <class P, typename C, int DIR, bool STRIDED, class MkIn, class MkOut>
+__device__ __forceinline__ void run_items(const FftPlan& pl, int j0, int nitems, const MkIn& mk_in,
+                                          const MkOut& mk_out, const Lds<C, STRIDED>& lds, const C* tw) {
+  if constexpr (P::rt) fft_items<C, DIR, STRIDED>(pl, j0, nitems, mk_in, mk_out, lds, tw);
+  else fft_items_c<P, C, DIR, STRIDED>(j0, nitems, mk_in, mk_out, lds, tw);
+}
+
+// Calls f(PlanC<...>{}) for the lengths with a compile-time plan, else f(PlanRT{}).
+template <class F>
+void with_plan(int L, F&& f) {
+  switch (L) {
+    case 16: f(PlanC<4, 4>{}); break;
+    case 32: f(PlanC<8, 4>{}); break;
+    case 64: f(PlanC<8, 8>{}); break;
+    case 128: f(PlanC<8, 4, 4>{}); break;
+    case 192: f(PlanC<8, 8, 3>{}); break;
+    case 256: f(PlanC<8, 8, 4>{}); break;
+    case 512: f(PlanC<8, 8, 8>{}); break;
+    case 1024: f(PlanC<8, 8, 4, 4>{}); break;
+    default: f(PlanRT{}); break;
+  }
+}
+
 // ----------------------------------------------------------------- X pass --
 template <typename C> struct XIn {
   const C* __restrict__ x;       // compact vector of this component
@@ -197,8 +363,8 @@ template <typename C> struct RowOut {
   }
 };
 
-template <typename T>
-__global__ void __launch_bounds__(1024) k_pass_x(FftPlan pl, int WX, int Kx, int Ky, int nzp, int K,
+template <typename T, class P>
+__global__ void __launch_bounds__(256) k_pass_x(FftPlan pl, int WX, int Kx, int Ky, int nzp, int K, int nvec,
                                                  const int32_t* __restrict__ zlist,
                                                  const int32_t* __restrict__ vidx,
                                                  const typename CT<T>::t* __restrict__ x,
@@ -208,19 +374,34 @@ __global__ void __launch_bounds__(1024) k_pass_x(FftPlan pl, int WX, int Kx, int
   extern __shared__ unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   const int t = threadIdx.x;
-  const int j0 = t % pl.tp, w = t / pl.tp;
-  const int vec = blockIdx.y;
-  const int P = nzp * Ky;
-  const int pen = blockIdx.x * WX + w;
-  const bool valid = pen < P;
-  const int pc = valid ? pen : 0;
-  const int y = pc % Ky, zp = pc / Ky;
-  const int z = zlist[zp];
-  const int Lx = pl.L;
-  XIn<C> gin{x + (size_t)vec * K, vidx + ((size_t)z * Ky + y) * Kx, Kx, valid};
-  RowOut<C> gout{A + (((size_t)vec * nzp + zp) * Ky + y) * Lx, Lx, valid};
-  Lds<C, false> acc{lds, WX, Lx + 1, w};
-  fft_group<C, -1, false>(pl, j0, gin, gout, acc, tw);
+  const int TPP = P::tpof(pl);
+  const int j0 = t % TPP, w = t / TPP;
+  const int NP = nzp * Ky;
+  const int ngrp = (NP + WX - 1) / WX;
+  const int Lx = P::Lof(pl);
+  // item = vec * ngrp + pencil group
+  auto where = [&](int item, int& vec, int& y, int& zp, bool& valid) {
+    vec = item / ngrp;
+    const int pen = (item % ngrp) * WX + w;
+    valid = pen < NP;
+    const int pc = valid ? pen : 0;
+    y = pc % Ky;
+    zp = pc / Ky;
+  };
+  auto mk_in = [&](int item) {
+    int vec, y, zp;
+    bool valid;
+    where(item, vec, y, zp, valid);
+    return XIn<C>{x + (size_t)vec * K, vidx + ((size_t)zlist[zp] * Ky + y) * Kx, Kx, valid};
+  };
+  auto mk_out = [&](int item) {
+    int vec, y, zp;
+    bool valid;
+    where(item, vec, y, zp, valid);
+    return RowOut<C>{A + (((size_t)vec * nzp + zp) * Ky + y) * Lx, Lx, valid};
+  };
+  Lds<C, false> acc{lds, WX, pencil_pitch(Lx), w};
+  run_items<P, C, -1, false>(pl, j0, ngrp * nvec, mk_in, mk_out, acc, tw);
 }
 
 // ------------------------------------------------------------ Y passes ----
@@ -243,8 +424,12 @@ template <typename C> struct ColOut {
 
 // DIR = -1: A[vec][zp][y < Ky][kx] -> B[vec][zp][ky < Ly][kx]
 // DIR = +1: B -> A (crop to y < Ky)
-template <typename T, int DIR>
-__global__ void __launch_bounds__(1024) k_pass_y(FftPlan pl, int W, int Lx, int Ky, int nzp,
+// Block size limit: 1024 threads for FP32, 512 for FP64 (which leaves 256
+// VGPRs per lane for the double-width butterflies).
+template <typename T> struct MaxThreads { static constexpr int v = sizeof(T) == 8 ? 512 : 1024; };
+
+template <typename T, int DIR, class P>
+__global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_y(FftPlan pl, int W, int Lx, int Ky, int nzp, int nvec,
                                                  const typename CT<T>::t* __restrict__ in,
                                                  typename CT<T>::t* __restrict__ out,
                                                  const typename CT<T>::t* __restrict__ tw) {
@@ -253,21 +438,30 @@ __global__ void __launch_bounds__(1024) k_pass_y(FftPlan pl, int W, int Lx, int 
   C* lds = reinterpret_cast<C*>(smem_raw);
   const int t = threadIdx.x;
   const int w = t % W, j0 = t / W;
-  const int vec = blockIdx.y;
   const int ntile = (Lx + W - 1) / W;
-  const int tile = blockIdx.x % ntile, zp = blockIdx.x / ntile;
-  const int kx = tile * W + w;
-  const bool valid = kx < Lx;
-  const int kxc = valid ? kx : 0;
-  const int Ly = pl.L;
+  const int Ly = P::Lof(pl);
   const int rows_in = DIR < 0 ? Ky : Ly;
   const int rows_out = DIR < 0 ? Ly : Ky;
-  const C* ib = in + ((size_t)vec * nzp + zp) * rows_in * Lx + kxc;
-  C* ob = out + ((size_t)vec * nzp + zp) * rows_out * Lx + kxc;
-  ColIn<C> gin{ib, Lx, DIR < 0 ? Ky : Ly, valid};
-  ColOut<C> gout{ob, Lx, DIR < 0 ? Ly : Ky, valid};
+  // item = (vec * nzp + zp) * ntile + tile
+  auto col = [&](int item, bool& valid) {
+    const int tile = item % ntile;
+    const int vz = item / ntile;  // vec * nzp + zp
+    const int kx = tile * W + w;
+    valid = kx < Lx;
+    return std::make_pair((size_t)vz, valid ? kx : 0);
+  };
+  auto mk_in = [&](int item) {
+    bool valid;
+    const auto c = col(item, valid);
+    return ColIn<C>{in + c.first * rows_in * Lx + c.second, Lx, rows_in, valid};
+  };
+  auto mk_out = [&](int item) {
+    bool valid;
+    const auto c = col(item, valid);
+    return ColOut<C>{out + c.first * rows_out * Lx + c.second, Lx, rows_out, valid};
+  };
   Lds<C, true> acc{lds, W, 0, w};
-  fft_group<C, DIR, true>(pl, j0, gin, gout, acc, tw);
+  run_items<P, C, DIR, true>(pl, j0, ntile * nzp * nvec, mk_in, mk_out, acc, tw);
 }
 
 // ---------------------------------------------------------------- Z pass --
@@ -340,7 +534,7 @@ __device__ __forceinline__ void fused_mul(int R, int L, int j0, int TP, const Sr
 }
 
 template <typename T>
-__global__ void __launch_bounds__(1024) k_pass_z(FftPlan pl, FftPlan ipl, int W, int Lx, int Ly, int nzp,
+__global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_z(FftPlan pl, FftPlan ipl, int W, int Lx, int Ly, int nzp,
                                                  int nvec, int vpb, const int32_t* __restrict__ zslot,
                                                  const T* __restrict__ zhat,
                                                  typename CT<T>::t* __restrict__ B,
@@ -414,53 +608,89 @@ __global__ void __launch_bounds__(1024) k_pass_z(FftPlan pl, FftPlan ipl, int W,
 // circulant spectrum (real and even in the offset because the spectrum is
 // real and even).  Exact for any plane set; used when few planes are occupied
 // (the padded z FFT then spends almost all of its work on zeros).
-// Block: W adjacent kx of one ky; thread (w, lane) owns pencil w for the
-// vectors lane, lane + nlanes, ...: it holds all of one vector's z values in
-// registers, so the in-place update needs no barrier.
-template <typename T, int NZ>
-__global__ void __launch_bounds__(256) k_zdirect(int W, int Lx, int Ly, int Kz, int nzp, int nvec, int vpb,
+// Block: W adjacent kx of one ky, RG row groups (W * RG = 256 threads).
+// Thread (w, rg) keeps rows rg, rg + RG, ... of its pencil's nzp x nzp matrix
+// in registers for all vectors; each chunk of V vectors is staged through
+// LDS with 128/256-byte coalesced loads and updated in place.
+template <typename T, int NZ, int RG, int V>
+__global__ void __launch_bounds__(256) k_zdirect(int Lx, int Ly, int nzp, int nvec, int vpb,
                                                  const int32_t* __restrict__ zlist,
                                                  const T* __restrict__ g,
                                                  typename CT<T>::t* __restrict__ B) {
   typedef typename CT<T>::t C;
+  constexpr int W = 256 / RG;
+  constexpr int R = (NZ + RG - 1) / RG;
   extern __shared__ unsigned char smem_raw[];
-  T* gs = reinterpret_cast<T*>(smem_raw);            // [Kz][W]
-  int* zl = reinterpret_cast<int*>(gs + (size_t)Kz * W);
+  C* xs = reinterpret_cast<C*>(smem_raw);                    // [V][NZ][W]
+  int* zl = reinterpret_cast<int*>(xs + (size_t)V * NZ * W); // [NZ]
   const int t = threadIdx.x;
   const int ntile = (Lx + W - 1) / W;
   const int tile = blockIdx.x % ntile, ky = blockIdx.x / ntile;
-  for (int i = t; i < Kz * W; i += blockDim.x) {
-    const int dz = i / W, w = i % W, kx = tile * W + w;
-    gs[i] = kx < Lx ? g[((size_t)dz * Ly + ky) * Lx + kx] : (T)0;
-  }
-  for (int i = t; i < nzp; i += blockDim.x) zl[i] = zlist[i];
+  const int kx0 = tile * W;
+  for (int i = t; i < NZ; i += 256) zl[i] = i < nzp ? zlist[i] : 0;
   __syncthreads();
-  const int w = t % W, lane = t / W, nl = blockDim.x / W;
-  const int kx = tile * W + w;
-  if (kx >= Lx) return;
+  const int w = t % W, rg = t / W;
+  const int kx = kx0 + w;
+  const bool valid = kx < Lx;
+  // rows of this pencil's z matrix, read once per block (x-adjacent lanes)
+  T m[R][NZ];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = rg + r * RG;
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) {
+      int d = zl[i < NZ ? i : 0] - zl[j];
+      d = d < 0 ? -d : d;
+      m[r][j] = (valid && i < nzp && j < nzp) ? g[((size_t)d * Ly + ky) * Lx + kx] : (T)0;
+    }
+  }
   const size_t plane = (size_t)Ly * Lx;
-  const int v0 = blockIdx.y * vpb, v1 = min(nvec, v0 + vpb);
-  for (int vec = v0 + lane; vec < v1; vec += nl) {
-    C* base = B + (size_t)vec * nzp * plane + (size_t)ky * Lx + kx;
-    C xv[NZ];
+  C* base = B + (size_t)ky * Lx + kx0;
+  const int vbeg = blockIdx.y * vpb;
+  const int vend = min(nvec, vbeg + vpb);
+  // staged element e of a chunk: ww = e % W, j = (e / W) % NZ, v = e / (W NZ);
+  // thread t stages e = t + 256 q, q < EPT
+  constexpr int EPT = (V * NZ * W + 255) / 256;
+  C pre[EPT];
+  auto fetch = [&](int v0) {
+    const int nv = min(V, vend - v0);
 #pragma unroll
-    for (int j = 0; j < NZ; ++j)
-      if (j < nzp) xv[j] = base[(size_t)j * plane];
+    for (int q = 0; q < EPT; ++q) {
+      const int e = t + 256 * q;
+      const int ww = e % W, j = (e / W) % NZ, v = e / (W * NZ);
+      pre[q] = (v < nv && j < nzp && kx0 + ww < Lx) ? base[((size_t)(v0 + v) * nzp + j) * plane + ww] : C{0, 0};
+    }
+  };
+  if (vbeg < vend) fetch(vbeg);
+  for (int v0 = vbeg; v0 < vend; v0 += V) {
+    const int nv = min(V, vend - v0);
+    __syncthreads();  // previous chunk's readers are done with xs
 #pragma unroll
-    for (int i = 0; i < NZ; ++i) {
-      if (i >= nzp) break;
-      const int zi = zl[i];
-      T ar = 0, ai = 0;
+    for (int q = 0; q < EPT; ++q) {
+      const int e = t + 256 * q;
+      if (e < V * NZ * W) xs[e] = pre[q];
+    }
+    __syncthreads();
+    if (v0 + V < vend) fetch(v0 + V);  // next chunk in flight during the sums
+    for (int v = 0; v < nv; ++v) {
+      T ar[R], ai[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) ar[r] = ai[r] = 0;
+      const C* xv = xs + (size_t)v * NZ * W + w;
 #pragma unroll
       for (int j = 0; j < NZ; ++j) {
-        if (j < nzp) {
-          const int d = zi - zl[j];
-          const T gv = gs[(d < 0 ? -d : d) * W + w];
-          ar += gv * xv[j].x;
-          ai += gv * xv[j].y;
+        const C xj = xv[j * W];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          ar[r] += m[r][j] * xj.x;
+          ai[r] += m[r][j] * xj.y;
         }
       }
-      base[(size_t)i * plane] = C{ar, ai};
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = rg + r * RG;
+        if (i < nzp && valid) base[((size_t)(v0 + v) * nzp + i) * plane + w] = C{ar[r], ai[r]};
+      }
     }
   }
 }
@@ -484,8 +714,8 @@ template <typename C, typename T> struct XOut {
   }
 };
 
-template <typename T>
-__global__ void __launch_bounds__(1024) k_pass_xi(FftPlan pl, int WX, int Kx, int Ky, int nzp, int K,
+template <typename T, class P>
+__global__ void __launch_bounds__(256) k_pass_xi(FftPlan pl, int WX, int Kx, int Ky, int nzp, int K, int nvec,
                                                   EpiParams ep, const int32_t* __restrict__ zlist,
                                                   const int32_t* __restrict__ vidx,
                                                   const typename CT<T>::t* __restrict__ A,
@@ -499,26 +729,50 @@ __global__ void __launch_bounds__(1024) k_pass_xi(FftPlan pl, int WX, int Kx, in
   extern __shared__ unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   const int t = threadIdx.x;
-  const int j0 = t % pl.tp, w = t / pl.tp;
-  const int vec = blockIdx.y;
-  const int P = nzp * Ky;
-  const int pen = blockIdx.x * WX + w;
-  const bool valid = pen < P;
-  const int pc = valid ? pen : 0;
-  const int yy = pc % Ky, zp = pc / Ky;
-  const int z = zlist[zp];
-  const int Lx = pl.L;
-  const int f = ep.fidx[vec / ep.C];
-  C scale = f >= 0 ? cscale(sconv[f], inv_n) : C{inv_n, 0};
-  const C* cd = f >= 0 ? cdiag + (size_t)f * K : nullptr;
-  ColIn<C> gin{A + (((size_t)vec * nzp + zp) * Ky + yy) * Lx, 1, Lx, valid};
-  XOut<C, T> gout{y + (size_t)vec * K, x + (size_t)vec * K, cd, vidx + ((size_t)z * Ky + yy) * Kx,
-                  scale, Kx, valid};
-  Lds<C, false> acc{lds, WX, Lx + 1, w};
-  fft_group<C, +1, false>(pl, j0, gin, gout, acc, tw);
+  const int TPP = P::tpof(pl);
+  const int j0 = t % TPP, w = t / TPP;
+  const int NP = nzp * Ky;
+  const int ngrp = (NP + WX - 1) / WX;
+  const int Lx = P::Lof(pl);
+  auto where = [&](int item, int& vec, int& yy, int& zp, bool& valid) {
+    vec = item / ngrp;
+    const int pen = (item % ngrp) * WX + w;
+    valid = pen < NP;
+    const int pc = valid ? pen : 0;
+    yy = pc % Ky;
+    zp = pc / Ky;
+  };
+  auto mk_in = [&](int item) {
+    int vec, yy, zp;
+    bool valid;
+    where(item, vec, yy, zp, valid);
+    return ColIn<C>{A + (((size_t)vec * nzp + zp) * Ky + yy) * Lx, 1, Lx, valid};
+  };
+  auto mk_out = [&](int item) {
+    int vec, yy, zp;
+    bool valid;
+    where(item, vec, yy, zp, valid);
+    const int f = ep.fidx[vec / ep.C];
+    const C scale = f >= 0 ? cscale(sconv[f], inv_n) : C{inv_n, 0};
+    const C* cd = f >= 0 ? cdiag + (size_t)f * K : nullptr;
+    return XOut<C, T>{y + (size_t)vec * K, x + (size_t)vec * K, cd, vidx + ((size_t)zlist[zp] * Ky + yy) * Kx,
+                      scale, Kx, valid};
+  };
+  Lds<C, false> acc{lds, WX, pencil_pitch(Lx), w};
+  run_items<P, C, +1, false>(pl, j0, ngrp * nvec, mk_in, mk_out, acc, tw);
 }
 
 // ------------------------------------------------------------- launcher ---
+// Blocks of a persistent launch: as many as can be resident at once.
+static int persistent_grid(const void* kernel, int threads, size_t shmem, int nitems, int ncu, int mult) {
+  if (mult <= 0) return nitems;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, shmem) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  const long long g = (long long)per_cu * ncu * mult;
+  return (int)(g < nitems ? g : nitems);
+}
+
 bool use_zdirect(const svh_problem* p) {
   const int nzp = (int)p->zlist.size();
   if (p->zstep == SVH_ZSTEP_FFT) return false;
@@ -535,7 +789,8 @@ static int pencils_per_block_x(int tp) {
 // elements when possible, within 1024 threads and 64 KiB of LDS.
 static int cols_per_block(int tp, int L, size_t csize) {
   int W = csize == 16 ? 8 : 16;
-  while (W > 1 && (W * tp > 1024 || (size_t)W * L * csize > 65536)) W /= 2;
+  const int maxt = csize == 16 ? 512 : 1024;
+  while (W > 1 && (W * tp > maxt || (size_t)W * L * csize > 65536)) W /= 2;
   return W;
 }
 
@@ -556,46 +811,60 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
   const int Lx = p->L[0], Ly = p->L[1];
   const int nzp = (int)p->zlist.size();
   const int K = p->nvox;
+  const Tune& tn = p->tune[dbl ? SVH_FP64 : SVH_FP32];
   if (ev) hipEventRecord(ev[0], s);
   // X
-  {
+  with_plan(Lx, [&](auto tag) {
+    using P = decltype(tag);
     const FftPlan& pl = p->plan[0];
-    const int WX = pencils_per_block_x(pl.tp);
-    const int P = nzp * Ky;
-    dim3 grid((P + WX - 1) / WX, nvec);
-    const size_t sh = (size_t)WX * (Lx + 1) * sizeof(C);
-    hipLaunchKernelGGL(k_pass_x<T>, grid, dim3(WX * pl.tp), sh, s, pl, WX, Kx, Ky, nzp, K, p->d_zlist,
-                       p->d_vidx, x, A, tw[0]);
-  }
+    const int tp = P::tpof(pl);
+    const int WX = pencils_per_block_x(tp);
+    const int NP = nzp * Ky;
+    const int nitems = ((NP + WX - 1) / WX) * nvec;
+    const size_t sh = (size_t)WX * pencil_pitch(Lx) * sizeof(C);
+    const int g = persistent_grid((const void*)k_pass_x<T, P>, WX * tp, sh, nitems, p->ncu, tn.grid_mult[0]);
+    hipLaunchKernelGGL((k_pass_x<T, P>), dim3(g), dim3(WX * tp), sh, s, pl, WX, Kx, Ky, nzp, K, nvec,
+                       p->d_zlist, p->d_vidx, x, A, tw[0]);
+  });
   if (ev) hipEventRecord(ev[1], s);
   // Y forward
-  {
+  with_plan(Ly, [&](auto tag) {
+    using P = decltype(tag);
     const FftPlan& pl = p->plan[1];
-    const int W = cols_per_block(pl.tp, pl.L, sizeof(C));
-    dim3 grid(((Lx + W - 1) / W) * nzp, nvec);
+    const int tp = P::tpof(pl);
+    const int W = cols_per_block(tp, Ly, sizeof(C));
+    const int nitems = ((Lx + W - 1) / W) * nzp * nvec;
     const size_t sh = (size_t)W * Ly * sizeof(C);
-    hipLaunchKernelGGL((k_pass_y<T, -1>), grid, dim3(W * pl.tp), sh, s, pl, W, Lx, Ky, nzp, A, B, tw[1]);
-  }
+    const int g = persistent_grid((const void*)k_pass_y<T, -1, P>, W * tp, sh, nitems, p->ncu, tn.grid_mult[1]);
+    hipLaunchKernelGGL((k_pass_y<T, -1, P>), dim3(g), dim3(W * tp), sh, s, pl, W, Lx, Ky, nzp, nvec, A, B,
+                       tw[1]);
+  });
   if (ev) hipEventRecord(ev[2], s);
   // Z step: padded FFT along z with the spectrum product, or the direct sum
   const bool zdirect = use_zdirect(p);
   if (zdirect) {
-    int W = dbl ? 16 : 32;
-    while (W > 1 && (size_t)p->K[2] * W * sizeof(T) + (size_t)nzp * sizeof(int) > 65536) W /= 2;
-    const int nl = 256 / W;
-    const int vpb = nvec <= nl * 8 ? nvec : nl * 8;
-    dim3 grid(((Lx + W - 1) / W) * Ly, (nvec + vpb - 1) / vpb);
-    const size_t sh = (size_t)p->K[2] * W * sizeof(T) + (size_t)nzp * sizeof(int);
-    const int Kz = p->K[2];
-    if (nzp <= 8)
-      hipLaunchKernelGGL((k_zdirect<T, 8>), grid, dim3(256), sh, s, W, Lx, Ly, Kz, nzp, nvec, vpb, p->d_zlist,
-                         static_cast<const T*>(zhat), B);
-    else if (nzp <= 16)
-      hipLaunchKernelGGL((k_zdirect<T, 16>), grid, dim3(256), sh, s, W, Lx, Ly, Kz, nzp, nvec, vpb, p->d_zlist,
-                         static_cast<const T*>(zhat), B);
-    else
-      hipLaunchKernelGGL((k_zdirect<T, 32>), grid, dim3(256), sh, s, W, Lx, Ly, Kz, nzp, nvec, vpb, p->d_zlist,
-                         static_cast<const T*>(zhat), B);
+    // double: 16 pencils x 16 row groups; float: 32 pencils x 8 row groups
+    constexpr int RG = sizeof(T) == 8 ? 16 : 8;
+    constexpr int W = 256 / RG;
+    constexpr int V = 4;
+    const int ntile = (Lx + W - 1) / W;
+    const int nblk = ntile * Ly;
+    int vpb = nvec;
+    while (vpb > V && (long long)nblk * ((nvec + vpb - 1) / vpb) < 4096) vpb = (vpb + 1) / 2;
+    dim3 grid(nblk, (nvec + vpb - 1) / vpb);
+    const int NZ = nzp <= 8 ? 8 : nzp <= 16 ? 16 : nzp <= 24 ? 24 : 32;
+    const size_t sh = (size_t)V * NZ * W * sizeof(C) + (size_t)NZ * sizeof(int);
+    const T* gk = static_cast<const T*>(zhat);
+    switch (NZ) {
+      case 8: hipLaunchKernelGGL((k_zdirect<T, 8, RG, V>), grid, dim3(256), sh, s, Lx, Ly, nzp, nvec, vpb,
+                                 p->d_zlist, gk, B); break;
+      case 16: hipLaunchKernelGGL((k_zdirect<T, 16, RG, V>), grid, dim3(256), sh, s, Lx, Ly, nzp, nvec, vpb,
+                                  p->d_zlist, gk, B); break;
+      case 24: hipLaunchKernelGGL((k_zdirect<T, 24, RG, V>), grid, dim3(256), sh, s, Lx, Ly, nzp, nvec, vpb,
+                                  p->d_zlist, gk, B); break;
+      default: hipLaunchKernelGGL((k_zdirect<T, 32, RG, V>), grid, dim3(256), sh, s, Lx, Ly, nzp, nvec, vpb,
+                                  p->d_zlist, gk, B); break;
+    }
   } else {
     const FftPlan& pl = p->plan[2];
     const int W = cols_per_block(pl.tp, pl.L, sizeof(C));
@@ -608,29 +877,36 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
   }
   if (ev) hipEventRecord(ev[3], s);
   // Y inverse
-  {
+  with_plan(Ly, [&](auto tag) {
+    using P = decltype(tag);
     const FftPlan& pl = p->plan[1];
-    const int W = cols_per_block(pl.tp, pl.L, sizeof(C));
-    dim3 grid(((Lx + W - 1) / W) * nzp, nvec);
+    const int tp = P::tpof(pl);
+    const int W = cols_per_block(tp, Ly, sizeof(C));
+    const int nitems = ((Lx + W - 1) / W) * nzp * nvec;
     const size_t sh = (size_t)W * Ly * sizeof(C);
-    hipLaunchKernelGGL((k_pass_y<T, +1>), grid, dim3(W * pl.tp), sh, s, pl, W, Lx, Ky, nzp, B, A, tw[1]);
-  }
+    const int g = persistent_grid((const void*)k_pass_y<T, +1, P>, W * tp, sh, nitems, p->ncu, tn.grid_mult[2]);
+    hipLaunchKernelGGL((k_pass_y<T, +1, P>), dim3(g), dim3(W * tp), sh, s, pl, W, Lx, Ky, nzp, nvec, B, A,
+                       tw[1]);
+  });
   if (ev) hipEventRecord(ev[4], s);
   // X inverse + epilogue
-  {
+  with_plan(Lx, [&](auto tag) {
+    using P = decltype(tag);
     const FftPlan& pl = p->plan[0];
-    const int WX = pencils_per_block_x(pl.tp);
-    const int P = nzp * Ky;
-    dim3 grid((P + WX - 1) / WX, nvec);
-    const size_t sh = (size_t)WX * (Lx + 1) * sizeof(C);
+    const int tp = P::tpof(pl);
+    const int WX = pencils_per_block_x(tp);
+    const int NP = nzp * Ky;
+    const int nitems = ((NP + WX - 1) / WX) * nvec;
+    const size_t sh = (size_t)WX * pencil_pitch(Lx) * sizeof(C);
+    const int g = persistent_grid((const void*)k_pass_xi<T, P>, WX * tp, sh, nitems, p->ncu, tn.grid_mult[3]);
     // the direct z sum uses the z-space kernel, so only the x and y
     // transforms leave a factor to divide out
     const T inv_n = (T)(1.0 / ((double)p->L[0] * p->L[1] * (zdirect ? 1.0 : (double)p->L[2])));
     const C* sc = dbl ? reinterpret_cast<const C*>(p->d_sconv64) : reinterpret_cast<const C*>(p->d_sconv32);
     const C* cd = dbl ? reinterpret_cast<const C*>(p->d_cdiag64) : reinterpret_cast<const C*>(p->d_cdiag32);
-    hipLaunchKernelGGL(k_pass_xi<T>, grid, dim3(WX * pl.tp), sh, s, pl, WX, Kx, Ky, nzp, K, ep,
+    hipLaunchKernelGGL((k_pass_xi<T, P>), dim3(g), dim3(WX * tp), sh, s, pl, WX, Kx, Ky, nzp, K, nvec, ep,
                        p->d_zlist, p->d_vidx, A, x, y, sc, cd, inv_n, tw[0]);
-  }
+  });
   if (ev) hipEventRecord(ev[5], s);
   return hipGetLastError();
 }

@@ -46,6 +46,14 @@ struct EpiParams {
   int fidx[kMaxVecsPerChunk];  // frequency slot per RHS of the chunk (-1 = bare)
 };
 
+// Launch choices of the FFT passes, picked by svh_autotune per precision.
+// grid_mult[i] for pass i in {X, Y, Yi, Xi}: the persistent launch uses
+// (resident blocks per CU x CUs x grid_mult) blocks; 0 = one block per item.
+constexpr int kTuneCandidates[4] = {1, 2, 4, 0};
+struct Tune {
+  int grid_mult[4] = {1, 1, 1, 1};
+};
+
 }  // namespace svh
 
 struct svh_problem {
@@ -56,6 +64,7 @@ struct svh_problem {
   int C = 3;
   int nvox = 0;
   int device = 0;
+  int ncu = 256;  // compute units of the device
   std::vector<int32_t> vidx;       // dense -> compact index or -1, [z][y][x]
   std::vector<int32_t> zlist;      // occupied z planes
   std::vector<int32_t> zslot;      // z -> plane slot or -1 (size L[2])
@@ -79,6 +88,7 @@ struct svh_problem {
   double* d_g64 = nullptr;      // dense z-space kernel [Kz][Ly][Lx] (real)
   float* d_g32 = nullptr;
   int zstep = 0;                // SVH_ZSTEP_AUTO / _FFT / _DIRECT
+  svh::Tune tune[2];            // per precision (SVH_FP64, SVH_FP32)
   bool tucker = false;
   svh::DevTucker tk;
   // per-kernel timing: one event set per enqueued chunk while enabled

@@ -174,3 +174,19 @@ def test_repeat_calls_are_deterministic(dev):
     y1 = p.matvec(x, [0, 1, 0, -1]).cpu()
     y2 = p.matvec(x, [0, 1, 0, -1]).cpu()
     assert torch.equal(y1, y2)
+
+
+def test_autotuned_launch_shapes_keep_parity(dev):
+    """The autotuner only changes launch shapes: results stay at oracle parity."""
+    mask = wl.random_mask(41, 24, 20, 6, fill=0.6)
+    dx = 0.25e-6
+    p = _problem(mask, dx)
+    fidx = [0, 1, 0, -1]
+    x = wl.random_currents(42, (4, 3, p.K))
+    ref = _oracle(mask, dx, x, fidx)
+    for dtype, tol in [(torch.complex128, 1e-12), (torch.complex64, 1e-5)]:
+        xt = torch.from_numpy(x).to(dev).to(dtype)
+        ms = p.autotune(xt, fidx)
+        assert ms > 0
+        err = _relerr(_run(p, x, fidx, dev, dtype), ref)
+        assert np.all(err <= tol), err
