@@ -94,7 +94,8 @@ void free_tucker(svh_problem* p) {
 
 size_t vec_bytes_AB(const svh_problem* p, size_t csize) {
   const size_t nzp = p->zlist.size();
-  return nzp * ((size_t)p->K[1] + p->L[1]) * p->L[0] * csize;
+  const Geo g = make_geo(p, csize);
+  return nzp * (size_t)(g.pa + g.pb) * csize;
 }
 
 int chunk_rhs(const svh_problem* p, int nrhs) {
@@ -336,8 +337,9 @@ svh_status svh_matvec(svh_problem* p, svh_prec prec, int nrhs, const int32_t* fr
   auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
   const int cr = chunk_rhs(p, nrhs);
   const size_t nzp = p->zlist.size();
-  const size_t Abytes = align((size_t)cr * p->C * nzp * p->K[1] * p->L[0] * cs);
-  const size_t Bbytes = (size_t)cr * p->C * nzp * p->L[1] * p->L[0] * cs;
+  const Geo geo = make_geo(p, cs);
+  const size_t Abytes = align((size_t)cr * p->C * nzp * geo.pa * cs);
+  const size_t Bbytes = (size_t)cr * p->C * nzp * geo.pb * cs;
   char* A = w;
   char* B = w + Abytes;
   const bool zdirect = use_zdirect(p);

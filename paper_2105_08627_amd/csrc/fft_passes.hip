@@ -364,7 +364,7 @@ template <typename C> struct RowOut {
 };
 
 template <typename T, class P>
-__global__ void __launch_bounds__(256) k_pass_x(FftPlan pl, int WX, int Kx, int Ky, int nzp, int K, int nvec,
+__global__ void __launch_bounds__(256) k_pass_x(FftPlan pl, Geo geo, int WX, int Kx, int Ky, int nzp, int K, int nvec,
                                                  const int32_t* __restrict__ zlist,
                                                  const int32_t* __restrict__ vidx,
                                                  const typename CT<T>::t* __restrict__ x,
@@ -398,7 +398,7 @@ __global__ void __launch_bounds__(256) k_pass_x(FftPlan pl, int WX, int Kx, int 
     int vec, y, zp;
     bool valid;
     where(item, vec, y, zp, valid);
-    return RowOut<C>{A + (((size_t)vec * nzp + zp) * Ky + y) * Lx, Lx, valid};
+    return RowOut<C>{A + ((size_t)vec * nzp + zp) * geo.pa + (size_t)y * geo.rp, Lx, valid};
   };
   Lds<C, false> acc{lds, WX, pencil_pitch(Lx), w};
   run_items<P, C, -1, false>(pl, j0, ngrp * nvec, mk_in, mk_out, acc, tw);
@@ -429,7 +429,7 @@ template <typename C> struct ColOut {
 template <typename T> struct MaxThreads { static constexpr int v = sizeof(T) == 8 ? 512 : 1024; };
 
 template <typename T, int DIR, class P>
-__global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_y(FftPlan pl, int W, int Lx, int Ky, int nzp, int nvec,
+__global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_y(FftPlan pl, Geo geo, int W, int Lx, int Ky, int nzp, int nvec,
                                                  const typename CT<T>::t* __restrict__ in,
                                                  typename CT<T>::t* __restrict__ out,
                                                  const typename CT<T>::t* __restrict__ tw) {
@@ -453,12 +453,12 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_y(FftPlan pl, int W, 
   auto mk_in = [&](int item) {
     bool valid;
     const auto c = col(item, valid);
-    return ColIn<C>{in + c.first * rows_in * Lx + c.second, Lx, rows_in, valid};
+    return ColIn<C>{in + c.first * (DIR < 0 ? geo.pa : geo.pb) + c.second, geo.rp, rows_in, valid};
   };
   auto mk_out = [&](int item) {
     bool valid;
     const auto c = col(item, valid);
-    return ColOut<C>{out + c.first * rows_out * Lx + c.second, Lx, rows_out, valid};
+    return ColOut<C>{out + c.first * (DIR < 0 ? geo.pb : geo.pa) + c.second, geo.rp, rows_out, valid};
   };
   Lds<C, true> acc{lds, W, 0, w};
   run_items<P, C, DIR, true>(pl, j0, ntile * nzp * nvec, mk_in, mk_out, acc, tw);
@@ -534,7 +534,7 @@ __device__ __forceinline__ void fused_mul(int R, int L, int j0, int TP, const Sr
 }
 
 template <typename T>
-__global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_z(FftPlan pl, FftPlan ipl, int W, int Lx, int Ly, int nzp,
+__global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_z(FftPlan pl, FftPlan ipl, Geo geo, int W, int Lx, int Ly, int nzp,
                                                  int nvec, int vpb, const int32_t* __restrict__ zslot,
                                                  const T* __restrict__ zhat,
                                                  typename CT<T>::t* __restrict__ B,
@@ -572,9 +572,9 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_z(FftPlan pl, FftPlan
   const int v0 = blockIdx.y * vpb;
   const int v1 = min(nvec, v0 + vpb);
   for (int vec = v0; vec < v1; ++vec) {
-    C* vb = B + (size_t)vec * nzp * plane + (size_t)ky * Lx + kxc;
-    ZIn<C> gin{vb, zslot, plane, valid};
-    ZOut<C> gout{vb, zslot, plane, valid};
+    C* vb = B + (size_t)vec * nzp * geo.pb + (size_t)ky * geo.rp + kxc;
+    ZIn<C> gin{vb, zslot, (size_t)geo.pb, valid};
+    ZOut<C> gout{vb, zslot, (size_t)geo.pb, valid};
     if (pl.ns == 1) {
       fused_mul<C, T>(Rl, L, j0, TP, gin, gout, tw, zv, false);
     } else {
@@ -613,7 +613,7 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_z(FftPlan pl, FftPlan
 // in registers for all vectors; each chunk of V vectors is staged through
 // LDS with 128/256-byte coalesced loads and updated in place.
 template <typename T, int NZ, int RG, int V>
-__global__ void __launch_bounds__(256) k_zdirect(int Lx, int Ly, int nzp, int nvec, int vpb,
+__global__ void __launch_bounds__(256) k_zdirect(Geo geo, int Lx, int Ly, int nzp, int nvec, int vpb,
                                                  const int32_t* __restrict__ zlist,
                                                  const T* __restrict__ g,
                                                  typename CT<T>::t* __restrict__ B) {
@@ -644,8 +644,8 @@ __global__ void __launch_bounds__(256) k_zdirect(int Lx, int Ly, int nzp, int nv
       m[r][j] = (valid && i < nzp && j < nzp) ? g[((size_t)d * Ly + ky) * Lx + kx] : (T)0;
     }
   }
-  const size_t plane = (size_t)Ly * Lx;
-  C* base = B + (size_t)ky * Lx + kx0;
+  const size_t plane = (size_t)geo.pb;
+  C* base = B + (size_t)ky * geo.rp + kx0;
   const int vbeg = blockIdx.y * vpb;
   const int vend = min(nvec, vbeg + vpb);
   // staged element e of a chunk: ww = e % W, j = (e / W) % NZ, v = e / (W NZ);
@@ -715,7 +715,7 @@ template <typename C, typename T> struct XOut {
 };
 
 template <typename T, class P>
-__global__ void __launch_bounds__(256) k_pass_xi(FftPlan pl, int WX, int Kx, int Ky, int nzp, int K, int nvec,
+__global__ void __launch_bounds__(256) k_pass_xi(FftPlan pl, Geo geo, int WX, int Kx, int Ky, int nzp, int K, int nvec,
                                                   EpiParams ep, const int32_t* __restrict__ zlist,
                                                   const int32_t* __restrict__ vidx,
                                                   const typename CT<T>::t* __restrict__ A,
@@ -746,7 +746,7 @@ __global__ void __launch_bounds__(256) k_pass_xi(FftPlan pl, int WX, int Kx, int
     int vec, yy, zp;
     bool valid;
     where(item, vec, yy, zp, valid);
-    return ColIn<C>{A + (((size_t)vec * nzp + zp) * Ky + yy) * Lx, 1, Lx, valid};
+    return ColIn<C>{A + ((size_t)vec * nzp + zp) * geo.pa + (size_t)yy * geo.rp, 1, Lx, valid};
   };
   auto mk_out = [&](int item) {
     int vec, yy, zp;
@@ -763,6 +763,14 @@ __global__ void __launch_bounds__(256) k_pass_xi(FftPlan pl, int WX, int Kx, int
 }
 
 // ------------------------------------------------------------- launcher ---
+Geo make_geo(const svh_problem* p, size_t csize) {
+  Geo g;
+  g.rp = p->L[0] + (int)(128 / csize);
+  g.pa = (long long)p->K[1] * g.rp + (long long)(256 / csize);
+  g.pb = (long long)p->L[1] * g.rp + (long long)(256 / csize);
+  return g;
+}
+
 // Blocks of a persistent launch: as many as can be resident at once.
 static int persistent_grid(const void* kernel, int threads, size_t shmem, int nitems, int ncu, int mult) {
   if (mult <= 0) return nitems;
@@ -812,6 +820,7 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
   const int nzp = (int)p->zlist.size();
   const int K = p->nvox;
   const Tune& tn = p->tune[dbl ? SVH_FP64 : SVH_FP32];
+  const Geo geo = make_geo(p, sizeof(C));
   if (ev) hipEventRecord(ev[0], s);
   // X
   with_plan(Lx, [&](auto tag) {
@@ -823,7 +832,7 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const int nitems = ((NP + WX - 1) / WX) * nvec;
     const size_t sh = (size_t)WX * pencil_pitch(Lx) * sizeof(C);
     const int g = persistent_grid((const void*)k_pass_x<T, P>, WX * tp, sh, nitems, p->ncu, tn.grid_mult[0]);
-    hipLaunchKernelGGL((k_pass_x<T, P>), dim3(g), dim3(WX * tp), sh, s, pl, WX, Kx, Ky, nzp, K, nvec,
+    hipLaunchKernelGGL((k_pass_x<T, P>), dim3(g), dim3(WX * tp), sh, s, pl, geo, WX, Kx, Ky, nzp, K, nvec,
                        p->d_zlist, p->d_vidx, x, A, tw[0]);
   });
   if (ev) hipEventRecord(ev[1], s);
@@ -836,7 +845,7 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const int nitems = ((Lx + W - 1) / W) * nzp * nvec;
     const size_t sh = (size_t)W * Ly * sizeof(C);
     const int g = persistent_grid((const void*)k_pass_y<T, -1, P>, W * tp, sh, nitems, p->ncu, tn.grid_mult[1]);
-    hipLaunchKernelGGL((k_pass_y<T, -1, P>), dim3(g), dim3(W * tp), sh, s, pl, W, Lx, Ky, nzp, nvec, A, B,
+    hipLaunchKernelGGL((k_pass_y<T, -1, P>), dim3(g), dim3(W * tp), sh, s, pl, geo, W, Lx, Ky, nzp, nvec, A, B,
                        tw[1]);
   });
   if (ev) hipEventRecord(ev[2], s);
@@ -856,13 +865,13 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const size_t sh = (size_t)V * NZ * W * sizeof(C) + (size_t)NZ * sizeof(int);
     const T* gk = static_cast<const T*>(zhat);
     switch (NZ) {
-      case 8: hipLaunchKernelGGL((k_zdirect<T, 8, RG, V>), grid, dim3(256), sh, s, Lx, Ly, nzp, nvec, vpb,
+      case 8: hipLaunchKernelGGL((k_zdirect<T, 8, RG, V>), grid, dim3(256), sh, s, geo, Lx, Ly, nzp, nvec, vpb,
                                  p->d_zlist, gk, B); break;
-      case 16: hipLaunchKernelGGL((k_zdirect<T, 16, RG, V>), grid, dim3(256), sh, s, Lx, Ly, nzp, nvec, vpb,
+      case 16: hipLaunchKernelGGL((k_zdirect<T, 16, RG, V>), grid, dim3(256), sh, s, geo, Lx, Ly, nzp, nvec, vpb,
                                   p->d_zlist, gk, B); break;
-      case 24: hipLaunchKernelGGL((k_zdirect<T, 24, RG, V>), grid, dim3(256), sh, s, Lx, Ly, nzp, nvec, vpb,
+      case 24: hipLaunchKernelGGL((k_zdirect<T, 24, RG, V>), grid, dim3(256), sh, s, geo, Lx, Ly, nzp, nvec, vpb,
                                   p->d_zlist, gk, B); break;
-      default: hipLaunchKernelGGL((k_zdirect<T, 32, RG, V>), grid, dim3(256), sh, s, Lx, Ly, nzp, nvec, vpb,
+      default: hipLaunchKernelGGL((k_zdirect<T, 32, RG, V>), grid, dim3(256), sh, s, geo, Lx, Ly, nzp, nvec, vpb,
                                   p->d_zlist, gk, B); break;
     }
   } else {
@@ -872,7 +881,7 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const int vpb = nvec < 4 ? nvec : 4;
     dim3 grid(((Lx + W - 1) / W) * Ly, (nvec + vpb - 1) / vpb);
     const size_t sh = (size_t)W * pl.L * sizeof(C);
-    hipLaunchKernelGGL(k_pass_z<T>, grid, dim3(W * pl.tp), sh, s, pl, ipl, W, Lx, Ly, nzp, nvec, vpb,
+    hipLaunchKernelGGL(k_pass_z<T>, grid, dim3(W * pl.tp), sh, s, pl, ipl, geo, W, Lx, Ly, nzp, nvec, vpb,
                        p->d_zslot, static_cast<const T*>(zhat), B, tw[2]);
   }
   if (ev) hipEventRecord(ev[3], s);
@@ -885,7 +894,7 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const int nitems = ((Lx + W - 1) / W) * nzp * nvec;
     const size_t sh = (size_t)W * Ly * sizeof(C);
     const int g = persistent_grid((const void*)k_pass_y<T, +1, P>, W * tp, sh, nitems, p->ncu, tn.grid_mult[2]);
-    hipLaunchKernelGGL((k_pass_y<T, +1, P>), dim3(g), dim3(W * tp), sh, s, pl, W, Lx, Ky, nzp, nvec, B, A,
+    hipLaunchKernelGGL((k_pass_y<T, +1, P>), dim3(g), dim3(W * tp), sh, s, pl, geo, W, Lx, Ky, nzp, nvec, B, A,
                        tw[1]);
   });
   if (ev) hipEventRecord(ev[4], s);
@@ -904,7 +913,7 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const T inv_n = (T)(1.0 / ((double)p->L[0] * p->L[1] * (zdirect ? 1.0 : (double)p->L[2])));
     const C* sc = dbl ? reinterpret_cast<const C*>(p->d_sconv64) : reinterpret_cast<const C*>(p->d_sconv32);
     const C* cd = dbl ? reinterpret_cast<const C*>(p->d_cdiag64) : reinterpret_cast<const C*>(p->d_cdiag32);
-    hipLaunchKernelGGL((k_pass_xi<T, P>), dim3(g), dim3(WX * tp), sh, s, pl, WX, Kx, Ky, nzp, K, nvec, ep,
+    hipLaunchKernelGGL((k_pass_xi<T, P>), dim3(g), dim3(WX * tp), sh, s, pl, geo, WX, Kx, Ky, nzp, K, nvec, ep,
                        p->d_zlist, p->d_vidx, A, x, y, sc, cd, inv_n, tw[0]);
   });
   if (ev) hipEventRecord(ev[5], s);

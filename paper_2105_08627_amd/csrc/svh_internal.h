@@ -46,6 +46,16 @@ struct EpiParams {
   int fidx[kMaxVecsPerChunk];  // frequency slot per RHS of the chunk (-1 = bare)
 };
 
+// Strides (in complex elements) of the intermediate buffers
+// A[vec][plane][y < Ky][x < Lx] and B[vec][plane][ky < Ly][x < Lx]: rows and
+// planes are padded off powers of two so that the rows a column pass touches
+// spread over memory channels instead of aliasing onto one.
+struct Geo {
+  int rp;          // row pitch
+  long long pa;    // plane stride of A
+  long long pb;    // plane stride of B
+};
+
 // Launch choices of the FFT passes, picked by svh_autotune per precision.
 // grid_mult[i] for pass i in {X, Y, Yi, Xi}: the persistent launch uses
 // (resident blocks per CU x CUs x grid_mult) blocks; 0 = one block per item.
@@ -105,6 +115,7 @@ hipError_t launch_even_spectrum(const svh_problem* p, const double* d_T, double*
 hipError_t launch_tucker_rebuild(const svh_problem* p, bool fp32_out, bool zspace, void* d_out,
                                  double* d_V, double* d_W, hipStream_t s);
 bool use_zdirect(const svh_problem* p);
+Geo make_geo(const svh_problem* p, size_t csize);
 size_t tucker_scratch_doubles(const svh_problem* p);
 hipError_t launch_to_f32(const double* in, float* out, size_t n, hipStream_t s);
 

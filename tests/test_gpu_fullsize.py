@@ -1,0 +1,88 @@
+"""Full-size checks on the benchmark workload, in the benchmark's launch
+configuration: the 256 x 256 x 128 three-layer stack, 64 right-hand sides
+(8 ports x 8 frequencies), Tucker tolerance 1e-8, autotuned launch shapes.
+
+The oracle cannot form the whole product at this size, so it computes sampled
+outputs one by one (each observer voxel: its full row of Green integrals
+against all 687,600 voxels).  Properties that hold at any size are checked on
+the whole output.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import green
+from oracle import operator as op
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def stack():
+    import paper_2105_08627_amd as svh
+    assert torch.cuda.is_available()
+    dev = torch.device("cuda")
+    cfg = wl.WORKLOADS["c5_stack"]
+    mask = cfg["mask"]()
+    p = svh.Problem(mask, cfg["dx"])
+    p.set_material(cfg["freqs"], cfg["sigma0"], cfg["lam"])
+    p.setup_tensors()
+    ranks, bound = p.tucker_compress(1e-8)
+    nrhs = 64
+    fidx = [r % 8 for r in range(nrhs)]
+    x = wl.random_currents(cfg["seed"], (nrhs, 3, p.K))
+    x64 = torch.from_numpy(x).to(dev)
+    x32 = x64.to(torch.complex64)
+    p.autotune(x64, fidx)
+    p.autotune(x32, fidx)
+    y64 = p.matvec(x64, fidx).cpu().numpy()
+    y32 = p.matvec(x32, fidx).cpu().numpy().astype(np.complex128)
+    print(f"[fullsize] K={p.K} ranks={ranks} bound={bound:.2e}", flush=True)
+    return dict(p=p, mask=mask, cfg=cfg, x=x, fidx=fidx, y64=y64, y32=y32, dev=dev, bound=bound)
+
+
+def test_sampled_outputs_match_oracle(stack):
+    """Sampled outputs (2 observer voxels x 3 components x 64 RHS) against the
+    oracle's one-by-one row sums.  The spectrum is Tucker-truncated at 1e-8
+    (bound-level estimate printed); the tolerance is 1e-7 relative to the row's
+    scale, FP64; FP32 1e-5."""
+    cfg, mask, x = stack["cfg"], stack["mask"], stack["x"]
+    P = op.voxel_coords(mask)
+    dx = cfg["dx"]
+    rng = np.random.default_rng(77)
+    for l in rng.choice(P.shape[0], size=2, replace=False):
+        Tl = green.family_values("M0", P - P[l])
+        print(f"[fullsize] observer {l} at {P[l]}", flush=True)
+        for r, f in enumerate(stack["fidx"]):
+            w = 2 * np.pi * cfg["freqs"][f]
+            c = op.material_c(cfg["freqs"][f], cfg["sigma0"], cfg["lam"])
+            for b in range(3):
+                ref = 1j * w * op.MU0 * dx * (Tl @ x[r, b]) + c / dx * x[r, b, l]
+                scale = abs(1j * w * op.MU0 * dx) * np.sqrt(np.sum(Tl ** 2) * np.mean(np.abs(x[r, b]) ** 2)) + abs(ref)
+                e64 = abs(stack["y64"][r, b, l] - ref) / scale
+                e32 = abs(stack["y32"][r, b, l] - ref) / scale
+                assert e64 <= 1e-7, (l, r, b, e64)
+                assert e32 <= 1e-5, (l, r, b, e32)
+
+
+def test_fp32_matches_fp64_whole_output(stack):
+    y64, y32 = stack["y64"], stack["y32"]
+    for r in range(y64.shape[0]):
+        e = np.linalg.norm(y32[r] - y64[r]) / np.linalg.norm(y64[r])
+        assert e <= 1e-6, (r, e)
+
+
+def test_operator_symmetry_whole_grid(stack):
+    """u^T Z v = v^T Z u (Galerkin symmetry, transpose without conjugation)
+    over the full grid, FP64."""
+    p, dev = stack["p"], stack["dev"]
+    u = wl.random_currents(5, (1, 3, p.K))
+    v = wl.random_currents(6, (1, 3, p.K))
+    Zu = p.matvec(torch.from_numpy(u).to(dev), [3]).cpu().numpy()
+    Zv = p.matvec(torch.from_numpy(v).to(dev), [3]).cpu().numpy()
+    a = np.sum(v * Zu)
+    b = np.sum(u * Zv)
+    assert abs(a - b) <= 1e-12 * abs(a), (a, b)
