@@ -159,6 +159,59 @@ svh_status svh_profile_read(svh_problem* p, double* ms_out, int* ncalls_out);
 #define SVH_ZSTEP_DIRECT 2
 svh_status svh_set_zstep(svh_problem* p, int mode);
 
+/* ---------------------------------------------------------------- solve --
+ * Saddle system of eq. 7 with ports.  Nodes are the centres of the faces of
+ * non-empty voxels; A[m, (k, a)] is the current basis f^a of voxel k draws
+ * from node m (+1 at its -a face, -1 at its +a face), so A I = 0 is current
+ * conservation (eq. 2) and the first block row reads Z I - A^T Phi = V.
+ * A port holds Phi = 1 on its + terminal faces and Phi = 0 on its - terminal
+ * faces and on the faces of every other port.  Each conductor region without
+ * a port face has one node grounded (its potential is otherwise undefined).
+ * The admittance Y[q][p] is the current entering port q's + terminal when
+ * port p is driven (b_q^T I_p with b_q = A_{q+}^T 1); Y^-1 is the port
+ * impedance matrix and Im(Y^-1)/w the inductance matrix. */
+#define SVH_MAX_PORTS 64
+
+/* Define the ports.  Faces are (voxel index k in compact order, face code)
+ * pairs with face codes 0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z.  Port q's +
+ * terminal faces are plus_faces[2*i .. 2*i+1] for plus_ptr[q] <= i <
+ * plus_ptr[q+1] (minus likewise); 1 <= nports <= SVH_MAX_PORTS.  Builds the
+ * node topology on first use.  Host arrays, read during the call. */
+svh_status svh_set_ports(svh_problem* p, int nports, const int32_t* plus_ptr, const int32_t* plus_faces,
+                         const int32_t* minus_ptr, const int32_t* minus_faces);
+
+/* Unknowns per port column N = 3K + M and node count M (after svh_set_ports). */
+svh_status svh_solve_sizes(const svh_problem* p, int* N, int* M);
+
+typedef struct {
+  int iterations;        /* outer (F)GMRES steps                              */
+  int restarts;          /* restart cycles                                     */
+  int inner_iterations;  /* conjugate-gradient steps in the preconditioner    */
+  int converged;         /* 1 if every port reached the tolerance             */
+  double relres;         /* largest true relative residual ||b - K x|| / ||b|| */
+  double relres_port[SVH_MAX_PORTS];
+} svh_solve_info;
+
+/* Workspace bytes of svh_solve for restart length `restart` (SVH_FP64). */
+size_t svh_solve_workspace_bytes(const svh_problem* p, svh_prec prec, int restart);
+
+/* Solve K x_p = [b_p; 0] for every port p (right-preconditioned flexible
+ * GMRES with restart `restart`, Sec. III; the preconditioner is eq. 12 with
+ * Y = |diag Z| applied through eqs. 13-15, its Schur complement solved by
+ * conjugate gradients to a relative 1e-8 or rre, whichever is smaller).
+ * prec: SVH_FP64.  freq_idx: frequency slot of the material.  rre: relative
+ * residual target (the paper uses 1e-8).  maxit: cap on GMRES steps.
+ * transpose != 0 solves K^T x = [b; 0] instead (adjoint system).
+ * x_dev: nports columns of N complex doubles (currents, component-major as in
+ * svh_matvec, then node potentials; port and grounded nodes hold 0).
+ * Y_host (may be NULL): nports*nports complex doubles, Y[q*nports + p].
+ * info (may be NULL): iteration counts and true residuals.
+ * Returns SVH_ENOTCONV (with x, Y and info filled) if the target is missed.
+ * Synchronises the stream. */
+svh_status svh_solve(svh_problem* p, svh_prec prec, int freq_idx, double rre, int restart, int maxit,
+                     int transpose, void* x_dev, double* Y_host, svh_solve_info* info, void* ws_dev,
+                     size_t ws_bytes, void* stream);
+
 /* Text of the last error on this problem (never NULL). */
 const char* svh_last_error(const svh_problem* p);
 

@@ -22,7 +22,7 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: 
 EXPORTED = [
     "svh_create", "svh_get_sizes", "svh_set_material", "svh_setup_tensors", "svh_green_toeplitz",
     "svh_get_toeplitz", "svh_tucker_compress", "svh_workspace_bytes", "svh_matvec",
-    "svh_set_zstep", "svh_autotune", "svh_profile_enable", "svh_profile_read", "svh_last_error", "svh_destroy",
+    "svh_set_zstep", "svh_autotune", "svh_set_ports", "svh_solve_sizes", "svh_solve_workspace_bytes", "svh_solve", "svh_profile_enable", "svh_profile_read", "svh_last_error", "svh_destroy",
 ]
 PROF_NAMES = ["tucker_restore", "pass_x", "pass_y", "pass_z_mul", "pass_yi", "pass_xi"]
 
@@ -31,6 +31,15 @@ _lib = None
 
 class SvhError(RuntimeError):
     pass
+
+
+MAX_PORTS = 64
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("inner_iterations", ctypes.c_int),
+                ("converged", ctypes.c_int), ("relres", ctypes.c_double),
+                ("relres_port", ctypes.c_double * MAX_PORTS)]
 
 
 def lib():
@@ -54,6 +63,11 @@ def lib():
     L.svh_workspace_bytes.restype = sz
     L.svh_matvec.argtypes = [vp, i32, i32, vp, vp, vp, vp, sz, vp]
     L.svh_set_zstep.argtypes = [vp, i32]
+    L.svh_set_ports.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.svh_solve_sizes.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.svh_solve_workspace_bytes.argtypes = [vp, i32, i32]
+    L.svh_solve_workspace_bytes.restype = sz
+    L.svh_solve.argtypes = [vp, i32, i32, dbl, i32, i32, i32, vp, vp, ctypes.POINTER(SolveInfo), vp, sz, vp]
     L.svh_autotune.argtypes = [vp, i32, i32, vp, vp, vp, vp, sz, vp, vp]
     L.svh_profile_enable.argtypes = [vp, i32]
     L.svh_profile_read.argtypes = [vp, vp, vp]
@@ -62,7 +76,7 @@ def lib():
     L.svh_destroy.argtypes = [vp]
     L.svh_destroy.restype = None
     for name in EXPORTED:
-        if name not in ("svh_workspace_bytes", "svh_last_error", "svh_destroy"):
+        if name not in ("svh_workspace_bytes", "svh_last_error", "svh_destroy", "svh_solve_workspace_bytes"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -188,6 +202,44 @@ class Problem:
                                        ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                        _stream_handle(stream), _ptr(ms)), "svh_autotune")
         return float(ms[0])
+
+    def set_ports(self, ports):
+        """ports: list of (plus_faces, minus_faces); faces are (k, face code)
+        pairs, face codes 0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z."""
+        def csr(lists):
+            ptr = np.zeros(len(lists) + 1, dtype=np.int32)
+            flat = []
+            for i, faces in enumerate(lists):
+                flat.extend([int(v) for kf in faces for v in kf])
+                ptr[i + 1] = ptr[i] + len(faces)
+            return ptr, np.ascontiguousarray(np.asarray(flat, dtype=np.int32))
+        pp, pf = csr([pl for pl, _ in ports])
+        mp, mf = csr([mi for _, mi in ports])
+        self._check(lib().svh_set_ports(self._h, len(ports), _ptr(pp), _ptr(pf), _ptr(mp), _ptr(mf)),
+                    "svh_set_ports")
+        N, M = ctypes.c_int(), ctypes.c_int()
+        self._check(lib().svh_solve_sizes(self._h, ctypes.byref(N), ctypes.byref(M)), "svh_solve_sizes")
+        self.N, self.M, self.nports = N.value, M.value, len(ports)
+
+    def solve(self, freq_idx, rre=1e-8, restart=50, maxit=1000, transpose=False, device="cuda", stream=None,
+              check=True):
+        """Solve every port excitation; returns (X (nports, N) complex128 device
+        tensor, Y admittance (nports, nports) numpy array, info dict)."""
+        import torch
+        X = torch.empty((self.nports, self.N), dtype=torch.complex128, device=device)
+        nb = int(lib().svh_solve_workspace_bytes(self._h, SVH_FP64, restart))
+        ws = torch.empty(nb, dtype=torch.uint8, device=device)
+        Y = np.zeros((self.nports, self.nports), dtype=np.complex128)
+        info = SolveInfo()
+        st = lib().svh_solve(self._h, SVH_FP64, int(freq_idx), float(rre), int(restart), int(maxit),
+                             int(transpose), ctypes.c_void_p(X.data_ptr()), _ptr(Y), ctypes.byref(info),
+                             ctypes.c_void_p(ws.data_ptr()), nb, _stream_handle(stream))
+        d = {"iterations": info.iterations, "restarts": info.restarts, "inner_iterations": info.inner_iterations,
+             "converged": bool(info.converged), "relres": info.relres,
+             "relres_port": [info.relres_port[i] for i in range(self.nports)]}
+        if st != 0 and not (st == -4 and not check):
+            self._check(st, "svh_solve")
+        return X, Y, d
 
     def profile(self, enable=True):
         self._check(lib().svh_profile_enable(self._h, int(enable)), "svh_profile_enable")

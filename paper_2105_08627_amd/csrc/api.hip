@@ -207,7 +207,10 @@ svh_status svh_set_material(svh_problem* p, int nfreq, const double* f_hz, const
   HIPCHK(upload(&p->d_cdiag32, cd32.data(), cd32.size()));
   HIPCHK(upload(&p->d_sconv64, s64.data(), s64.size()));
   HIPCHK(upload(&p->d_sconv32, s32.data(), s32.size()));
+  p->cdiag_host.resize(cd64.size());
+  for (size_t i = 0; i < cd64.size(); ++i) p->cdiag_host[i] = std::complex<double>(cd64[i].x, cd64[i].y);
   p->nfreq = nfreq;
+  p->diag_freq = -2;
   return SVH_OK;
 }
 
@@ -315,6 +318,15 @@ size_t svh_workspace_bytes(const svh_problem* p, svh_prec prec, int nrhs) {
 svh_status svh_matvec(svh_problem* p, svh_prec prec, int nrhs, const int32_t* freq_idx, const void* x,
                       void* y, void* ws, size_t ws_bytes, void* stream) {
   if (!p) return SVH_EINVAL;
+  const long long ld = (long long)p->C * p->nvox;
+  return svh::matvec_impl(p, prec, nrhs, freq_idx, x, ld, y, ld, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+namespace svh {
+svh_status matvec_impl(svh_problem* p, svh_prec prec, int nrhs, const int32_t* freq_idx, const void* x,
+                       long long ldx, void* y, long long ldy, void* ws, size_t ws_bytes, hipStream_t s) {
   if (nrhs < 1 || !freq_idx || !x || !y || !ws) return fail(p, SVH_EINVAL, "matvec: bad arguments");
   if (prec != SVH_FP64 && prec != SVH_FP32) return fail(p, SVH_EINVAL, "matvec: bad precision");
   if (!p->tucker && !p->d_zhat64) return fail(p, SVH_ESTATE, "matvec: call svh_setup_tensors first");
@@ -324,15 +336,16 @@ svh_status svh_matvec(svh_problem* p, svh_prec prec, int nrhs, const int32_t* fr
   }
   const size_t need = svh_workspace_bytes(p, prec, nrhs);
   if (ws_bytes < need) return fail(p, SVH_EINVAL, "matvec: workspace too small");
-  hipStream_t s = static_cast<hipStream_t>(stream);
   const bool dbl = prec == SVH_FP64;
   const size_t cs = dbl ? sizeof(double2) : sizeof(float2);
-  const size_t vecb = (size_t)p->nvox * cs;
-  // overlap check of x and y
-  const size_t tot = (size_t)nrhs * p->C * vecb;
+  const long long ck = (long long)p->C * p->nvox;
+  if (ldx < ck || ldy < ck) return fail(p, SVH_EINVAL, "matvec: stride below one vector");
+  // overlap check of x and y (whole strided extents)
   const char* xb = static_cast<const char*>(x);
   const char* yb = static_cast<const char*>(y);
-  if (xb < yb + tot && yb < xb + tot) return fail(p, SVH_EINVAL, "matvec: x and y overlap");
+  const size_t xext = ((size_t)(nrhs - 1) * ldx + ck) * cs;
+  const size_t yext = ((size_t)(nrhs - 1) * ldy + ck) * cs;
+  if (xb < yb + yext && yb < xb + xext) return fail(p, SVH_EINVAL, "matvec: x and y overlap");
   char* w = static_cast<char*>(ws);
   auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
   const int cr = chunk_rhs(p, nrhs);
@@ -387,10 +400,12 @@ svh_status svh_matvec(svh_problem* p, svh_prec prec, int nrhs, const int32_t* fr
     ep.C = p->C;
     ep.K = p->nvox;
     ep.vec0 = 0;
+    ep.ldx = ldx;
+    ep.ldy = ldy;
     for (int i = 0; i < kMaxVecsPerChunk; ++i) ep.fidx[i] = -1;
     for (int i = 0; i < nr; ++i) ep.fidx[i] = freq_idx[r0 + i];
-    const char* xc = xb + (size_t)r0 * p->C * vecb;
-    char* yc = static_cast<char*>(y) + (size_t)r0 * p->C * vecb;
+    const char* xc = xb + (size_t)r0 * ldx * cs;
+    char* yc = static_cast<char*>(y) + (size_t)r0 * ldy * cs;
     hipError_t e = dbl ? launch_matvec_chunk<double>(p, nr * p->C, ep, xc, yc, A, B, zhat, s, ev)
                        : launch_matvec_chunk<float>(p, nr * p->C, ep, xc, yc, A, B, zhat, s, ev);
     HIPCHK(e);
@@ -399,6 +414,9 @@ svh_status svh_matvec(svh_problem* p, svh_prec prec, int nrhs, const int32_t* fr
     p->prof_events.push_back(std::vector<hipEvent_t>(evs.begin() + i, evs.begin() + i + 8));
   return SVH_OK;
 }
+}  // namespace svh
+
+extern "C" {
 
 svh_status svh_autotune(svh_problem* p, svh_prec prec, int nrhs, const int32_t* freq_idx, const void* x, void* y,
                         void* ws, size_t ws_bytes, void* stream, double* ms_out) {
@@ -510,6 +528,7 @@ void svh_destroy(svh_problem* p) {
   dfree(p->d_g64);
   dfree(p->d_g32);
   free_tucker(p);
+  svh::free_solver(p);
   for (auto& set : p->prof_events)
     for (hipEvent_t e : set) (void)hipEventDestroy(e);
   for (hipEvent_t e : p->prof_pool) (void)hipEventDestroy(e);

@@ -365,6 +365,7 @@ template <typename C> struct RowOut {
 
 template <typename T, class P>
 __global__ void __launch_bounds__(256) k_pass_x(FftPlan pl, Geo geo, int WX, int Kx, int Ky, int nzp, int K, int nvec,
+                                                int ncomp, long long ldx,
                                                  const int32_t* __restrict__ zlist,
                                                  const int32_t* __restrict__ vidx,
                                                  const typename CT<T>::t* __restrict__ x,
@@ -392,7 +393,8 @@ __global__ void __launch_bounds__(256) k_pass_x(FftPlan pl, Geo geo, int WX, int
     int vec, y, zp;
     bool valid;
     where(item, vec, y, zp, valid);
-    return XIn<C>{x + (size_t)vec * K, vidx + ((size_t)zlist[zp] * Ky + y) * Kx, Kx, valid};
+    return XIn<C>{x + (size_t)(vec / ncomp) * ldx + (size_t)(vec % ncomp) * K,
+                  vidx + ((size_t)zlist[zp] * Ky + y) * Kx, Kx, valid};
   };
   auto mk_out = [&](int item) {
     int vec, y, zp;
@@ -755,8 +757,9 @@ __global__ void __launch_bounds__(256) k_pass_xi(FftPlan pl, Geo geo, int WX, in
     const int f = ep.fidx[vec / ep.C];
     const C scale = f >= 0 ? cscale(sconv[f], inv_n) : C{inv_n, 0};
     const C* cd = f >= 0 ? cdiag + (size_t)f * K : nullptr;
-    return XOut<C, T>{y + (size_t)vec * K, x + (size_t)vec * K, cd, vidx + ((size_t)zlist[zp] * Ky + yy) * Kx,
-                      scale, Kx, valid};
+    const int rhs = vec / ep.C, comp = vec % ep.C;
+    return XOut<C, T>{y + (size_t)rhs * ep.ldy + (size_t)comp * K, x + (size_t)rhs * ep.ldx + (size_t)comp * K, cd,
+                      vidx + ((size_t)zlist[zp] * Ky + yy) * Kx, scale, Kx, valid};
   };
   Lds<C, false> acc{lds, WX, pencil_pitch(Lx), w};
   run_items<P, C, +1, false>(pl, j0, ngrp * nvec, mk_in, mk_out, acc, tw);
@@ -833,7 +836,7 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const size_t sh = (size_t)WX * pencil_pitch(Lx) * sizeof(C);
     const int g = persistent_grid((const void*)k_pass_x<T, P>, WX * tp, sh, nitems, p->ncu, tn.grid_mult[0]);
     hipLaunchKernelGGL((k_pass_x<T, P>), dim3(g), dim3(WX * tp), sh, s, pl, geo, WX, Kx, Ky, nzp, K, nvec,
-                       p->d_zlist, p->d_vidx, x, A, tw[0]);
+                       ep.C, ep.ldx, p->d_zlist, p->d_vidx, x, A, tw[0]);
   });
   if (ev) hipEventRecord(ev[1], s);
   // Y forward

@@ -1,6 +1,7 @@
 // Host-side math of the library (compiled with the host compiler, no HIP).
 #pragma once
 
+#include <cstdint>
 #include <vector>
 
 namespace svh {
@@ -13,6 +14,21 @@ struct TuckerFactors {
   std::vector<double> F[3];  // F[i][k * d[i] + c], k < L[i]
   double relerr = 0;
 };
+
+// Face-node topology of the saddle system (eq. 7): incidence matrix A in
+// compressed column (one column per basis function a * nvox + k) and
+// compressed row (one row per node) form.
+struct Topology {
+  int M = 0, C = 3, nvox = 0;
+  std::vector<int32_t> coords;     // (x, y, z) per voxel
+  std::vector<int32_t> face_node;  // node of face 0..5 (-x, +x, -y, +y, -z, +z) per voxel
+  std::vector<int> cptr, crow;
+  std::vector<double> cval;
+  std::vector<int> rptr, rcol;
+  std::vector<double> rval;
+};
+int build_topology(const int K[3], const int32_t* vidx, int nvox, int basis, Topology& t);
+void ground_floating(const Topology& t, std::vector<char>& dirichlet);
 
 // Unit-voxel Green integral T[dz][dy][dx] for offsets 0 <= d < K.
 void green_toeplitz_m0(int Kx, int Ky, int Kz, double* T);

@@ -1,0 +1,770 @@
+// Port solve of the saddle system (eq. 7) on the device, FP64.
+//
+//   K [I; Phi_F] = [A_D^T Phi_D; 0],  K = [[Z, -A_F^T], [A_F, 0]]
+//
+// Right-preconditioned flexible GMRES (restart m, Sec. III settings), all
+// port excitations in lockstep.  The preconditioner is the sparse saddle
+// matrix of eq. 12 with Y = |diag Z|, applied through its Schur complement
+// (eqs. 13-15): e = d - A Y^-1 c, S b = e with S = A Y^-1 A^T (real, SPD on
+// the free nodes), a = Y^-1 (c + A^T b).  S b = e is solved by Jacobi-
+// preconditioned conjugate gradients on the device; since that inner solve
+// is inexact the outer method is the flexible variant.  Gram-Schmidt runs
+// twice (CGS2) with all inner products in FP64 on the device; only the
+// Hessenberg column (a few scalars per port) crosses to the host per step.
+//
+// Vector layout: per port one column of N = C*K + M complex doubles,
+// currents (component-major, as for svh_matvec) then one potential per node.
+// Dirichlet (port and grounded) node entries are kept at zero.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <vector>
+
+#include "host_math.h"
+#include "svh_internal.h"
+
+namespace svh {
+
+typedef std::complex<double> cd;
+
+__device__ __forceinline__ double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 zsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 zcmul(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 zscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+#define GRID_STRIDE(i, n) \
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long long)gridDim.x * blockDim.x)
+
+// ------------------------------------------------------------- operator --
+// After y_I = Z x_I: y_I -= A^T x_Phi and y_Phi = A x_I on free nodes
+// (transpose: y_I += A^T x_Phi, y_Phi = -A x_I).
+__global__ void k_saddle_fix(int nrhs, long long N, int CK, int M, const int* __restrict__ cptr,
+                             const int* __restrict__ crow, const double* __restrict__ cval,
+                             const int* __restrict__ rptr, const int* __restrict__ rcol,
+                             const double* __restrict__ rval, const uint8_t* __restrict__ freem,
+                             const double2* __restrict__ x, double2* __restrict__ y, int transpose) {
+  const long long per = (long long)CK + M;
+  GRID_STRIDE(i, per * nrhs) {
+    const long long r = i / per, idx = i % per;
+    const double2* xr = x + r * N;
+    double2* yr = y + r * N;
+    if (idx < CK) {
+      double2 acc = make_double2(0, 0);
+      for (int q = cptr[idx]; q < cptr[idx + 1]; ++q) acc = zadd(acc, zscale(xr[CK + crow[q]], cval[q]));
+      yr[idx] = transpose ? zadd(yr[idx], acc) : zsub(yr[idx], acc);
+    } else {
+      const int m = (int)(idx - CK);
+      double2 acc = make_double2(0, 0);
+      if (freem[m])
+        for (int q = rptr[m]; q < rptr[m + 1]; ++q) acc = zadd(acc, zscale(xr[rcol[q]], rval[q]));
+      yr[idx] = transpose ? zscale(acc, -1.0) : acc;
+    }
+  }
+}
+
+// ------------------------------------------------------- preconditioner --
+// e = d - A Y^-1 c (free rows; transpose: d + A Y^-1 c), into node vector e
+__global__ void k_pre_rhs(int nrhs, long long N, int CK, int M, const int* __restrict__ rptr,
+                          const int* __restrict__ rcol, const double* __restrict__ rval,
+                          const uint8_t* __restrict__ freem, const double* __restrict__ ydiag,
+                          const double2* __restrict__ in, double2* __restrict__ e, int transpose) {
+  GRID_STRIDE(i, (long long)M * nrhs) {
+    const long long r = i / M;
+    const int m = (int)(i % M);
+    const double2* c = in + r * N;
+    double2 acc = make_double2(0, 0);
+    if (freem[m]) {
+      for (int q = rptr[m]; q < rptr[m + 1]; ++q) acc = zadd(acc, zscale(c[rcol[q]], rval[q] / ydiag[rcol[q]]));
+      const double2 d = c[CK + m];
+      acc = transpose ? zadd(d, acc) : zsub(d, acc);
+    }
+    e[r * M + m] = acc;
+  }
+}
+
+// u = Y^-1 A^T v (basis-sized), v a node vector with zero Dirichlet entries
+__global__ void k_s_half(int nrhs, int CK, int M, const int* __restrict__ cptr, const int* __restrict__ crow,
+                         const double* __restrict__ cval, const double* __restrict__ ydiag,
+                         const double2* __restrict__ v, double2* __restrict__ u) {
+  GRID_STRIDE(i, (long long)CK * nrhs) {
+    const long long r = i / CK;
+    const int b = (int)(i % CK);
+    const double2* vr = v + r * M;
+    double2 acc = make_double2(0, 0);
+    for (int q = cptr[b]; q < cptr[b + 1]; ++q) acc = zadd(acc, zscale(vr[crow[q]], cval[q]));
+    u[r * CK + b] = zscale(acc, 1.0 / ydiag[b]);
+  }
+}
+
+// q = A u on free nodes (S v = A Y^-1 A^T v)
+__global__ void k_s_full(int nrhs, int CK, int M, const int* __restrict__ rptr, const int* __restrict__ rcol,
+                         const double* __restrict__ rval, const uint8_t* __restrict__ freem,
+                         const double2* __restrict__ u, double2* __restrict__ q) {
+  GRID_STRIDE(i, (long long)M * nrhs) {
+    const long long r = i / M;
+    const int m = (int)(i % M);
+    double2 acc = make_double2(0, 0);
+    if (freem[m])
+      for (int k = rptr[m]; k < rptr[m + 1]; ++k) acc = zadd(acc, zscale(u[r * CK + rcol[k]], rval[k]));
+    q[r * M + m] = acc;
+  }
+}
+
+// a = Y^-1 (c + A^T b) (transpose: Y^-1 (c - A^T b)); out = [a; b]
+__global__ void k_pre_out(int nrhs, long long N, int CK, int M, const int* __restrict__ cptr,
+                          const int* __restrict__ crow, const double* __restrict__ cval,
+                          const double* __restrict__ ydiag, const double2* __restrict__ in,
+                          const double2* __restrict__ bsol, double2* __restrict__ out, int transpose) {
+  const long long per = (long long)CK + M;
+  GRID_STRIDE(i, per * nrhs) {
+    const long long r = i / per, idx = i % per;
+    const double2* br = bsol + r * M;
+    if (idx < CK) {
+      double2 acc = make_double2(0, 0);
+      for (int q = cptr[idx]; q < cptr[idx + 1]; ++q) acc = zadd(acc, zscale(br[crow[q]], cval[q]));
+      const double2 c = in[r * N + idx];
+      out[r * N + idx] = zscale(transpose ? zsub(c, acc) : zadd(c, acc), 1.0 / ydiag[idx]);
+    } else {
+      out[r * N + idx] = br[idx - CK];
+    }
+  }
+}
+
+// ------------------------------------------------------------ reductions --
+// part[g][blk] = sum over the block's chunk of conj(X_g) * Y_g, where pair g
+// = (i, r) reads X at X + i * xs_i + r * xs_r and Y at Y + r * ys_r.
+__global__ void __launch_bounds__(256) k_mdot(long long n, int nrhs, const double2* __restrict__ X, long long xs_i,
+                                              long long xs_r, const double2* __restrict__ Y, long long ys_r,
+                                              double2* __restrict__ part, int conj_x) {
+  __shared__ double2 sh[256];
+  const int g = blockIdx.y;
+  const int i = g / nrhs, r = g % nrhs;
+  const double2* xp = X + (long long)i * xs_i + (long long)r * xs_r;
+  const double2* yp = Y + (long long)r * ys_r;
+  double2 acc = make_double2(0, 0);
+  for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < n; k += (long long)gridDim.x * 256)
+    acc = zadd(acc, conj_x ? zcmul(xp[k], yp[k]) : zmul(xp[k], yp[k]));
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = zadd(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(long long)g * gridDim.x + blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_psum(int nb, const double2* __restrict__ part, double2* __restrict__ out) {
+  __shared__ double2 sh[256];
+  const int g = blockIdx.x;
+  double2 acc = make_double2(0, 0);
+  for (int k = threadIdx.x; k < nb; k += 256) acc = zadd(acc, part[(long long)g * nb + k]);
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = zadd(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[g] = sh[0];
+}
+
+// ------------------------------------------------------------------ PCG --
+// r = e, b = 0, z = D^-1 r, p = z
+__global__ void k_pcg_init(long long n, int M, const double* __restrict__ sdiag, const uint8_t* __restrict__ freem,
+                           const double2* __restrict__ e, double2* __restrict__ r, double2* __restrict__ z,
+                           double2* __restrict__ p, double2* __restrict__ b) {
+  GRID_STRIDE(i, n) {
+    const int m = (int)(i % M);
+    const double2 v = e[i];
+    r[i] = v;
+    const double2 zz = freem[m] ? zscale(v, 1.0 / sdiag[m]) : make_double2(0, 0);
+    z[i] = zz;
+    p[i] = zz;
+    b[i] = make_double2(0, 0);
+  }
+}
+
+// alpha = rho / Re(p^H q) per right-hand side (0 when converged or degenerate)
+__global__ void k_pcg_alpha(int nrhs, const double2* __restrict__ rho, const double2* __restrict__ pq,
+                            double* __restrict__ alpha) {
+  const int r = threadIdx.x;
+  if (r < nrhs) alpha[r] = (pq[r].x > 0 && rho[r].x > 0) ? rho[r].x / pq[r].x : 0.0;
+}
+
+// b += alpha p, r -= alpha q, z = D^-1 r
+__global__ void k_pcg_update(long long n, int M, const double* __restrict__ sdiag, const uint8_t* __restrict__ freem,
+                             const double* __restrict__ alpha, const double2* __restrict__ p,
+                             const double2* __restrict__ q, double2* __restrict__ b, double2* __restrict__ r,
+                             double2* __restrict__ z) {
+  GRID_STRIDE(i, n) {
+    const int m = (int)(i % M);
+    const double a = alpha[i / M];
+    b[i] = zadd(b[i], zscale(p[i], a));
+    const double2 rr = zsub(r[i], zscale(q[i], a));
+    r[i] = rr;
+    z[i] = freem[m] ? zscale(rr, 1.0 / sdiag[m]) : make_double2(0, 0);
+  }
+}
+
+// beta = rho_new / rho; rho = rho_new
+__global__ void k_pcg_beta(int nrhs, double2* __restrict__ rho, const double2* __restrict__ rho_new,
+                           double* __restrict__ beta) {
+  const int r = threadIdx.x;
+  if (r < nrhs) {
+    beta[r] = rho[r].x > 0 ? rho_new[r].x / rho[r].x : 0.0;
+    rho[r] = rho_new[r];
+  }
+}
+
+__global__ void k_pcg_dir(long long n, int M, const double* __restrict__ beta, const double2* __restrict__ z,
+                          double2* __restrict__ p) {
+  GRID_STRIDE(i, n) p[i] = zadd(z[i], zscale(p[i], beta[i / M]));
+}
+
+// ---------------------------------------------------------------- GMRES --
+// w -= sum_{i<=j} h[i][r] V_i  (h on the device, from k_mdot/k_psum)
+__global__ void k_cgs_update(long long N, int nrhs, int ni, const double2* __restrict__ V, long long vs_i,
+                             const double2* __restrict__ h, double2* __restrict__ w) {
+  GRID_STRIDE(k, N * nrhs) {
+    const long long r = k / N, n = k % N;
+    double2 acc = w[k];
+    for (int i = 0; i < ni; ++i) acc = zsub(acc, zmul(h[i * nrhs + r], V[(long long)i * vs_i + r * N + n]));
+    w[k] = acc;
+  }
+}
+
+// hh[i][r] += h2[i][r]
+__global__ void k_add_small(int n, double2* __restrict__ a, const double2* __restrict__ b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = zadd(a[i], b[i]);
+}
+
+// V[r] = w[r] / sqrt(nrm2[r]) (0 if the norm vanishes)
+__global__ void k_normalize(long long N, int nrhs, const double2* __restrict__ nrm2, const double2* __restrict__ w,
+                            double2* __restrict__ v) {
+  GRID_STRIDE(k, N * nrhs) {
+    const double s = nrm2[k / N].x;
+    v[k] = s > 0 ? zscale(w[k], 1.0 / sqrt(s)) : make_double2(0, 0);
+  }
+}
+
+// x[r] += sum_j coef[j][r] Z_j[r]
+__global__ void k_combine(long long N, int nrhs, int nj, const double2* __restrict__ Zk, long long zs_j,
+                          const double2* __restrict__ coef, double2* __restrict__ x) {
+  GRID_STRIDE(k, N * nrhs) {
+    const long long r = k / N, n = k % N;
+    double2 acc = x[k];
+    for (int j = 0; j < nj; ++j) acc = zadd(acc, zmul(coef[j * nrhs + r], Zk[(long long)j * zs_j + r * N + n]));
+    x[k] = acc;
+  }
+}
+
+// out = b - out (residual from out = K x)
+__global__ void k_resid(long long n, const double2* __restrict__ b, double2* __restrict__ out) {
+  GRID_STRIDE(i, n) out[i] = zsub(b[i], out[i]);
+}
+
+// rhs[r] = [b_r (real port vector); 0]
+__global__ void k_port_rhs(int nrhs, long long N, int CK, const double* __restrict__ bport,
+                           double2* __restrict__ rhs) {
+  GRID_STRIDE(k, N * nrhs) {
+    const long long r = k / N, n = k % N;
+    rhs[k] = n < CK ? make_double2(bport[r * CK + n], 0.0) : make_double2(0, 0);
+  }
+}
+
+__global__ void k_copy(long long n, const double2* __restrict__ a, double2* __restrict__ b) {
+  GRID_STRIDE(i, n) b[i] = a[i];
+}
+__global__ void k_zero(long long n, double2* __restrict__ a) {
+  GRID_STRIDE(i, n) a[i] = make_double2(0, 0);
+}
+
+// Y[q][p] = b_q^T I_p (no conjugation), partial sums per block
+__global__ void __launch_bounds__(256) k_ydot(int CK, int nports, long long N, const double* __restrict__ bport,
+                                              const double2* __restrict__ X, double2* __restrict__ part) {
+  __shared__ double2 sh[256];
+  const int g = blockIdx.y;
+  const int q = g / nports, pp = g % nports;
+  double2 acc = make_double2(0, 0);
+  for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < CK; k += (long long)gridDim.x * 256)
+    acc = zadd(acc, zscale(X[pp * N + k], bport[(long long)q * CK + k]));
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = zadd(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(long long)g * gridDim.x + blockIdx.x] = sh[0];
+}
+
+}  // namespace svh
+
+// ======================================================================
+// host side
+// ======================================================================
+namespace svh {
+
+namespace {
+
+svh_status sfail(svh_problem* p, svh_status st, const std::string& m) {
+  p->err = m;
+  return st;
+}
+
+#define SCHK(call)                                                                         \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return sfail(p, e_ == hipErrorOutOfMemory ? SVH_ENOMEM : SVH_EHIP,                   \
+                   std::string(#call) + ": " + hipGetErrorString(e_));                     \
+  } while (0)
+
+template <typename T>
+hipError_t up(T** dst, const T* src, size_t n) {
+  if (*dst) (void)hipFree(*dst);
+  *dst = nullptr;
+  if (n == 0) return hipSuccess;
+  hipError_t e = hipMalloc(dst, n * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+}
+
+template <typename T>
+void fr(T*& ptr) {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+}
+
+int nblocks(long long n) {
+  long long b = (n + 255) / 256;
+  return (int)std::max(1LL, std::min(b, 8192LL));
+}
+
+constexpr int kDotBlocks = 256;
+
+struct SolveWs {
+  double2 *V, *Zk, *W, *Rhs, *E, *R, *Zp, *P, *Q, *Bs, *U, *part, *h, *h2, *nrm, *rho, *rhon, *pq;
+  double *alpha, *beta;
+  void* mv;
+  size_t mv_bytes;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Carves the caller's workspace; returns the bytes needed (ws may be null).
+size_t carve(const svh_problem* p, int restart, char* ws, SolveWs* w) {
+  const long long CK = (long long)p->C * p->nvox, M = p->topo.M, N = CK + M;
+  const int nr = std::max(1, p->nports);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* q = ws ? ws + off : nullptr;
+    off += align256(bytes);
+    return q;
+  };
+  const size_t z = sizeof(double2);
+  char* V = take((size_t)(restart + 1) * nr * N * z);
+  char* Zk = take((size_t)restart * nr * N * z);
+  char* W = take((size_t)nr * N * z);
+  char* Rhs = take((size_t)nr * N * z);
+  char* E = take((size_t)nr * M * z);
+  char* R = take((size_t)nr * M * z);
+  char* Zp = take((size_t)nr * M * z);
+  char* P = take((size_t)nr * M * z);
+  char* Q = take((size_t)nr * M * z);
+  char* Bs = take((size_t)nr * M * z);
+  char* U = take((size_t)nr * CK * z);
+  char* part = take((size_t)kDotBlocks * (restart + 1) * nr * z);
+  char* h = take((size_t)(restart + 2) * nr * z);
+  char* h2 = take((size_t)(restart + 2) * nr * z);
+  char* nrm = take((size_t)nr * z);
+  char* rho = take((size_t)nr * z);
+  char* rhon = take((size_t)nr * z);
+  char* pq = take((size_t)nr * z);
+  char* alpha = take((size_t)nr * sizeof(double));
+  char* beta = take((size_t)nr * sizeof(double));
+  const size_t mvb = svh_workspace_bytes(p, SVH_FP64, nr);
+  char* mv = take(mvb);
+  if (w) {
+    w->V = (double2*)V; w->Zk = (double2*)Zk; w->W = (double2*)W; w->Rhs = (double2*)Rhs;
+    w->E = (double2*)E; w->R = (double2*)R; w->Zp = (double2*)Zp; w->P = (double2*)P; w->Q = (double2*)Q;
+    w->Bs = (double2*)Bs; w->U = (double2*)U; w->part = (double2*)part; w->h = (double2*)h;
+    w->h2 = (double2*)h2; w->nrm = (double2*)nrm; w->rho = (double2*)rho; w->rhon = (double2*)rhon;
+    w->pq = (double2*)pq; w->alpha = (double*)alpha; w->beta = (double*)beta; w->mv = mv; w->mv_bytes = mvb;
+  }
+  return off;
+}
+
+struct Ctx {
+  svh_problem* p;
+  hipStream_t s;
+  SolveWs w;
+  int nr, CK, M, fidx, transpose;
+  long long N;
+};
+
+// out = sum over chunks of conj(X_(i,r)) Y_r into dst[(i * nr + r)]
+void mdot(Ctx& c, long long n, int ni, const double2* X, long long xs_i, long long xs_r, const double2* Y,
+          long long ys_r, double2* dst) {
+  hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks, ni * c.nr), dim3(256), 0, c.s, n, c.nr, X, xs_i, xs_r, Y, ys_r,
+                     c.w.part, 1);
+  hipLaunchKernelGGL(k_psum, dim3(ni * c.nr), dim3(256), 0, c.s, kDotBlocks, c.w.part, dst);
+}
+
+// y = K x (batched columns of length N)
+svh_status apply_K(Ctx& c, const double2* x, double2* y) {
+  svh_problem* p = c.p;
+  std::vector<int32_t> fi(c.nr, c.fidx);
+  svh_status st = matvec_impl(p, SVH_FP64, c.nr, fi.data(), x, c.N, y, c.N, c.w.mv, c.w.mv_bytes, c.s);
+  if (st != SVH_OK) return st;
+  hipLaunchKernelGGL(k_saddle_fix, dim3(nblocks((c.CK + c.M) * (long long)c.nr)), dim3(256), 0, c.s, c.nr, c.N,
+                     c.CK, c.M, p->d_cptr, p->d_crow, p->d_cval, p->d_rptr, p->d_rcol, p->d_rval, p->d_free, x, y,
+                     c.transpose);
+  SCHK(hipGetLastError());
+  return SVH_OK;
+}
+
+// out = P in (eqs. 13-15), inner PCG to rel. tolerance itol; returns iterations
+svh_status apply_P(Ctx& c, const double2* in, double2* out, double itol, int imax, int& iters) {
+  svh_problem* p = c.p;
+  const long long nM = (long long)c.M * c.nr;
+  hipLaunchKernelGGL(k_pre_rhs, dim3(nblocks(nM)), dim3(256), 0, c.s, c.nr, c.N, c.CK, c.M, p->d_rptr, p->d_rcol,
+                     p->d_rval, p->d_free, p->d_ydiag, in, c.w.E, c.transpose);
+  hipLaunchKernelGGL(k_pcg_init, dim3(nblocks(nM)), dim3(256), 0, c.s, nM, c.M, p->d_sdiag, p->d_free, c.w.E,
+                     c.w.R, c.w.Zp, c.w.P, c.w.Bs);
+  mdot(c, c.M, 1, c.w.R, 0, c.M, c.w.Zp, c.M, c.w.rho);
+  std::vector<double2> rho0(c.nr), rhoc(c.nr);
+  SCHK(hipMemcpyAsync(rho0.data(), c.w.rho, sizeof(double2) * c.nr, hipMemcpyDeviceToHost, c.s));
+  SCHK(hipStreamSynchronize(c.s));
+  iters = 0;
+  bool any = false;
+  for (int r = 0; r < c.nr; ++r) any = any || rho0[r].x > 0;
+  while (any && iters < imax) {
+    for (int k = 0; k < 16 && iters < imax; ++k, ++iters) {
+      hipLaunchKernelGGL(k_s_half, dim3(nblocks((long long)c.CK * c.nr)), dim3(256), 0, c.s, c.nr, c.CK, c.M,
+                         p->d_cptr, p->d_crow, p->d_cval, p->d_ydiag, c.w.P, c.w.U);
+      hipLaunchKernelGGL(k_s_full, dim3(nblocks(nM)), dim3(256), 0, c.s, c.nr, c.CK, c.M, p->d_rptr, p->d_rcol,
+                         p->d_rval, p->d_free, c.w.U, c.w.Q);
+      mdot(c, c.M, 1, c.w.P, 0, c.M, c.w.Q, c.M, c.w.pq);
+      hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(256), 0, c.s, c.nr, c.w.rho, c.w.pq, c.w.alpha);
+      hipLaunchKernelGGL(k_pcg_update, dim3(nblocks(nM)), dim3(256), 0, c.s, nM, c.M, p->d_sdiag, p->d_free,
+                         c.w.alpha, c.w.P, c.w.Q, c.w.Bs, c.w.R, c.w.Zp);
+      mdot(c, c.M, 1, c.w.R, 0, c.M, c.w.Zp, c.M, c.w.rhon);
+      hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(256), 0, c.s, c.nr, c.w.rho, c.w.rhon, c.w.beta);
+      hipLaunchKernelGGL(k_pcg_dir, dim3(nblocks(nM)), dim3(256), 0, c.s, nM, c.M, c.w.beta, c.w.Zp, c.w.P);
+    }
+    SCHK(hipMemcpyAsync(rhoc.data(), c.w.rho, sizeof(double2) * c.nr, hipMemcpyDeviceToHost, c.s));
+    SCHK(hipStreamSynchronize(c.s));
+    any = false;
+    for (int r = 0; r < c.nr; ++r)
+      if (rho0[r].x > 0 && std::sqrt(std::max(rhoc[r].x, 0.0) / rho0[r].x) > itol) any = true;
+  }
+  hipLaunchKernelGGL(k_pre_out, dim3(nblocks((c.CK + c.M) * (long long)c.nr)), dim3(256), 0, c.s, c.nr, c.N, c.CK,
+                     c.M, p->d_cptr, p->d_crow, p->d_cval, p->d_ydiag, in, c.w.Bs, out, c.transpose);
+  SCHK(hipGetLastError());
+  return SVH_OK;
+}
+
+// |diag Z| per basis function and the diagonal of S for frequency slot f
+svh_status prepare_diag(svh_problem* p, int f) {
+  if (p->diag_freq == f && p->d_ydiag) return SVH_OK;
+  const int K = p->nvox, CK = p->C * K, M = p->topo.M;
+  const std::complex<double> s = p->sconv[f];  // j w mu0 dx
+  const double T0 = p->T[0];
+  std::vector<double> yd(CK), sd(M, 1.0);
+  for (int a = 0; a < p->C; ++a)
+    for (int k = 0; k < K; ++k) yd[(size_t)a * K + k] = std::abs(p->cdiag_host[(size_t)f * K + k] + s * T0);
+  for (int m = 0; m < M; ++m) {
+    if (p->dirichlet[m]) continue;
+    double acc = 0;
+    for (int q = p->topo.rptr[m]; q < p->topo.rptr[m + 1]; ++q)
+      acc += p->topo.rval[q] * p->topo.rval[q] / yd[p->topo.rcol[q]];
+    sd[m] = acc > 0 ? acc : 1.0;
+  }
+  SCHK(up(&p->d_ydiag, yd.data(), yd.size()));
+  SCHK(up(&p->d_sdiag, sd.data(), sd.size()));
+  p->diag_freq = f;
+  return SVH_OK;
+}
+
+// complex Givens rotation zeroing b below a (b real >= 0)
+void givens(cd a, double b, double& cs, cd& sn, cd& r) {
+  const double aa = std::abs(a);
+  if (aa == 0) {
+    cs = 0;
+    sn = 1;
+    r = b;
+    return;
+  }
+  const double rho = std::sqrt(aa * aa + b * b);
+  cs = aa / rho;
+  sn = (a / aa) * b / rho;
+  r = (a / aa) * rho;
+}
+
+}  // namespace
+
+void free_solver(svh_problem* p) {
+  fr(p->d_cptr);
+  fr(p->d_crow);
+  fr(p->d_cval);
+  fr(p->d_rptr);
+  fr(p->d_rcol);
+  fr(p->d_rval);
+  fr(p->d_free);
+  fr(p->d_bport);
+  fr(p->d_ydiag);
+  fr(p->d_sdiag);
+}
+
+}  // namespace svh
+
+using namespace svh;
+
+extern "C" {
+
+svh_status svh_set_ports(svh_problem* p, int nports, const int32_t* plus_ptr, const int32_t* plus_faces,
+                         const int32_t* minus_ptr, const int32_t* minus_faces) {
+  if (!p) return SVH_EINVAL;
+  if (nports < 1 || nports > SVH_MAX_PORTS || !plus_ptr || !plus_faces || !minus_ptr || !minus_faces)
+    return sfail(p, SVH_EINVAL, "set_ports: bad arguments");
+  if (!p->topo_built) {
+    if (build_topology(p->K, p->vidx.data(), p->nvox, p->basis, p->topo) != 0)
+      return sfail(p, SVH_EINVAL, "set_ports: unsupported basis");
+    p->topo_built = true;
+    SCHK(up(&p->d_cptr, p->topo.cptr.data(), p->topo.cptr.size()));
+    SCHK(up(&p->d_crow, p->topo.crow.data(), p->topo.crow.size()));
+    SCHK(up(&p->d_cval, p->topo.cval.data(), p->topo.cval.size()));
+    SCHK(up(&p->d_rptr, p->topo.rptr.data(), p->topo.rptr.size()));
+    SCHK(up(&p->d_rcol, p->topo.rcol.data(), p->topo.rcol.size()));
+    SCHK(up(&p->d_rval, p->topo.rval.data(), p->topo.rval.size()));
+  }
+  const int M = p->topo.M, K = p->nvox, CK = p->C * K;
+  std::vector<char> dir(M, 0);
+  std::vector<std::vector<int>> plus(nports);
+  auto node_of = [&](int k, int face, int& m) -> bool {
+    if (k < 0 || k >= K || face < 0 || face > 5) return false;
+    m = p->topo.face_node[6 * (size_t)k + face];
+    return m >= 0;
+  };
+  for (int q = 0; q < nports; ++q) {
+    if (plus_ptr[q + 1] <= plus_ptr[q] || minus_ptr[q + 1] <= minus_ptr[q])
+      return sfail(p, SVH_EINVAL, "set_ports: every port needs + and - faces");
+    for (int i = plus_ptr[q]; i < plus_ptr[q + 1]; ++i) {
+      int m;
+      if (!node_of(plus_faces[2 * i], plus_faces[2 * i + 1], m)) return sfail(p, SVH_EINVAL, "set_ports: bad face");
+      plus[q].push_back(m);
+      dir[m] = 1;
+    }
+    for (int i = minus_ptr[q]; i < minus_ptr[q + 1]; ++i) {
+      int m;
+      if (!node_of(minus_faces[2 * i], minus_faces[2 * i + 1], m)) return sfail(p, SVH_EINVAL, "set_ports: bad face");
+      dir[m] = 1;
+    }
+  }
+  ground_floating(p->topo, dir);
+  p->dirichlet = dir;
+  p->port_plus = plus;
+  p->nports = nports;
+  // b_q = A_{q+}^T 1 (one value per basis function)
+  std::vector<char> inplus(M, 0);
+  p->bport_host.assign((size_t)nports * CK, 0.0);
+  for (int q = 0; q < nports; ++q) {
+    for (int m : plus[q]) inplus[m] = 1;
+    for (int col = 0; col < CK; ++col)
+      for (int i = p->topo.cptr[col]; i < p->topo.cptr[col + 1]; ++i)
+        if (inplus[p->topo.crow[i]]) p->bport_host[(size_t)q * CK + col] += p->topo.cval[i];
+    for (int m : plus[q]) inplus[m] = 0;
+  }
+  std::vector<uint8_t> fm(M);
+  for (int m = 0; m < M; ++m) fm[m] = dir[m] ? 0 : 1;
+  SCHK(up(&p->d_free, fm.data(), fm.size()));
+  SCHK(up(&p->d_bport, p->bport_host.data(), p->bport_host.size()));
+  p->diag_freq = -2;
+  return SVH_OK;
+}
+
+svh_status svh_solve_sizes(const svh_problem* p, int* N, int* M) {
+  if (!p || !p->topo_built) return SVH_ESTATE;
+  if (M) *M = p->topo.M;
+  if (N) *N = p->C * p->nvox + p->topo.M;
+  return SVH_OK;
+}
+
+size_t svh_solve_workspace_bytes(const svh_problem* p, svh_prec prec, int restart) {
+  if (!p || !p->topo_built || restart < 1 || prec != SVH_FP64) return 0;
+  return carve(p, restart, nullptr, nullptr) + 1024;
+}
+
+svh_status svh_solve(svh_problem* p, svh_prec prec, int freq_idx, double rre, int restart, int maxit,
+                     int transpose, void* x_dev, double* Y_host, svh_solve_info* info, void* ws, size_t ws_bytes,
+                     void* stream) {
+  if (!p) return SVH_EINVAL;
+  if (!p->topo_built || p->nports < 1) return sfail(p, SVH_ESTATE, "solve: set the ports first");
+  if (p->T.empty() || p->nfreq < 1) return sfail(p, SVH_ESTATE, "solve: set material and tensors first");
+  if (prec != SVH_FP64) return sfail(p, SVH_EINVAL, "solve: precision not supported");
+  if (freq_idx < 0 || freq_idx >= p->nfreq || !(rre > 0) || restart < 1 || maxit < 1 || !x_dev || !ws)
+    return sfail(p, SVH_EINVAL, "solve: bad arguments");
+  if (ws_bytes < svh_solve_workspace_bytes(p, prec, restart)) return sfail(p, SVH_EINVAL, "solve: workspace too small");
+  Ctx c;
+  c.p = p;
+  c.s = static_cast<hipStream_t>(stream);
+  c.nr = p->nports;
+  c.CK = p->C * p->nvox;
+  c.M = p->topo.M;
+  c.N = (long long)c.CK + c.M;
+  c.fidx = freq_idx;
+  c.transpose = transpose ? 1 : 0;
+  carve(p, restart, static_cast<char*>((void*)(((uintptr_t)ws + 255) & ~(uintptr_t)255)), &c.w);
+  svh_status st = prepare_diag(p, freq_idx);
+  if (st != SVH_OK) return st;
+  const int nr = c.nr;
+  const long long NN = c.N * nr;
+  double2* X = static_cast<double2*>(x_dev);
+  // right-hand sides and zero initial guess
+  hipLaunchKernelGGL(k_port_rhs, dim3(nblocks(NN)), dim3(256), 0, c.s, nr, c.N, c.CK, p->d_bport, c.w.Rhs);
+  hipLaunchKernelGGL(k_zero, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, X);
+  std::vector<double2> hb(nr);
+  mdot(c, c.N, 1, c.w.Rhs, 0, c.N, c.w.Rhs, c.N, c.w.nrm);
+  SCHK(hipMemcpyAsync(hb.data(), c.w.nrm, sizeof(double2) * nr, hipMemcpyDeviceToHost, c.s));
+  SCHK(hipStreamSynchronize(c.s));
+  std::vector<double> bnorm(nr);
+  for (int r = 0; r < nr; ++r) bnorm[r] = std::sqrt(hb[r].x);
+  const double itol = std::min(1e-8, rre);
+  const int imax = 20000;
+  int total = 0, inner_total = 0, restarts = 0;
+  std::vector<double> relres(nr, 1.0);
+  bool converged = false;
+  const long long vs = c.N * nr;  // stride between Krylov vectors
+  while (total < maxit) {
+    // residual r = b - K x  (first cycle: x = 0, r = b)
+    if (total == 0) {
+      hipLaunchKernelGGL(k_copy, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, c.w.Rhs, c.w.W);
+    } else {
+      if ((st = apply_K(c, X, c.w.W)) != SVH_OK) return st;
+      hipLaunchKernelGGL(k_resid, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, c.w.Rhs, c.w.W);
+    }
+    mdot(c, c.N, 1, c.w.W, 0, c.N, c.w.W, c.N, c.w.nrm);
+    std::vector<double2> hn(nr);
+    SCHK(hipMemcpyAsync(hn.data(), c.w.nrm, sizeof(double2) * nr, hipMemcpyDeviceToHost, c.s));
+    SCHK(hipStreamSynchronize(c.s));
+    std::vector<double> beta(nr);
+    bool done = true;
+    for (int r = 0; r < nr; ++r) {
+      beta[r] = std::sqrt(std::max(hn[r].x, 0.0));
+      relres[r] = bnorm[r] > 0 ? beta[r] / bnorm[r] : 0.0;
+      if (relres[r] > rre) done = false;
+    }
+    if (done) {
+      converged = true;
+      break;
+    }
+    hipLaunchKernelGGL(k_normalize, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, c.w.nrm, c.w.W, c.w.V);
+    std::vector<std::vector<cd>> H(nr, std::vector<cd>((size_t)(restart + 1) * restart, 0.0));
+    std::vector<std::vector<double>> cs(nr, std::vector<double>(restart, 0.0));
+    std::vector<std::vector<cd>> sn(nr, std::vector<cd>(restart, 0.0));
+    std::vector<std::vector<cd>> g(nr, std::vector<cd>(restart + 1, 0.0));
+    for (int r = 0; r < nr; ++r) g[r][0] = beta[r];
+    int jdone = 0;
+    std::vector<double2> hcol((size_t)(restart + 2) * nr);
+    for (int j = 0; j < restart && total < maxit; ++j) {
+      int it = 0;
+      if ((st = apply_P(c, c.w.V + j * vs, c.w.Zk + j * vs, itol, imax, it)) != SVH_OK) return st;
+      inner_total += it;
+      if ((st = apply_K(c, c.w.Zk + j * vs, c.w.W)) != SVH_OK) return st;
+      // CGS2
+      mdot(c, c.N, j + 1, c.w.V, vs, c.N, c.w.W, c.N, c.w.h);
+      hipLaunchKernelGGL(k_cgs_update, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, j + 1, c.w.V, vs, c.w.h,
+                         c.w.W);
+      mdot(c, c.N, j + 1, c.w.V, vs, c.N, c.w.W, c.N, c.w.h2);
+      hipLaunchKernelGGL(k_cgs_update, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, j + 1, c.w.V, vs, c.w.h2,
+                         c.w.W);
+      hipLaunchKernelGGL(k_add_small, dim3(1), dim3(256 * ((j + 1) * nr / 256 + 1)), 0, c.s, (j + 1) * nr, c.w.h,
+                         c.w.h2);
+      mdot(c, c.N, 1, c.w.W, 0, c.N, c.w.W, c.N, c.w.nrm);
+      hipLaunchKernelGGL(k_normalize, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, c.w.nrm, c.w.W,
+                         c.w.V + (j + 1) * vs);
+      SCHK(hipMemcpyAsync(hcol.data(), c.w.h, sizeof(double2) * (j + 1) * nr, hipMemcpyDeviceToHost, c.s));
+      SCHK(hipMemcpyAsync(hcol.data() + (size_t)(j + 1) * nr, c.w.nrm, sizeof(double2) * nr,
+                          hipMemcpyDeviceToHost, c.s));
+      SCHK(hipStreamSynchronize(c.s));
+      ++total;
+      jdone = j + 1;
+      bool all = true;
+      for (int r = 0; r < nr; ++r) {
+        std::vector<cd>& Hr = H[r];
+        for (int i = 0; i <= j; ++i) Hr[(size_t)i * restart + j] = cd(hcol[(size_t)i * nr + r].x, hcol[(size_t)i * nr + r].y);
+        double hj1 = std::sqrt(std::max(hcol[(size_t)(j + 1) * nr + r].x, 0.0));
+        for (int i = 0; i < j; ++i) {
+          const cd a = Hr[(size_t)i * restart + j], b = Hr[(size_t)(i + 1) * restart + j];
+          Hr[(size_t)i * restart + j] = cs[r][i] * a + sn[r][i] * b;
+          Hr[(size_t)(i + 1) * restart + j] = -std::conj(sn[r][i]) * a + cs[r][i] * b;
+        }
+        cd rr;
+        givens(Hr[(size_t)j * restart + j], hj1, cs[r][j], sn[r][j], rr);
+        Hr[(size_t)j * restart + j] = rr;
+        const cd gj = g[r][j];
+        g[r][j] = cs[r][j] * gj;
+        g[r][j + 1] = -std::conj(sn[r][j]) * gj;
+        relres[r] = bnorm[r] > 0 ? std::abs(g[r][j + 1]) / bnorm[r] : 0.0;
+        if (relres[r] > rre) all = false;
+      }
+      if (all) break;
+    }
+    // y = H^-1 g, x += Zk y
+    std::vector<double2> coef((size_t)jdone * nr);
+    for (int r = 0; r < nr; ++r) {
+      std::vector<cd> y(jdone);
+      for (int i = jdone - 1; i >= 0; --i) {
+        cd acc = g[r][i];
+        for (int k = i + 1; k < jdone; ++k) acc -= H[r][(size_t)i * restart + k] * y[k];
+        const cd d = H[r][(size_t)i * restart + i];
+        y[i] = std::abs(d) > 0 ? acc / d : cd(0.0);
+      }
+      for (int i = 0; i < jdone; ++i) coef[(size_t)i * nr + r] = make_double2(y[i].real(), y[i].imag());
+    }
+    SCHK(hipMemcpyAsync(c.w.h2, coef.data(), sizeof(double2) * coef.size(), hipMemcpyHostToDevice, c.s));
+    hipLaunchKernelGGL(k_combine, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, jdone, c.w.Zk, vs, c.w.h2, X);
+    ++restarts;
+    SCHK(hipStreamSynchronize(c.s));
+  }
+  // true residual
+  if ((st = apply_K(c, X, c.w.W)) != SVH_OK) return st;
+  hipLaunchKernelGGL(k_resid, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, c.w.Rhs, c.w.W);
+  mdot(c, c.N, 1, c.w.W, 0, c.N, c.w.W, c.N, c.w.nrm);
+  std::vector<double2> hn(nr);
+  SCHK(hipMemcpyAsync(hn.data(), c.w.nrm, sizeof(double2) * nr, hipMemcpyDeviceToHost, c.s));
+  // port admittance Y[q][p] = b_q^T I_p
+  std::vector<double2> yq((size_t)nr * nr);
+  hipLaunchKernelGGL(k_ydot, dim3(kDotBlocks, nr * nr), dim3(256), 0, c.s, c.CK, nr, c.N, p->d_bport, X, c.w.part);
+  hipLaunchKernelGGL(k_psum, dim3(nr * nr), dim3(256), 0, c.s, kDotBlocks, c.w.part, c.w.V);
+  SCHK(hipMemcpyAsync(yq.data(), c.w.V, sizeof(double2) * yq.size(), hipMemcpyDeviceToHost, c.s));
+  SCHK(hipStreamSynchronize(c.s));
+  double worst = 0;
+  for (int r = 0; r < nr; ++r) {
+    relres[r] = bnorm[r] > 0 ? std::sqrt(std::max(hn[r].x, 0.0)) / bnorm[r] : 0.0;
+    worst = std::max(worst, relres[r]);
+  }
+  converged = worst <= 2 * rre;  // true residual, with slack for rounding against the recurrence
+  if (Y_host)
+    for (size_t i = 0; i < yq.size(); ++i) {
+      Y_host[2 * i] = yq[i].x;
+      Y_host[2 * i + 1] = yq[i].y;
+    }
+  if (info) {
+    info->iterations = total;
+    info->restarts = restarts;
+    info->inner_iterations = inner_total;
+    info->relres = worst;
+    for (int r = 0; r < nr && r < SVH_MAX_PORTS; ++r) info->relres_port[r] = relres[r];
+    info->converged = converged ? 1 : 0;
+  }
+  return converged ? SVH_OK : SVH_ENOTCONV;
+}
+
+}  // extern "C"

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/svh.h"
+#include "host_math.h"
 
 namespace svh {
 
@@ -43,6 +44,7 @@ struct EpiParams {
   int C;              // components per right-hand side
   int K;              // non-empty voxels
   int vec0;           // first component-vector of this chunk
+  long long ldx, ldy; // element stride between right-hand sides of x and y
   int fidx[kMaxVecsPerChunk];  // frequency slot per RHS of the chunk (-1 = bare)
 };
 
@@ -101,6 +103,21 @@ struct svh_problem {
   svh::Tune tune[2];            // per precision (SVH_FP64, SVH_FP32)
   bool tucker = false;
   svh::DevTucker tk;
+  std::vector<std::complex<double>> cdiag_host;  // [nfreq][K] c / dx
+  // saddle system (eq. 7) and ports
+  bool topo_built = false;
+  svh::Topology topo;
+  int nports = 0;
+  std::vector<char> dirichlet;          // per node
+  std::vector<double> bport_host;       // [nports][C*K] port vectors A_{q+}^T 1
+  std::vector<std::vector<int>> port_plus;  // + terminal nodes per port
+  int32_t *d_cptr = nullptr, *d_crow = nullptr, *d_rptr = nullptr, *d_rcol = nullptr;
+  double *d_cval = nullptr, *d_rval = nullptr;
+  uint8_t* d_free = nullptr;
+  double* d_bport = nullptr;
+  double* d_ydiag = nullptr;  // |diag Z| per basis function (for diag_freq)
+  double* d_sdiag = nullptr;  // diagonal of the Schur complement per node
+  int diag_freq = -2;
   // per-kernel timing: one event set per enqueued chunk while enabled
   bool prof = false;
   std::vector<std::vector<hipEvent_t>> prof_events;  // [tucker0, tucker1, x, y, z, yi, xi, end]
@@ -116,6 +133,10 @@ hipError_t launch_tucker_rebuild(const svh_problem* p, bool fp32_out, bool zspac
                                  double* d_V, double* d_W, hipStream_t s);
 bool use_zdirect(const svh_problem* p);
 Geo make_geo(const svh_problem* p, size_t csize);
+void free_solver(svh_problem* p);
+// y = Z x with element strides ldx, ldy between right-hand sides.
+svh_status matvec_impl(svh_problem* p, svh_prec prec, int nrhs, const int32_t* freq_idx, const void* x,
+                       long long ldx, void* y, long long ldy, void* ws, size_t ws_bytes, hipStream_t s);
 size_t tucker_scratch_doubles(const svh_problem* p);
 hipError_t launch_to_f32(const double* in, float* out, size_t n, hipStream_t s);
 
