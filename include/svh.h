@@ -48,7 +48,9 @@ typedef enum {
   SVH_ESTATE = -5    /* call made in the wrong order (e.g. matvec before setup) */
 } svh_status;
 
-typedef enum { SVH_FP64 = 0, SVH_FP32 = 1 } svh_prec;
+/* SVH_FP32_IR (solve only): iterative refinement, FP64 residuals and
+ * updates around inner solves whose operator runs in FP32. */
+typedef enum { SVH_FP64 = 0, SVH_FP32 = 1, SVH_FP32_IR = 2 } svh_prec;
 
 typedef struct svh_problem svh_problem;
 
@@ -187,19 +189,24 @@ typedef struct {
   int iterations;        /* outer (F)GMRES steps                              */
   int restarts;          /* restart cycles                                     */
   int inner_iterations;  /* conjugate-gradient steps in the preconditioner    */
+  int refinement_steps;  /* outer refinement steps (SVH_FP32_IR)              */
   int converged;         /* 1 if every port reached the tolerance             */
   double relres;         /* largest true relative residual ||b - K x|| / ||b|| */
   double relres_port[SVH_MAX_PORTS];
 } svh_solve_info;
 
-/* Workspace bytes of svh_solve for restart length `restart` (SVH_FP64). */
+/* Workspace bytes of svh_solve for restart length `restart`. */
 size_t svh_solve_workspace_bytes(const svh_problem* p, svh_prec prec, int restart);
 
 /* Solve K x_p = [b_p; 0] for every port p (right-preconditioned flexible
  * GMRES with restart `restart`, Sec. III; the preconditioner is eq. 12 with
  * Y = |diag Z| applied through eqs. 13-15, its Schur complement solved by
  * conjugate gradients to a relative 1e-8 or rre, whichever is smaller).
- * prec: SVH_FP64.  freq_idx: frequency slot of the material.  rre: relative
+ * prec: SVH_FP64, or SVH_FP32_IR: refinement steps x += d with the residual
+ *   b - K x formed in FP64 and d from an inner flexible GMRES (relative
+ *   tolerance max(1e-6, rre)) whose Z products run in FP32 (Tucker
+ *   restoration, Krylov vectors, orthogonalisation and preconditioner stay
+ *   FP64).  freq_idx: frequency slot of the material.  rre: relative
  * residual target (the paper uses 1e-8).  maxit: cap on GMRES steps.
  * transpose != 0 solves K^T x = [b; 0] instead (adjoint system).
  * x_dev: nports columns of N complex doubles (currents, component-major as in
@@ -211,6 +218,10 @@ size_t svh_solve_workspace_bytes(const svh_problem* p, svh_prec prec, int restar
 svh_status svh_solve(svh_problem* p, svh_prec prec, int freq_idx, double rre, int restart, int maxit,
                      int transpose, void* x_dev, double* Y_host, svh_solve_info* info, void* ws_dev,
                      size_t ws_bytes, void* stream);
+
+/* Replay the conjugate-gradient iteration block of the preconditioner from a
+ * captured HIP graph (default 1) or launch it kernel by kernel (0). */
+svh_status svh_set_graphs(svh_problem* p, int enable);
 
 /* Text of the last error on this problem (never NULL). */
 const char* svh_last_error(const svh_problem* p);

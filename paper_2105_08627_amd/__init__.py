@@ -15,14 +15,14 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsvh.so")
 
-SVH_FP64, SVH_FP32 = 0, 1
+SVH_FP64, SVH_FP32, SVH_FP32_IR = 0, 1, 2
 ZSTEP = {"auto": 0, "fft": 1, "direct": 2}
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "ESTATE"}
 
 EXPORTED = [
     "svh_create", "svh_get_sizes", "svh_set_material", "svh_setup_tensors", "svh_green_toeplitz",
     "svh_get_toeplitz", "svh_tucker_compress", "svh_workspace_bytes", "svh_matvec",
-    "svh_set_zstep", "svh_autotune", "svh_set_ports", "svh_solve_sizes", "svh_solve_workspace_bytes", "svh_solve", "svh_profile_enable", "svh_profile_read", "svh_last_error", "svh_destroy",
+    "svh_set_zstep", "svh_autotune", "svh_set_ports", "svh_solve_sizes", "svh_solve_workspace_bytes", "svh_solve", "svh_set_graphs", "svh_profile_enable", "svh_profile_read", "svh_last_error", "svh_destroy",
 ]
 PROF_NAMES = ["tucker_restore", "pass_x", "pass_y", "pass_z_mul", "pass_yi", "pass_xi"]
 
@@ -38,7 +38,7 @@ MAX_PORTS = 64
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("inner_iterations", ctypes.c_int),
-                ("converged", ctypes.c_int), ("relres", ctypes.c_double),
+                ("refinement_steps", ctypes.c_int), ("converged", ctypes.c_int), ("relres", ctypes.c_double),
                 ("relres_port", ctypes.c_double * MAX_PORTS)]
 
 
@@ -64,6 +64,7 @@ def lib():
     L.svh_matvec.argtypes = [vp, i32, i32, vp, vp, vp, vp, sz, vp]
     L.svh_set_zstep.argtypes = [vp, i32]
     L.svh_set_ports.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.svh_set_graphs.argtypes = [vp, i32]
     L.svh_solve_sizes.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.svh_solve_workspace_bytes.argtypes = [vp, i32, i32]
     L.svh_solve_workspace_bytes.restype = sz
@@ -221,20 +222,25 @@ class Problem:
         self._check(lib().svh_solve_sizes(self._h, ctypes.byref(N), ctypes.byref(M)), "svh_solve_sizes")
         self.N, self.M, self.nports = N.value, M.value, len(ports)
 
+    def set_graphs(self, enable):
+        self._check(lib().svh_set_graphs(self._h, int(enable)), "svh_set_graphs")
+
     def solve(self, freq_idx, rre=1e-8, restart=50, maxit=1000, transpose=False, device="cuda", stream=None,
-              check=True):
+              check=True, refine=False):
         """Solve every port excitation; returns (X (nports, N) complex128 device
         tensor, Y admittance (nports, nports) numpy array, info dict)."""
         import torch
         X = torch.empty((self.nports, self.N), dtype=torch.complex128, device=device)
-        nb = int(lib().svh_solve_workspace_bytes(self._h, SVH_FP64, restart))
+        prec = SVH_FP32_IR if refine else SVH_FP64
+        nb = int(lib().svh_solve_workspace_bytes(self._h, prec, restart))
         ws = torch.empty(nb, dtype=torch.uint8, device=device)
         Y = np.zeros((self.nports, self.nports), dtype=np.complex128)
         info = SolveInfo()
-        st = lib().svh_solve(self._h, SVH_FP64, int(freq_idx), float(rre), int(restart), int(maxit),
+        st = lib().svh_solve(self._h, prec, int(freq_idx), float(rre), int(restart), int(maxit),
                              int(transpose), ctypes.c_void_p(X.data_ptr()), _ptr(Y), ctypes.byref(info),
                              ctypes.c_void_p(ws.data_ptr()), nb, _stream_handle(stream))
         d = {"iterations": info.iterations, "restarts": info.restarts, "inner_iterations": info.inner_iterations,
+             "refinement_steps": info.refinement_steps,
              "converged": bool(info.converged), "relres": info.relres,
              "relres_port": [info.relres_port[i] for i in range(self.nports)]}
         if st != 0 and not (st == -4 and not check):

@@ -278,6 +278,9 @@ __global__ void k_port_rhs(int nrhs, long long N, int CK, const double* __restri
   }
 }
 
+__global__ void k_add(long long n, const double2* __restrict__ a, double2* __restrict__ b) {
+  GRID_STRIDE(i, n) b[i] = zadd(b[i], a[i]);
+}
 __global__ void k_copy(long long n, const double2* __restrict__ a, double2* __restrict__ b) {
   GRID_STRIDE(i, n) b[i] = a[i];
 }
@@ -349,18 +352,20 @@ int nblocks(long long n) {
 constexpr int kDotBlocks = 256;
 
 struct SolveWs {
-  double2 *V, *Zk, *W, *Rhs, *E, *R, *Zp, *P, *Q, *Bs, *U, *part, *h, *h2, *nrm, *rho, *rhon, *pq;
+  double2 *V, *Zk, *W, *Rhs, *E, *R, *Zp, *P, *Q, *Bs, *U, *part, *h, *h2, *nrm, *rho, *rhon, *pq, *D, *Rr;
+  float2 *x32, *y32;
   double *alpha, *beta;
-  void* mv;
-  size_t mv_bytes;
+  void *mv, *mv32;
+  size_t mv_bytes, mv32_bytes;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Carves the caller's workspace; returns the bytes needed (ws may be null).
-size_t carve(const svh_problem* p, int restart, char* ws, SolveWs* w) {
+size_t carve(const svh_problem* p, int restart, svh_prec prec, char* ws, SolveWs* w) {
   const long long CK = (long long)p->C * p->nvox, M = p->topo.M, N = CK + M;
   const int nr = std::max(1, p->nports);
+  const bool ir = prec == SVH_FP32_IR;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     char* q = ws ? ws + off : nullptr;
@@ -388,14 +393,22 @@ size_t carve(const svh_problem* p, int restart, char* ws, SolveWs* w) {
   char* pq = take((size_t)nr * z);
   char* alpha = take((size_t)nr * sizeof(double));
   char* beta = take((size_t)nr * sizeof(double));
+  char* D = ir ? take((size_t)nr * N * z) : nullptr;
+  char* Rr = ir ? take((size_t)nr * N * z) : nullptr;
+  char* x32 = ir ? take((size_t)nr * CK * sizeof(float2)) : nullptr;
+  char* y32 = ir ? take((size_t)nr * CK * sizeof(float2)) : nullptr;
   const size_t mvb = svh_workspace_bytes(p, SVH_FP64, nr);
   char* mv = take(mvb);
+  const size_t mvb32 = ir ? svh_workspace_bytes(p, SVH_FP32, nr) : 0;
+  char* mv32 = ir ? take(mvb32) : nullptr;
   if (w) {
     w->V = (double2*)V; w->Zk = (double2*)Zk; w->W = (double2*)W; w->Rhs = (double2*)Rhs;
     w->E = (double2*)E; w->R = (double2*)R; w->Zp = (double2*)Zp; w->P = (double2*)P; w->Q = (double2*)Q;
     w->Bs = (double2*)Bs; w->U = (double2*)U; w->part = (double2*)part; w->h = (double2*)h;
     w->h2 = (double2*)h2; w->nrm = (double2*)nrm; w->rho = (double2*)rho; w->rhon = (double2*)rhon;
     w->pq = (double2*)pq; w->alpha = (double*)alpha; w->beta = (double*)beta; w->mv = mv; w->mv_bytes = mvb;
+    w->D = (double2*)D; w->Rr = (double2*)Rr; w->x32 = (float2*)x32; w->y32 = (float2*)y32;
+    w->mv32 = mv32; w->mv32_bytes = mvb32;
   }
   return off;
 }
@@ -406,26 +419,89 @@ struct Ctx {
   SolveWs w;
   int nr, CK, M, fidx, transpose;
   long long N;
+  bool op32 = false;      // apply Z in FP32 (refinement inner solves)
+  hipGraphExec_t pcg_graph = nullptr;  // 16 PCG iterations, replayed
+  hipGraph_t pcg_g = nullptr;
 };
 
 // out = sum over chunks of conj(X_(i,r)) Y_r into dst[(i * nr + r)]
 void mdot(Ctx& c, long long n, int ni, const double2* X, long long xs_i, long long xs_r, const double2* Y,
-          long long ys_r, double2* dst) {
-  hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks, ni * c.nr), dim3(256), 0, c.s, n, c.nr, X, xs_i, xs_r, Y, ys_r,
+          long long ys_r, double2* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks, ni * c.nr), dim3(256), 0, s, n, c.nr, X, xs_i, xs_r, Y, ys_r,
                      c.w.part, 1);
-  hipLaunchKernelGGL(k_psum, dim3(ni * c.nr), dim3(256), 0, c.s, kDotBlocks, c.w.part, dst);
+  hipLaunchKernelGGL(k_psum, dim3(ni * c.nr), dim3(256), 0, s, kDotBlocks, c.w.part, dst);
+}
+void mdot(Ctx& c, long long n, int ni, const double2* X, long long xs_i, long long xs_r, const double2* Y,
+          long long ys_r, double2* dst) {
+  mdot(c, n, ni, X, xs_i, xs_r, Y, ys_r, dst, c.s);
 }
 
-// y = K x (batched columns of length N)
+__global__ void k_to32(int nrhs, long long N, int CK, const double2* __restrict__ x, float2* __restrict__ x32) {
+  GRID_STRIDE(i, (long long)CK * nrhs) {
+    const double2 v = x[(i / CK) * N + i % CK];
+    x32[i] = make_float2((float)v.x, (float)v.y);
+  }
+}
+__global__ void k_from32(int nrhs, long long N, int CK, const float2* __restrict__ y32, double2* __restrict__ y) {
+  GRID_STRIDE(i, (long long)CK * nrhs) {
+    const float2 v = y32[i];
+    y[(i / CK) * N + i % CK] = make_double2(v.x, v.y);
+  }
+}
+
+// y = K x (batched columns of length N); the Z block in FP32 when c.op32
 svh_status apply_K(Ctx& c, const double2* x, double2* y) {
   svh_problem* p = c.p;
   std::vector<int32_t> fi(c.nr, c.fidx);
-  svh_status st = matvec_impl(p, SVH_FP64, c.nr, fi.data(), x, c.N, y, c.N, c.w.mv, c.w.mv_bytes, c.s);
-  if (st != SVH_OK) return st;
+  svh_status st;
+  if (c.op32) {
+    const long long n = (long long)c.CK * c.nr;
+    hipLaunchKernelGGL(k_to32, dim3(nblocks(n)), dim3(256), 0, c.s, c.nr, c.N, c.CK, x, c.w.x32);
+    st = matvec_impl(p, SVH_FP32, c.nr, fi.data(), c.w.x32, c.CK, c.w.y32, c.CK, c.w.mv32, c.w.mv32_bytes, c.s);
+    if (st != SVH_OK) return st;
+    hipLaunchKernelGGL(k_from32, dim3(nblocks(n)), dim3(256), 0, c.s, c.nr, c.N, c.CK, c.w.y32, y);
+  } else {
+    st = matvec_impl(p, SVH_FP64, c.nr, fi.data(), x, c.N, y, c.N, c.w.mv, c.w.mv_bytes, c.s);
+    if (st != SVH_OK) return st;
+  }
   hipLaunchKernelGGL(k_saddle_fix, dim3(nblocks((c.CK + c.M) * (long long)c.nr)), dim3(256), 0, c.s, c.nr, c.N,
                      c.CK, c.M, p->d_cptr, p->d_crow, p->d_cval, p->d_rptr, p->d_rcol, p->d_rval, p->d_free, x, y,
                      c.transpose);
   SCHK(hipGetLastError());
+  return SVH_OK;
+}
+
+constexpr int kPcgBlock = 16;  // PCG iterations per convergence check (one graph replay)
+
+// One block of kPcgBlock conjugate-gradient iterations on S b = e, enqueued on s.
+void pcg_block(Ctx& c, hipStream_t s) {
+  svh_problem* p = c.p;
+  const long long nM = (long long)c.M * c.nr;
+  for (int k = 0; k < kPcgBlock; ++k) {
+    hipLaunchKernelGGL(k_s_half, dim3(nblocks((long long)c.CK * c.nr)), dim3(256), 0, s, c.nr, c.CK, c.M,
+                       p->d_cptr, p->d_crow, p->d_cval, p->d_ydiag, c.w.P, c.w.U);
+    hipLaunchKernelGGL(k_s_full, dim3(nblocks(nM)), dim3(256), 0, s, c.nr, c.CK, c.M, p->d_rptr, p->d_rcol,
+                       p->d_rval, p->d_free, c.w.U, c.w.Q);
+    mdot(c, c.M, 1, c.w.P, 0, c.M, c.w.Q, c.M, c.w.pq, s);
+    hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(256), 0, s, c.nr, c.w.rho, c.w.pq, c.w.alpha);
+    hipLaunchKernelGGL(k_pcg_update, dim3(nblocks(nM)), dim3(256), 0, s, nM, c.M, p->d_sdiag, p->d_free,
+                       c.w.alpha, c.w.P, c.w.Q, c.w.Bs, c.w.R, c.w.Zp);
+    mdot(c, c.M, 1, c.w.R, 0, c.M, c.w.Zp, c.M, c.w.rhon, s);
+    hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(256), 0, s, c.nr, c.w.rho, c.w.rhon, c.w.beta);
+    hipLaunchKernelGGL(k_pcg_dir, dim3(nblocks(nM)), dim3(256), 0, s, nM, c.M, c.w.beta, c.w.Zp, c.w.P);
+  }
+}
+
+// Capture pcg_block once per solve call (all pointers are fixed workspace
+// buffers) on the problem's private stream; replays run on the caller's stream.
+svh_status pcg_graph(Ctx& c) {
+  svh_problem* p = c.p;
+  if (c.pcg_graph || !p->use_graphs) return SVH_OK;
+  if (!p->cap_stream) SCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  SCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+  pcg_block(c, p->cap_stream);
+  SCHK(hipStreamEndCapture(p->cap_stream, &c.pcg_g));
+  SCHK(hipGraphInstantiate(&c.pcg_graph, c.pcg_g, nullptr, nullptr, 0));
   return SVH_OK;
 }
 
@@ -444,20 +520,12 @@ svh_status apply_P(Ctx& c, const double2* in, double2* out, double itol, int ima
   iters = 0;
   bool any = false;
   for (int r = 0; r < c.nr; ++r) any = any || rho0[r].x > 0;
+  svh_status st = pcg_graph(c);
+  if (st != SVH_OK) return st;
   while (any && iters < imax) {
-    for (int k = 0; k < 16 && iters < imax; ++k, ++iters) {
-      hipLaunchKernelGGL(k_s_half, dim3(nblocks((long long)c.CK * c.nr)), dim3(256), 0, c.s, c.nr, c.CK, c.M,
-                         p->d_cptr, p->d_crow, p->d_cval, p->d_ydiag, c.w.P, c.w.U);
-      hipLaunchKernelGGL(k_s_full, dim3(nblocks(nM)), dim3(256), 0, c.s, c.nr, c.CK, c.M, p->d_rptr, p->d_rcol,
-                         p->d_rval, p->d_free, c.w.U, c.w.Q);
-      mdot(c, c.M, 1, c.w.P, 0, c.M, c.w.Q, c.M, c.w.pq);
-      hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(256), 0, c.s, c.nr, c.w.rho, c.w.pq, c.w.alpha);
-      hipLaunchKernelGGL(k_pcg_update, dim3(nblocks(nM)), dim3(256), 0, c.s, nM, c.M, p->d_sdiag, p->d_free,
-                         c.w.alpha, c.w.P, c.w.Q, c.w.Bs, c.w.R, c.w.Zp);
-      mdot(c, c.M, 1, c.w.R, 0, c.M, c.w.Zp, c.M, c.w.rhon);
-      hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(256), 0, c.s, c.nr, c.w.rho, c.w.rhon, c.w.beta);
-      hipLaunchKernelGGL(k_pcg_dir, dim3(nblocks(nM)), dim3(256), 0, c.s, nM, c.M, c.w.beta, c.w.Zp, c.w.P);
-    }
+    if (c.pcg_graph) SCHK(hipGraphLaunch(c.pcg_graph, c.s));
+    else pcg_block(c, c.s);
+    iters += kPcgBlock;
     SCHK(hipMemcpyAsync(rhoc.data(), c.w.rho, sizeof(double2) * c.nr, hipMemcpyDeviceToHost, c.s));
     SCHK(hipStreamSynchronize(c.s));
     any = false;
@@ -507,6 +575,131 @@ void givens(cd a, double b, double& cs, cd& sn, cd& r) {
   r = (a / aa) * rho;
 }
 
+struct FgmresStats {
+  int total = 0, inner = 0, restarts = 0;
+};
+
+svh_status finish(Ctx& c, svh_status st) {
+  if (c.pcg_graph) (void)hipGraphExecDestroy(c.pcg_graph);
+  if (c.pcg_g) (void)hipGraphDestroy(c.pcg_g);
+  c.pcg_graph = nullptr;
+  c.pcg_g = nullptr;
+  return st;
+}
+
+// per-column 2-norms of a batch of N-vectors
+svh_status norms(Ctx& c, const double2* v, std::vector<double>& out) {
+  svh_problem* p = c.p;
+  mdot(c, c.N, 1, v, 0, c.N, v, c.N, c.w.nrm);
+  std::vector<double2> h(c.nr);
+  SCHK(hipMemcpyAsync(h.data(), c.w.nrm, sizeof(double2) * c.nr, hipMemcpyDeviceToHost, c.s));
+  SCHK(hipStreamSynchronize(c.s));
+  out.resize(c.nr);
+  for (int r = 0; r < c.nr; ++r) out[r] = std::sqrt(std::max(h[r].x, 0.0));
+  return SVH_OK;
+}
+
+// Right-preconditioned flexible GMRES(restart) on K X = B for every column,
+// starting from the X given; stops when every column's residual estimate is
+// below rre * bnorm[r] or after maxit steps.
+svh_status fgmres(Ctx& c, const double2* B, double2* X, const std::vector<double>& bnorm, double rre, int restart,
+                  int maxit, double itol, FgmresStats& fs) {
+  svh_problem* p = c.p;
+  const int nr = c.nr;
+  const long long NN = c.N * nr;
+  const long long vs = NN;  // stride between Krylov vectors
+  const int imax = 20000;
+  svh_status st;
+  int steps = 0;
+  bool first = true;
+  while (steps < maxit) {
+    if (first) {
+      hipLaunchKernelGGL(k_copy, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, B, c.w.W);
+      hipLaunchKernelGGL(k_zero, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, X);
+      first = false;
+    } else {
+      if ((st = apply_K(c, X, c.w.W)) != SVH_OK) return st;
+      hipLaunchKernelGGL(k_resid, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, B, c.w.W);
+    }
+    std::vector<double> beta;
+    if ((st = norms(c, c.w.W, beta)) != SVH_OK) return st;
+    bool done = true;
+    for (int r = 0; r < nr; ++r)
+      if (bnorm[r] > 0 && beta[r] > rre * bnorm[r]) done = false;
+    if (done) return SVH_OK;
+    hipLaunchKernelGGL(k_normalize, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, c.w.nrm, c.w.W, c.w.V);
+    std::vector<std::vector<cd>> H(nr, std::vector<cd>((size_t)(restart + 1) * restart, 0.0));
+    std::vector<std::vector<double>> cs(nr, std::vector<double>(restart, 0.0));
+    std::vector<std::vector<cd>> sn(nr, std::vector<cd>(restart, 0.0));
+    std::vector<std::vector<cd>> g(nr, std::vector<cd>(restart + 1, 0.0));
+    for (int r = 0; r < nr; ++r) g[r][0] = beta[r];
+    int jdone = 0;
+    std::vector<double2> hcol((size_t)(restart + 2) * nr);
+    for (int j = 0; j < restart && steps < maxit; ++j) {
+      int it = 0;
+      if ((st = apply_P(c, c.w.V + j * vs, c.w.Zk + j * vs, itol, imax, it)) != SVH_OK) return st;
+      fs.inner += it;
+      if ((st = apply_K(c, c.w.Zk + j * vs, c.w.W)) != SVH_OK) return st;
+      // CGS2
+      mdot(c, c.N, j + 1, c.w.V, vs, c.N, c.w.W, c.N, c.w.h);
+      hipLaunchKernelGGL(k_cgs_update, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, j + 1, c.w.V, vs, c.w.h,
+                         c.w.W);
+      mdot(c, c.N, j + 1, c.w.V, vs, c.N, c.w.W, c.N, c.w.h2);
+      hipLaunchKernelGGL(k_cgs_update, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, j + 1, c.w.V, vs, c.w.h2,
+                         c.w.W);
+      hipLaunchKernelGGL(k_add_small, dim3(((j + 1) * nr + 255) / 256), dim3(256), 0, c.s, (j + 1) * nr, c.w.h,
+                         c.w.h2);
+      mdot(c, c.N, 1, c.w.W, 0, c.N, c.w.W, c.N, c.w.nrm);
+      hipLaunchKernelGGL(k_normalize, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, c.w.nrm, c.w.W,
+                         c.w.V + (j + 1) * vs);
+      SCHK(hipMemcpyAsync(hcol.data(), c.w.h, sizeof(double2) * (j + 1) * nr, hipMemcpyDeviceToHost, c.s));
+      SCHK(hipMemcpyAsync(hcol.data() + (size_t)(j + 1) * nr, c.w.nrm, sizeof(double2) * nr,
+                          hipMemcpyDeviceToHost, c.s));
+      SCHK(hipStreamSynchronize(c.s));
+      ++steps;
+      ++fs.total;
+      jdone = j + 1;
+      bool all = true;
+      for (int r = 0; r < nr; ++r) {
+        std::vector<cd>& Hr = H[r];
+        for (int i = 0; i <= j; ++i)
+          Hr[(size_t)i * restart + j] = cd(hcol[(size_t)i * nr + r].x, hcol[(size_t)i * nr + r].y);
+        const double hj1 = std::sqrt(std::max(hcol[(size_t)(j + 1) * nr + r].x, 0.0));
+        for (int i = 0; i < j; ++i) {
+          const cd a = Hr[(size_t)i * restart + j], b = Hr[(size_t)(i + 1) * restart + j];
+          Hr[(size_t)i * restart + j] = cs[r][i] * a + sn[r][i] * b;
+          Hr[(size_t)(i + 1) * restart + j] = -std::conj(sn[r][i]) * a + cs[r][i] * b;
+        }
+        cd rr;
+        givens(Hr[(size_t)j * restart + j], hj1, cs[r][j], sn[r][j], rr);
+        Hr[(size_t)j * restart + j] = rr;
+        const cd gj = g[r][j];
+        g[r][j] = cs[r][j] * gj;
+        g[r][j + 1] = -std::conj(sn[r][j]) * gj;
+        if (bnorm[r] > 0 && std::abs(g[r][j + 1]) > rre * bnorm[r]) all = false;
+      }
+      if (all) break;
+    }
+    // y = H^-1 g, x += Zk y
+    std::vector<double2> coef((size_t)jdone * nr);
+    for (int r = 0; r < nr; ++r) {
+      std::vector<cd> y(jdone);
+      for (int i = jdone - 1; i >= 0; --i) {
+        cd acc = g[r][i];
+        for (int k = i + 1; k < jdone; ++k) acc -= H[r][(size_t)i * restart + k] * y[k];
+        const cd d = H[r][(size_t)i * restart + i];
+        y[i] = std::abs(d) > 0 ? acc / d : cd(0.0);
+      }
+      for (int i = 0; i < jdone; ++i) coef[(size_t)i * nr + r] = make_double2(y[i].real(), y[i].imag());
+    }
+    SCHK(hipMemcpyAsync(c.w.h2, coef.data(), sizeof(double2) * coef.size(), hipMemcpyHostToDevice, c.s));
+    hipLaunchKernelGGL(k_combine, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, jdone, c.w.Zk, vs, c.w.h2, X);
+    ++fs.restarts;
+    SCHK(hipStreamSynchronize(c.s));
+  }
+  return SVH_ENOTCONV;
+}
+
 }  // namespace
 
 void free_solver(svh_problem* p) {
@@ -520,6 +713,8 @@ void free_solver(svh_problem* p) {
   fr(p->d_bport);
   fr(p->d_ydiag);
   fr(p->d_sdiag);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  p->cap_stream = nullptr;
 }
 
 }  // namespace svh
@@ -597,8 +792,8 @@ svh_status svh_solve_sizes(const svh_problem* p, int* N, int* M) {
 }
 
 size_t svh_solve_workspace_bytes(const svh_problem* p, svh_prec prec, int restart) {
-  if (!p || !p->topo_built || restart < 1 || prec != SVH_FP64) return 0;
-  return carve(p, restart, nullptr, nullptr) + 1024;
+  if (!p || !p->topo_built || restart < 1 || (prec != SVH_FP64 && prec != SVH_FP32_IR)) return 0;
+  return carve(p, restart, prec, nullptr, nullptr) + 1024;
 }
 
 svh_status svh_solve(svh_problem* p, svh_prec prec, int freq_idx, double rre, int restart, int maxit,
@@ -607,10 +802,11 @@ svh_status svh_solve(svh_problem* p, svh_prec prec, int freq_idx, double rre, in
   if (!p) return SVH_EINVAL;
   if (!p->topo_built || p->nports < 1) return sfail(p, SVH_ESTATE, "solve: set the ports first");
   if (p->T.empty() || p->nfreq < 1) return sfail(p, SVH_ESTATE, "solve: set material and tensors first");
-  if (prec != SVH_FP64) return sfail(p, SVH_EINVAL, "solve: precision not supported");
+  if (prec != SVH_FP64 && prec != SVH_FP32_IR) return sfail(p, SVH_EINVAL, "solve: precision not supported");
   if (freq_idx < 0 || freq_idx >= p->nfreq || !(rre > 0) || restart < 1 || maxit < 1 || !x_dev || !ws)
     return sfail(p, SVH_EINVAL, "solve: bad arguments");
-  if (ws_bytes < svh_solve_workspace_bytes(p, prec, restart)) return sfail(p, SVH_EINVAL, "solve: workspace too small");
+  if (ws_bytes < svh_solve_workspace_bytes(p, prec, restart))
+    return sfail(p, SVH_EINVAL, "solve: workspace too small");
   Ctx c;
   c.p = p;
   c.s = static_cast<hipStream_t>(stream);
@@ -620,125 +816,50 @@ svh_status svh_solve(svh_problem* p, svh_prec prec, int freq_idx, double rre, in
   c.N = (long long)c.CK + c.M;
   c.fidx = freq_idx;
   c.transpose = transpose ? 1 : 0;
-  carve(p, restart, static_cast<char*>((void*)(((uintptr_t)ws + 255) & ~(uintptr_t)255)), &c.w);
+  carve(p, restart, prec, static_cast<char*>((void*)(((uintptr_t)ws + 255) & ~(uintptr_t)255)), &c.w);
   svh_status st = prepare_diag(p, freq_idx);
   if (st != SVH_OK) return st;
   const int nr = c.nr;
   const long long NN = c.N * nr;
   double2* X = static_cast<double2*>(x_dev);
-  // right-hand sides and zero initial guess
   hipLaunchKernelGGL(k_port_rhs, dim3(nblocks(NN)), dim3(256), 0, c.s, nr, c.N, c.CK, p->d_bport, c.w.Rhs);
   hipLaunchKernelGGL(k_zero, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, X);
-  std::vector<double2> hb(nr);
-  mdot(c, c.N, 1, c.w.Rhs, 0, c.N, c.w.Rhs, c.N, c.w.nrm);
-  SCHK(hipMemcpyAsync(hb.data(), c.w.nrm, sizeof(double2) * nr, hipMemcpyDeviceToHost, c.s));
-  SCHK(hipStreamSynchronize(c.s));
-  std::vector<double> bnorm(nr);
-  for (int r = 0; r < nr; ++r) bnorm[r] = std::sqrt(hb[r].x);
-  const double itol = std::min(1e-8, rre);
-  const int imax = 20000;
-  int total = 0, inner_total = 0, restarts = 0;
+  std::vector<double> bnorm;
+  if ((st = norms(c, c.w.Rhs, bnorm)) != SVH_OK) return finish(c, st);
+  FgmresStats fs;
+  int ir_steps = 0;
   std::vector<double> relres(nr, 1.0);
-  bool converged = false;
-  const long long vs = c.N * nr;  // stride between Krylov vectors
-  while (total < maxit) {
-    // residual r = b - K x  (first cycle: x = 0, r = b)
-    if (total == 0) {
-      hipLaunchKernelGGL(k_copy, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, c.w.Rhs, c.w.W);
-    } else {
-      if ((st = apply_K(c, X, c.w.W)) != SVH_OK) return st;
-      hipLaunchKernelGGL(k_resid, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, c.w.Rhs, c.w.W);
+  if (prec == SVH_FP64) {
+    c.op32 = false;
+    st = fgmres(c, c.w.Rhs, X, bnorm, rre, restart, maxit, std::min(1e-8, rre), fs);
+    if (st != SVH_OK && st != SVH_ENOTCONV) return finish(c, st);
+  } else {
+    // iterative refinement: FP64 residual, FP32 operator in the inner solve
+    hipLaunchKernelGGL(k_copy, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, c.w.Rhs, c.w.Rr);
+    std::vector<double> rn = bnorm;
+    const double inner = std::max(1e-6, rre);
+    for (ir_steps = 0; ir_steps < 12 && fs.total < maxit; ++ir_steps) {
+      bool done = true;
+      for (int r = 0; r < nr; ++r)
+        if (bnorm[r] > 0 && rn[r] / bnorm[r] > rre) done = false;
+      if (done) break;
+      hipLaunchKernelGGL(k_zero, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, c.w.D);
+      c.op32 = true;
+      st = fgmres(c, c.w.Rr, c.w.D, rn, inner, restart, maxit - fs.total, std::min(1e-8, inner * 1e-2), fs);
+      if (st != SVH_OK && st != SVH_ENOTCONV) return finish(c, st);
+      hipLaunchKernelGGL(k_add, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, c.w.D, X);
+      c.op32 = false;
+      if ((st = apply_K(c, X, c.w.Rr)) != SVH_OK) return finish(c, st);
+      hipLaunchKernelGGL(k_resid, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, c.w.Rhs, c.w.Rr);
+      if ((st = norms(c, c.w.Rr, rn)) != SVH_OK) return finish(c, st);
     }
-    mdot(c, c.N, 1, c.w.W, 0, c.N, c.w.W, c.N, c.w.nrm);
-    std::vector<double2> hn(nr);
-    SCHK(hipMemcpyAsync(hn.data(), c.w.nrm, sizeof(double2) * nr, hipMemcpyDeviceToHost, c.s));
-    SCHK(hipStreamSynchronize(c.s));
-    std::vector<double> beta(nr);
-    bool done = true;
-    for (int r = 0; r < nr; ++r) {
-      beta[r] = std::sqrt(std::max(hn[r].x, 0.0));
-      relres[r] = bnorm[r] > 0 ? beta[r] / bnorm[r] : 0.0;
-      if (relres[r] > rre) done = false;
-    }
-    if (done) {
-      converged = true;
-      break;
-    }
-    hipLaunchKernelGGL(k_normalize, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, c.w.nrm, c.w.W, c.w.V);
-    std::vector<std::vector<cd>> H(nr, std::vector<cd>((size_t)(restart + 1) * restart, 0.0));
-    std::vector<std::vector<double>> cs(nr, std::vector<double>(restart, 0.0));
-    std::vector<std::vector<cd>> sn(nr, std::vector<cd>(restart, 0.0));
-    std::vector<std::vector<cd>> g(nr, std::vector<cd>(restart + 1, 0.0));
-    for (int r = 0; r < nr; ++r) g[r][0] = beta[r];
-    int jdone = 0;
-    std::vector<double2> hcol((size_t)(restart + 2) * nr);
-    for (int j = 0; j < restart && total < maxit; ++j) {
-      int it = 0;
-      if ((st = apply_P(c, c.w.V + j * vs, c.w.Zk + j * vs, itol, imax, it)) != SVH_OK) return st;
-      inner_total += it;
-      if ((st = apply_K(c, c.w.Zk + j * vs, c.w.W)) != SVH_OK) return st;
-      // CGS2
-      mdot(c, c.N, j + 1, c.w.V, vs, c.N, c.w.W, c.N, c.w.h);
-      hipLaunchKernelGGL(k_cgs_update, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, j + 1, c.w.V, vs, c.w.h,
-                         c.w.W);
-      mdot(c, c.N, j + 1, c.w.V, vs, c.N, c.w.W, c.N, c.w.h2);
-      hipLaunchKernelGGL(k_cgs_update, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, j + 1, c.w.V, vs, c.w.h2,
-                         c.w.W);
-      hipLaunchKernelGGL(k_add_small, dim3(1), dim3(256 * ((j + 1) * nr / 256 + 1)), 0, c.s, (j + 1) * nr, c.w.h,
-                         c.w.h2);
-      mdot(c, c.N, 1, c.w.W, 0, c.N, c.w.W, c.N, c.w.nrm);
-      hipLaunchKernelGGL(k_normalize, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, c.w.nrm, c.w.W,
-                         c.w.V + (j + 1) * vs);
-      SCHK(hipMemcpyAsync(hcol.data(), c.w.h, sizeof(double2) * (j + 1) * nr, hipMemcpyDeviceToHost, c.s));
-      SCHK(hipMemcpyAsync(hcol.data() + (size_t)(j + 1) * nr, c.w.nrm, sizeof(double2) * nr,
-                          hipMemcpyDeviceToHost, c.s));
-      SCHK(hipStreamSynchronize(c.s));
-      ++total;
-      jdone = j + 1;
-      bool all = true;
-      for (int r = 0; r < nr; ++r) {
-        std::vector<cd>& Hr = H[r];
-        for (int i = 0; i <= j; ++i) Hr[(size_t)i * restart + j] = cd(hcol[(size_t)i * nr + r].x, hcol[(size_t)i * nr + r].y);
-        double hj1 = std::sqrt(std::max(hcol[(size_t)(j + 1) * nr + r].x, 0.0));
-        for (int i = 0; i < j; ++i) {
-          const cd a = Hr[(size_t)i * restart + j], b = Hr[(size_t)(i + 1) * restart + j];
-          Hr[(size_t)i * restart + j] = cs[r][i] * a + sn[r][i] * b;
-          Hr[(size_t)(i + 1) * restart + j] = -std::conj(sn[r][i]) * a + cs[r][i] * b;
-        }
-        cd rr;
-        givens(Hr[(size_t)j * restart + j], hj1, cs[r][j], sn[r][j], rr);
-        Hr[(size_t)j * restart + j] = rr;
-        const cd gj = g[r][j];
-        g[r][j] = cs[r][j] * gj;
-        g[r][j + 1] = -std::conj(sn[r][j]) * gj;
-        relres[r] = bnorm[r] > 0 ? std::abs(g[r][j + 1]) / bnorm[r] : 0.0;
-        if (relres[r] > rre) all = false;
-      }
-      if (all) break;
-    }
-    // y = H^-1 g, x += Zk y
-    std::vector<double2> coef((size_t)jdone * nr);
-    for (int r = 0; r < nr; ++r) {
-      std::vector<cd> y(jdone);
-      for (int i = jdone - 1; i >= 0; --i) {
-        cd acc = g[r][i];
-        for (int k = i + 1; k < jdone; ++k) acc -= H[r][(size_t)i * restart + k] * y[k];
-        const cd d = H[r][(size_t)i * restart + i];
-        y[i] = std::abs(d) > 0 ? acc / d : cd(0.0);
-      }
-      for (int i = 0; i < jdone; ++i) coef[(size_t)i * nr + r] = make_double2(y[i].real(), y[i].imag());
-    }
-    SCHK(hipMemcpyAsync(c.w.h2, coef.data(), sizeof(double2) * coef.size(), hipMemcpyHostToDevice, c.s));
-    hipLaunchKernelGGL(k_combine, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, jdone, c.w.Zk, vs, c.w.h2, X);
-    ++restarts;
-    SCHK(hipStreamSynchronize(c.s));
   }
-  // true residual
-  if ((st = apply_K(c, X, c.w.W)) != SVH_OK) return st;
+  // true FP64 residual
+  c.op32 = false;
+  if ((st = apply_K(c, X, c.w.W)) != SVH_OK) return finish(c, st);
   hipLaunchKernelGGL(k_resid, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, c.w.Rhs, c.w.W);
-  mdot(c, c.N, 1, c.w.W, 0, c.N, c.w.W, c.N, c.w.nrm);
-  std::vector<double2> hn(nr);
-  SCHK(hipMemcpyAsync(hn.data(), c.w.nrm, sizeof(double2) * nr, hipMemcpyDeviceToHost, c.s));
+  std::vector<double> rfin;
+  if ((st = norms(c, c.w.W, rfin)) != SVH_OK) return finish(c, st);
   // port admittance Y[q][p] = b_q^T I_p
   std::vector<double2> yq((size_t)nr * nr);
   hipLaunchKernelGGL(k_ydot, dim3(kDotBlocks, nr * nr), dim3(256), 0, c.s, c.CK, nr, c.N, p->d_bport, X, c.w.part);
@@ -747,24 +868,31 @@ svh_status svh_solve(svh_problem* p, svh_prec prec, int freq_idx, double rre, in
   SCHK(hipStreamSynchronize(c.s));
   double worst = 0;
   for (int r = 0; r < nr; ++r) {
-    relres[r] = bnorm[r] > 0 ? std::sqrt(std::max(hn[r].x, 0.0)) / bnorm[r] : 0.0;
+    relres[r] = bnorm[r] > 0 ? rfin[r] / bnorm[r] : 0.0;
     worst = std::max(worst, relres[r]);
   }
-  converged = worst <= 2 * rre;  // true residual, with slack for rounding against the recurrence
+  const bool converged = worst <= 2 * rre;  // true residual, with slack for rounding
   if (Y_host)
     for (size_t i = 0; i < yq.size(); ++i) {
       Y_host[2 * i] = yq[i].x;
       Y_host[2 * i + 1] = yq[i].y;
     }
   if (info) {
-    info->iterations = total;
-    info->restarts = restarts;
-    info->inner_iterations = inner_total;
+    info->iterations = fs.total;
+    info->restarts = fs.restarts;
+    info->inner_iterations = fs.inner;
+    info->refinement_steps = ir_steps;
     info->relres = worst;
     for (int r = 0; r < nr && r < SVH_MAX_PORTS; ++r) info->relres_port[r] = relres[r];
     info->converged = converged ? 1 : 0;
   }
-  return converged ? SVH_OK : SVH_ENOTCONV;
+  return finish(c, converged ? SVH_OK : SVH_ENOTCONV);
+}
+
+svh_status svh_set_graphs(svh_problem* p, int enable) {
+  if (!p) return SVH_EINVAL;
+  p->use_graphs = enable != 0;
+  return SVH_OK;
 }
 
 }  // extern "C"

@@ -118,6 +118,8 @@ struct svh_problem {
   double* d_ydiag = nullptr;  // |diag Z| per basis function (for diag_freq)
   double* d_sdiag = nullptr;  // diagonal of the Schur complement per node
   int diag_freq = -2;
+  bool use_graphs = true;             // replay the captured PCG iteration block
+  hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
   // per-kernel timing: one event set per enqueued chunk while enabled
   bool prof = false;
   std::vector<std::vector<hipEvent_t>> prof_events;  // [tucker0, tucker1, x, y, z, yi, xi, end]

@@ -95,3 +95,44 @@ def test_adjoint_solution_identity():
     assert np.linalg.norm(Xt[:, :K3] - X[:, :K3]) <= 1e-9 * np.linalg.norm(X[:, :K3])
     assert np.linalg.norm(Xt[:, K3:] + X[:, K3:]) <= 1e-9 * np.linalg.norm(X[:, K3:])
     assert np.abs(Yt - Y).max() <= 1e-9 * np.abs(Y).max()
+
+
+def test_fp32_refinement_matches_fp64_and_oracle():
+    """FP32 operator inside FP64 iterative refinement reaches the FP64
+    tolerance; its admittance matches the FP64 solve and the dense oracle."""
+    import paper_2105_08627_amd as svh
+    dx = 0.5e-6
+    mask, ports = strips(nstrip=3, length=12, ground=True)
+    Yo, Io = _oracle(mask, ports, dx)
+    p = svh.Problem(mask, dx)
+    p.set_material([F], S0, LAM)
+    p.setup_tensors()
+    p.tucker_compress(1e-10)
+    p.set_ports(ports)
+    X64, Y64, i64 = p.solve(0, rre=1e-10, restart=30)
+    Xir, Yir, iir = p.solve(0, rre=1e-10, restart=30, refine=True)
+    print("fp64", i64, "ir", iir)
+    assert iir["converged"] and iir["refinement_steps"] >= 2
+    assert iir["relres"] <= 2e-10
+    assert np.abs(Yir - Y64).max() <= 1e-8 * np.abs(Y64).max()
+    assert np.abs(Yir - Yo).max() <= 1e-8 * np.abs(Yo).max()
+
+
+def test_graph_replay_equals_eager():
+    """The preconditioner's CG block replayed from a HIP graph (many replays
+    with eager kernels and synchronisations between them) gives bitwise the
+    same solution as launching every kernel directly."""
+    import paper_2105_08627_amd as svh
+    dx = 0.5e-6
+    mask, ports = strips(nstrip=2, length=10, ground=True)
+    p = svh.Problem(mask, dx)
+    p.set_material([F], S0, LAM)
+    p.setup_tensors()
+    p.set_ports(ports)
+    p.set_graphs(False)
+    Xe, Ye, ie = p.solve(0, rre=1e-10)
+    p.set_graphs(True)
+    for _ in range(3):
+        Xg, Yg, ig = p.solve(0, rre=1e-10)
+        assert torch.equal(Xe, Xg)
+        assert ig["inner_iterations"] == ie["inner_iterations"]
