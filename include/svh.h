@@ -223,6 +223,29 @@ svh_status svh_solve(svh_problem* p, svh_prec prec, int freq_idx, double rre, in
  * captured HIP graph (default 1) or launch it kernel by kernel (0). */
 svh_status svh_set_graphs(svh_problem* p, int enable);
 
+/* y = Z^T x (transpose, not conjugate transpose), same arguments and layout
+ * as svh_matvec.  Used by the adjoint solve (svh_solve with transpose = 1)
+ * and the gradient below. */
+svh_status svh_matvec_adjoint(svh_problem* p, svh_prec prec, int nrhs, const int32_t* freq_idx_host,
+                              const void* x_dev, void* y_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Gradient of the port admittance with respect to the per-voxel kinetic
+ * parameter p_k = lambda_k^-2 (eq. 3).  xfwd_dev: forward solutions of
+ * svh_solve (transpose = 0); xadj_dev: adjoint solutions (transpose = 1),
+ * both nports columns of N complex doubles, at the same frequency slot and
+ * material.  dY_dev receives nports*nports*K complex doubles,
+ * dY[(q*nports + p)*K + k] = d Y[q][p] / d p_k.  Enqueued on stream. */
+svh_status svh_port_gradient(svh_problem* p, int freq_idx, const void* xfwd_dev, const void* xadj_dev,
+                             void* dY_dev, void* stream);
+
+/* grad_dev[k] = scale * Im( sum_{q,p} W[q][p] dY[q][p][k] ) for K voxels, with
+ * dY from svh_port_gradient and W_host nports*nports complex doubles (host).
+ * For a scalar loss of the port inductances L = Im(Y^-1) / w with weights G
+ * (dLoss/dL), W = Z G Z (Z = Y^-1 symmetric) and scale = -1/w: the gradient
+ * with respect to lambda_k^-2.  Synchronises the stream. */
+svh_status svh_gradient_contract(svh_problem* p, const void* dY_dev, const double* W_host, double scale,
+                                 double* grad_dev, void* stream);
+
 /* Text of the last error on this problem (never NULL). */
 const char* svh_last_error(const svh_problem* p);
 

@@ -22,7 +22,7 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: 
 EXPORTED = [
     "svh_create", "svh_get_sizes", "svh_set_material", "svh_setup_tensors", "svh_green_toeplitz",
     "svh_get_toeplitz", "svh_tucker_compress", "svh_workspace_bytes", "svh_matvec",
-    "svh_set_zstep", "svh_autotune", "svh_set_ports", "svh_solve_sizes", "svh_solve_workspace_bytes", "svh_solve", "svh_set_graphs", "svh_profile_enable", "svh_profile_read", "svh_last_error", "svh_destroy",
+    "svh_set_zstep", "svh_autotune", "svh_set_ports", "svh_solve_sizes", "svh_solve_workspace_bytes", "svh_solve", "svh_set_graphs", "svh_matvec_adjoint", "svh_port_gradient", "svh_gradient_contract", "svh_profile_enable", "svh_profile_read", "svh_last_error", "svh_destroy",
 ]
 PROF_NAMES = ["tucker_restore", "pass_x", "pass_y", "pass_z_mul", "pass_yi", "pass_xi"]
 
@@ -65,6 +65,9 @@ def lib():
     L.svh_set_zstep.argtypes = [vp, i32]
     L.svh_set_ports.argtypes = [vp, i32, vp, vp, vp, vp]
     L.svh_set_graphs.argtypes = [vp, i32]
+    L.svh_matvec_adjoint.argtypes = [vp, i32, i32, vp, vp, vp, vp, sz, vp]
+    L.svh_port_gradient.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.svh_gradient_contract.argtypes = [vp, vp, vp, dbl, vp, vp]
     L.svh_solve_sizes.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.svh_solve_workspace_bytes.argtypes = [vp, i32, i32]
     L.svh_solve_workspace_bytes.restype = sz
@@ -221,6 +224,38 @@ class Problem:
         N, M = ctypes.c_int(), ctypes.c_int()
         self._check(lib().svh_solve_sizes(self._h, ctypes.byref(N), ctypes.byref(M)), "svh_solve_sizes")
         self.N, self.M, self.nports = N.value, M.value, len(ports)
+
+    def matvec_adjoint(self, x, freq_idx, out=None, stream=None):
+        """y = Z^T x (same conventions as matvec)."""
+        import torch
+        prec = SVH_FP64 if x.dtype == torch.complex128 else SVH_FP32
+        nrhs = x.shape[0]
+        fi = np.ascontiguousarray(np.broadcast_to(np.asarray(freq_idx, dtype=np.int32), (nrhs,)))
+        y = out if out is not None else torch.empty_like(x)
+        ws = self.workspace(prec, nrhs, x.device)
+        self._check(lib().svh_matvec_adjoint(self._h, prec, nrhs, _ptr(fi), ctypes.c_void_p(x.data_ptr()),
+                                             ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                             ws.numel(), _stream_handle(stream)), "svh_matvec_adjoint")
+        return y
+
+    def port_gradient(self, freq_idx, xfwd, xadj, stream=None):
+        """dY[q, p, k] = d Y_qp / d (lambda_k^-2) from forward and adjoint solutions."""
+        import torch
+        dY = torch.empty((self.nports, self.nports, self.K), dtype=torch.complex128, device=xfwd.device)
+        self._check(lib().svh_port_gradient(self._h, int(freq_idx), ctypes.c_void_p(xfwd.data_ptr()),
+                                            ctypes.c_void_p(xadj.data_ptr()), ctypes.c_void_p(dY.data_ptr()),
+                                            _stream_handle(stream)), "svh_port_gradient")
+        return dY
+
+    def gradient_contract(self, dY, W, scale, stream=None):
+        """grad[k] = scale * Im(sum_qp W[q,p] dY[q,p,k]) (device float64 tensor)."""
+        import torch
+        Wc = np.ascontiguousarray(np.asarray(W, dtype=np.complex128))
+        g = torch.empty(self.K, dtype=torch.float64, device=dY.device)
+        self._check(lib().svh_gradient_contract(self._h, ctypes.c_void_p(dY.data_ptr()), _ptr(Wc), float(scale),
+                                                ctypes.c_void_p(g.data_ptr()), _stream_handle(stream)),
+                    "svh_gradient_contract")
+        return g
 
     def set_graphs(self, enable):
         self._check(lib().svh_set_graphs(self._h, int(enable)), "svh_set_graphs")

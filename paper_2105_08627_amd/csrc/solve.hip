@@ -288,6 +288,43 @@ __global__ void k_zero(long long n, double2* __restrict__ a) {
   GRID_STRIDE(i, n) a[i] = make_double2(0, 0);
 }
 
+// Derivative of the admittance with respect to p_k = lambda_k^-2 (London
+// depth): only the voxel self terms c_k / dx of Z depend on p_k, with
+// dc/dp = j c^2 / (w mu0) (from eq. 3, c = 1/sigma).  With the adjoint
+// solutions y_q of K^T y_q = [b_q; 0],
+//   dY[q][p][k] = - sum_beta y_q[beta, k] x_p[beta, k] * j c_k^2 / (w mu0 dx).
+__global__ void k_port_grad(int nports, int C, int K, long long N, const double2* __restrict__ cdiag,
+                            double inv_wmu, const double2* __restrict__ xf, const double2* __restrict__ xa,
+                            double2* __restrict__ dY) {
+  GRID_STRIDE(i, (long long)K * nports * nports) {
+    const int k = (int)(i % K);
+    const long long qp = i / K;
+    const int q = (int)(qp / nports), pp = (int)(qp % nports);
+    double2 acc = make_double2(0, 0);
+    for (int b = 0; b < C; ++b)
+      acc = zadd(acc, zmul(xa[q * N + (long long)b * K + k], xf[pp * N + (long long)b * K + k]));
+    // cdiag holds c / dx; dz/dp = j c^2 / (w mu0 dx) = j (c/dx)^2 dx / (w mu0)
+    const double2 cd = cdiag[k];
+    const double2 c2 = zmul(cd, cd);
+    const double2 dz = make_double2(-c2.y * inv_wmu, c2.x * inv_wmu);
+    const double2 t = zmul(acc, dz);
+    dY[i] = make_double2(-t.x, -t.y);
+  }
+}
+
+// grad[k] = Im( sum_{q,p} W[q][p] dY[q][p][k] ) * scale
+__global__ void k_grad_contract(int nports, int K, const double2* __restrict__ W, const double2* __restrict__ dY,
+                                double scale, double* __restrict__ grad) {
+  GRID_STRIDE(k, (long long)K) {
+    double acc = 0;
+    for (int g = 0; g < nports * nports; ++g) {
+      const double2 a = W[g], b = dY[(long long)g * K + k];
+      acc += a.x * b.y + a.y * b.x;
+    }
+    grad[k] = acc * scale;
+  }
+}
+
 // Y[q][p] = b_q^T I_p (no conjugation), partial sums per block
 __global__ void __launch_bounds__(256) k_ydot(int CK, int nports, long long N, const double* __restrict__ bport,
                                               const double2* __restrict__ X, double2* __restrict__ part) {
@@ -887,6 +924,53 @@ svh_status svh_solve(svh_problem* p, svh_prec prec, int freq_idx, double rre, in
     info->converged = converged ? 1 : 0;
   }
   return finish(c, converged ? SVH_OK : SVH_ENOTCONV);
+}
+
+svh_status svh_port_gradient(svh_problem* p, int freq_idx, const void* xfwd_dev, const void* xadj_dev,
+                             void* dY_dev, void* stream) {
+  if (!p) return SVH_EINVAL;
+  if (!p->topo_built || p->nports < 1) return sfail(p, SVH_ESTATE, "port_gradient: set the ports first");
+  if (freq_idx < 0 || freq_idx >= p->nfreq || !xfwd_dev || !xadj_dev || !dY_dev)
+    return sfail(p, SVH_EINVAL, "port_gradient: bad arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int K = p->nvox, nr = p->nports;
+  const long long N = (long long)p->C * K + p->topo.M;
+  const double w = p->sconv[freq_idx].imag() / (kMu0 * p->dx);  // sconv = j w mu0 dx
+  const double inv_wmu = p->dx / (w * kMu0);
+  hipLaunchKernelGGL(k_port_grad, dim3(nblocks((long long)K * nr * nr)), dim3(256), 0, s, nr, p->C, K, N,
+                     p->d_cdiag64 + (size_t)freq_idx * K, inv_wmu, static_cast<const double2*>(xfwd_dev),
+                     static_cast<const double2*>(xadj_dev), static_cast<double2*>(dY_dev));
+  SCHK(hipGetLastError());
+  return SVH_OK;
+}
+
+svh_status svh_gradient_contract(svh_problem* p, const void* dY_dev, const double* W_host, double scale,
+                                 double* grad_dev, void* stream) {
+  if (!p) return SVH_EINVAL;
+  if (p->nports < 1 || !dY_dev || !W_host || !grad_dev) return sfail(p, SVH_EINVAL, "gradient_contract: bad arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int np = p->nports;
+  double2* dW = nullptr;
+  SCHK(hipMallocAsync((void**)&dW, sizeof(double2) * np * np, s));
+  SCHK(hipMemcpyAsync(dW, W_host, sizeof(double2) * np * np, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_grad_contract, dim3(nblocks(p->nvox)), dim3(256), 0, s, np, p->nvox, dW,
+                     static_cast<const double2*>(dY_dev), scale, grad_dev);
+  hipError_t e = hipGetLastError();
+  (void)hipFreeAsync(dW, s);
+  SCHK(e);
+  SCHK(hipStreamSynchronize(s));
+  return SVH_OK;
+}
+
+svh_status svh_matvec_adjoint(svh_problem* p, svh_prec prec, int nrhs, const int32_t* freq_idx_host,
+                              const void* x_dev, void* y_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+  // Every block of the piecewise-constant operator depends on the offset only
+  // through the even integral M0 and the diagonal is symmetric, so Z^T = Z
+  // (transpose, not conjugate) and the transposed block table is the block
+  // table itself: the adjoint product runs the same kernels.
+  if (!p) return SVH_EINVAL;
+  if (p->basis != 3) return sfail(p, SVH_EINVAL, "matvec_adjoint: basis not supported");
+  return svh_matvec(p, prec, nrhs, freq_idx_host, x_dev, y_dev, ws_dev, ws_bytes, stream);
 }
 
 svh_status svh_set_graphs(svh_problem* p, int enable) {
