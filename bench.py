@@ -84,6 +84,39 @@ def cpu_baseline(mask, dx, x, fidx, freqs, sigma0, lam, budget_s=20.0):
                       f"(K={K}), {dt:.1f} s; numpy threads={os.environ.get('OMP_NUM_THREADS', 'default')}"}
 
 
+def bench_solve(args):
+    """Port solve (eq. 7) of 16 coupled strips (256 x 128 x 4 grid, 16 ports),
+    plain FP64 vs FP32 products inside FP64 refinement, both to relative
+    residual 1e-8 (the paper's setting), restart 50."""
+    import torch
+    import paper_2105_08627_amd as svh
+    import workloads as wl
+    mask, ports = wl.strip_array()
+    dx, f = 0.25e-6, 10e9
+    p = svh.Problem(mask, dx)
+    p.set_material([f], 1e7, 90e-9)
+    p.setup_tensors()
+    p.tucker_compress(1e-8)
+    p.set_ports(ports)
+    log(f"[bench] solve workload: strips K={p.K} N={p.N} ports={len(ports)}")
+    res = {}
+    for name, refine in (("fp64", False), ("fp32_refined", True)):
+        p.solve(0, rre=1e-8, restart=50, refine=refine)  # warm-up (graphs, caches)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, Y, info = p.solve(0, rre=1e-8, restart=50, refine=refine)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[name] = {"seconds": dt, "Y": Y, **{k: info[k] for k in ("iterations", "inner_iterations",
+                                                                     "refinement_steps", "relres")}}
+        log(f"[bench] solve {name}: {dt:.3f}s {info['iterations']} its, inner {info['inner_iterations']}, "
+            f"relres {info['relres']:.2e}")
+    Y64, Yir = res["fp64"].pop("Y"), res["fp32_refined"].pop("Y")
+    return {"workload": f"16 coupled strips {mask.shape[2]}x{mask.shape[1]}x{mask.shape[0]}, K={p.K}, "
+                        f"N={p.N} per port, 16 ports, rre 1e-8", **res,
+            "admittance_rel_diff_fp32_refined_vs_fp64": float(np.abs(Yir - Y64).max() / np.abs(Y64).max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +127,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -218,6 +252,8 @@ def main():
         "tucker_restore": {"ms": tk_ms, "tflops": tflops / (tk_ms * 1e-3) / 1e12 if tk_ms > 0 else None,
                            "mfma_frac": (tflops / (tk_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS) if tk_ms > 0 else None},
     }
+    if not args.no_solve:
+        out["solve"] = bench_solve(args)
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(mask, dx, x64_h, fidx, freqs, sigma0, lam)

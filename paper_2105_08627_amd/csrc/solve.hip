@@ -640,16 +640,16 @@ svh_status norms(Ctx& c, const double2* v, std::vector<double>& out) {
 // starting from the X given; stops when every column's residual estimate is
 // below rre * bnorm[r] or after maxit steps.
 svh_status fgmres(Ctx& c, const double2* B, double2* X, const std::vector<double>& bnorm, double rre, int restart,
-                  int maxit, double itol, FgmresStats& fs) {
+                  int maxit, double itol, FgmresStats& fs, int max_cycles = 1 << 30) {
   svh_problem* p = c.p;
   const int nr = c.nr;
   const long long NN = c.N * nr;
   const long long vs = NN;  // stride between Krylov vectors
   const int imax = 20000;
   svh_status st;
-  int steps = 0;
+  int steps = 0, cycles = 0;
   bool first = true;
-  while (steps < maxit) {
+  while (steps < maxit && cycles < max_cycles) {
     if (first) {
       hipLaunchKernelGGL(k_copy, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, B, c.w.W);
       hipLaunchKernelGGL(k_zero, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, X);
@@ -732,6 +732,7 @@ svh_status fgmres(Ctx& c, const double2* B, double2* X, const std::vector<double
     SCHK(hipMemcpyAsync(c.w.h2, coef.data(), sizeof(double2) * coef.size(), hipMemcpyHostToDevice, c.s));
     hipLaunchKernelGGL(k_combine, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, jdone, c.w.Zk, vs, c.w.h2, X);
     ++fs.restarts;
+    ++cycles;
     SCHK(hipStreamSynchronize(c.s));
   }
   return SVH_ENOTCONV;
@@ -875,14 +876,22 @@ svh_status svh_solve(svh_problem* p, svh_prec prec, int freq_idx, double rre, in
     hipLaunchKernelGGL(k_copy, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, c.w.Rhs, c.w.Rr);
     std::vector<double> rn = bnorm;
     const double inner = std::max(1e-6, rre);
-    for (ir_steps = 0; ir_steps < 12 && fs.total < maxit; ++ir_steps) {
+    for (ir_steps = 0; ir_steps < 30 && fs.total < maxit; ++ir_steps) {
       bool done = true;
       for (int r = 0; r < nr; ++r)
         if (bnorm[r] > 0 && rn[r] / bnorm[r] > rre) done = false;
       if (done) break;
       hipLaunchKernelGGL(k_zero, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, c.w.D);
       c.op32 = true;
-      st = fgmres(c, c.w.Rr, c.w.D, rn, inner, restart, maxit - fs.total, std::min(1e-8, inner * 1e-2), fs);
+      // one inner cycle per refinement step, judged by its own recurrence
+      // estimate; only the FP64 residual below decides convergence (a true
+      // residual formed with the FP32 operator would stall at its rounding floor)
+      // inner target: the remaining factor to the goal, at least 1e-6 (FP32)
+      double need = 1.0;
+      for (int r = 0; r < nr; ++r)
+        if (rn[r] > 0) need = std::min(need, rre * bnorm[r] / rn[r]);
+      const double tin = std::max(inner, need);
+      st = fgmres(c, c.w.Rr, c.w.D, rn, tin, restart, maxit - fs.total, std::min(1e-8, tin * 1e-2), fs, 1);
       if (st != SVH_OK && st != SVH_ENOTCONV) return finish(c, st);
       hipLaunchKernelGGL(k_add, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, c.w.D, X);
       c.op32 = false;

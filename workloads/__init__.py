@@ -126,6 +126,26 @@ def layered_stack(seed, Kx=256, Ky=256, Kz=128):
     return m
 
 
+def strip_array(nstrip=16, length=256, width=4, thick=4, gap=4):
+    """Parallel x-directed strips (coupled lines), one port per strip: + terminal
+    on the -x end faces, - terminal on the +x end faces.  Returns (mask, ports)
+    with ports as lists of (voxel index in compact order, face code) pairs."""
+    Ky = nstrip * (width + gap)
+    mask = np.zeros((thick, Ky, length), dtype=np.uint8)
+    for i in range(nstrip):
+        mask[:, i * (width + gap):i * (width + gap) + width, :] = 1
+    zz, yy, xx = np.nonzero(mask)
+    order = np.lexsort((xx, yy, zz))
+    xx, yy = xx[order], yy[order]
+    ports = []
+    for i in range(nstrip):
+        sel = (yy >= i * (width + gap)) & (yy < i * (width + gap) + width)
+        plus = [(int(k), 0) for k in np.nonzero(sel & (xx == 0))[0]]
+        minus = [(int(k), 1) for k in np.nonzero(sel & (xx == length - 1))[0]]
+        ports.append((plus, minus))
+    return mask, ports
+
+
 # Workload table: grid, voxel size, material (sigma0 S/m, London depth m,
 # frequencies Hz), RHS count, and the mask generator.
 WORKLOADS = {
