@@ -5,22 +5,25 @@
  * equation for superconducting structures (SuperVoxHenry, arXiv 2105.08627):
  * eq. 1 (VIE with the two-fluid conductivity of eq. 3), discretised with the
  * piecewise-constant basis of eq. 4 (three current components per voxel),
- * whose block matrix (eq. 8) is applied through the FFT product of eq. 9 with
- * the circulant tensors rebuilt from their Tucker factors (eqs. 10-11,
- * Algorithm 1, Sec. II.B.2).
+ * optionally with the two piecewise-linear functions of eqs. 5-6 (five per
+ * voxel), whose block matrix (eq. 8) is applied through the FFT product of
+ * eq. 9 with the circulant tensors rebuilt from their Tucker factors
+ * (eqs. 10-11, Algorithm 1, Sec. II.B.2).
  *
  * Conventions used by every entry point
  *  - Voxels of the Kx x Ky x Kz grid are indexed x fastest, then y, then z.
  *    The K non-empty voxels (mask != 0) are numbered in that order.
  *  - Complex numbers are interleaved (re, im); FP64 entry points take
  *    double pairs, FP32 entry points float pairs.
- *  - A current vector holds C = 3 components, component-major:
- *    [I^x (K values); I^y (K); I^z (K)] (eq. 7).  A batch of nrhs vectors is
- *    stored back to back: element (rhs, comp, k) at (rhs*C + comp)*K + k.
- *  - Basis functions carry total current (f^x = x_hat / dx^2), so that the
- *    voxel self term is c/dx with c = 1/sigma (text under eq. 9, eqs. 16, 22-23)
- *    and the coupling is j*w*mu0*dx times the unit-voxel Green integral
- *    (App. B scaling with the basis normalisation); mu0 = 4*pi*1e-7 H/m.
+ *  - A current vector holds C = 3 (basis 3) or C = 5 (basis 5) components,
+ *    component-major: [I^x (K values); I^y (K); I^z (K); I^2D (K); I^3D (K)]
+ *    (eq. 7).  A batch of nrhs vectors is stored back to back: element
+ *    (rhs, comp, k) at (rhs*C + comp)*K + k.
+ *  - Basis functions carry total current (f^x = x_hat / dx^2, and eqs. 5-6
+ *    divided by dx^2), so that the voxel self terms are c/dx, c/(6 dx) and
+ *    c/(2 dx) with c = 1/sigma (text under eq. 9, eqs. 16-18, 22-23) and the
+ *    coupling is j*w*mu0*dx times unit-voxel Green integrals (App. B scaling
+ *    with the basis normalisation); mu0 = 4*pi*1e-7 H/m.
  *  - Pointers named *_dev are device pointers (hipMalloc or torch CUDA
  *    tensors); *_host are host pointers read during the call only.  The
  *    library owns the problem object and its tensors; the caller owns every
@@ -57,7 +60,10 @@ typedef struct svh_problem svh_problem;
 /* Create a problem on the current HIP device.
  * Kx, Ky, Kz >= 1: voxel counts per axis (Sec. II.A: Kt = Kx*Ky*Kz).
  * dx_m > 0: voxel edge length in metres.
- * basis: 3 (piecewise-constant basis f^x, f^y, f^z of eq. 4).
+ * basis: 3 (piecewise-constant basis f^x, f^y, f^z of eq. 4) or 5 (plus the
+ *   piecewise-linear f^2D, f^3D of eqs. 5-6, which let current turn corners).
+ *   Basis 5 runs the direct z step only: svh_setup_tensors then requires at
+ *   most 32 occupied z planes with at most 64 distinct plane offsets.
  * mask_host: Kt bytes, x fastest; non-zero marks a non-empty voxel.  At least
  *   one voxel must be non-empty.
  * The FFT grid is L_i = 2 K_i when 2 K_i factors into 2s and 3s, else the
@@ -97,13 +103,30 @@ svh_status svh_green_toeplitz(int Kx, int Ky, int Kz, double* T_host);
  * (Kt doubles, offsets x fastest). */
 svh_status svh_get_toeplitz(const svh_problem* p, double* T_host);
 
+/* Copy one voxel-pair integral family computed by svh_setup_tensors (Kt
+ * doubles for offsets [0,Kx) x [0,Ky) x [0,Kz), x fastest; unit voxels,
+ * positive sign).  For source point u' and observer point u measured from
+ * their voxel centres and g = 1/(4 pi |r|) (eq. 8, App. A eqs. 19-21):
+ *   family 0  M0   = int int g
+ *   family 1-3  M1_a = int int u'_a g   (a = x, y, z; odd along a)
+ *   family 4-6  M2_a = int int u_a u'_a g
+ * Family 0 is the closed form of svh_green_toeplitz; families 1-6 (basis 5
+ * only, EINVAL otherwise) are computed by Gauss-Legendre quadrature of the
+ * overlap-weighted 3D form on the device (Duffy pyramids on the host for the
+ * offsets whose boxes touch the singular point). */
+svh_status svh_get_family(const svh_problem* p, int family, double* T_host);
+
 /* Tucker-compress the circulant spectrum (Algorithm 1, Sec. II.B.2) with
  * relative Frobenius tolerance tol >= 0 (tol/sqrt(3) per mode).  After this
  * call every matvec restores the spectrum from the Tucker factors (eq. 10)
  * instead of keeping it resident, and the dense spectrum is freed.
- * ranks_out (3 ints, may be NULL): multilinear ranks d1, d2, d3.
+ * Basis 5 compresses the spectrum of each of the seven integral families
+ * separately (each to its own relative tolerance).
+ * ranks_out (may be NULL): multilinear ranks d1, d2, d3 per family (3 ints
+ *   for basis 3, 7 x 3 ints for basis 5 in family order).
  * relerr_out (may be NULL): bound-level estimate sqrt(sum of discarded
- * squared singular values) / ||Z||_F summed over the three modes. */
+ * squared singular values) / ||Z||_F summed over the three modes (largest
+ * over the families). */
 svh_status svh_tucker_compress(svh_problem* p, double tol, int32_t* ranks_out,
                                double* relerr_out);
 
@@ -116,7 +139,7 @@ size_t svh_workspace_bytes(const svh_problem* p, svh_prec prec, int nrhs);
  * freq_idx_host[nrhs]: frequency slot (from svh_set_material) per RHS, or -1
  *   for the bare unit-voxel convolution y = T * x (no j*w*mu0*dx factor and
  *   no diagonal term).
- * x_dev, y_dev: nrhs*3*K complex values each (layout above); must not
+ * x_dev, y_dev: nrhs*C*K complex values each (layout above); must not
  *   overlap.  ws_dev: at least svh_workspace_bytes(p, prec, nrhs) bytes.
  * stream: hipStream_t on which all work is enqueued; the call does not
  *   synchronise. */
@@ -155,7 +178,8 @@ svh_status svh_profile_read(svh_problem* p, double* ms_out, int* ncalls_out);
  *                   spectrum, inverse FFT (eq. 9 literally);
  *  SVH_ZSTEP_DIRECT after the x and y transforms, the Toeplitz sum along z
  *                   over the occupied planes with the inverse z transform of
- *                   the circulant spectrum (EINVAL if more than 32 planes). */
+ *                   the circulant spectrum (EINVAL if more than 32 planes).
+ * Basis 5 accepts AUTO and DIRECT only. */
 #define SVH_ZSTEP_AUTO 0
 #define SVH_ZSTEP_FFT 1
 #define SVH_ZSTEP_DIRECT 2
@@ -166,6 +190,9 @@ svh_status svh_set_zstep(svh_problem* p, int mode);
  * non-empty voxels; A[m, (k, a)] is the current basis f^a of voxel k draws
  * from node m (+1 at its -a face, -1 at its +a face), so A I = 0 is current
  * conservation (eq. 2) and the first block row reads Z I - A^T Phi = V.
+ * The linear functions draw -1/2 through both x faces and +1/2 through both
+ * y faces (f^2D), -1/2 through the four x and y faces and +1 through both z
+ * faces (f^3D).
  * A port holds Phi = 1 on its + terminal faces and Phi = 0 on its - terminal
  * faces and on the faces of every other port.  Each conductor region without
  * a port face has one node grounded (its potential is otherwise undefined).
@@ -182,7 +209,7 @@ svh_status svh_set_zstep(svh_problem* p, int mode);
 svh_status svh_set_ports(svh_problem* p, int nports, const int32_t* plus_ptr, const int32_t* plus_faces,
                          const int32_t* minus_ptr, const int32_t* minus_faces);
 
-/* Unknowns per port column N = 3K + M and node count M (after svh_set_ports). */
+/* Unknowns per port column N = C K + M and node count M (after svh_set_ports). */
 svh_status svh_solve_sizes(const svh_problem* p, int* N, int* M);
 
 typedef struct {

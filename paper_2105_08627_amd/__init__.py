@@ -21,7 +21,7 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: 
 
 EXPORTED = [
     "svh_create", "svh_get_sizes", "svh_set_material", "svh_setup_tensors", "svh_green_toeplitz",
-    "svh_get_toeplitz", "svh_tucker_compress", "svh_workspace_bytes", "svh_matvec",
+    "svh_get_toeplitz", "svh_get_family", "svh_tucker_compress", "svh_workspace_bytes", "svh_matvec",
     "svh_set_zstep", "svh_autotune", "svh_set_ports", "svh_solve_sizes", "svh_solve_workspace_bytes", "svh_solve", "svh_set_graphs", "svh_matvec_adjoint", "svh_port_gradient", "svh_gradient_contract", "svh_profile_enable", "svh_profile_read", "svh_last_error", "svh_destroy",
 ]
 PROF_NAMES = ["tucker_restore", "pass_x", "pass_y", "pass_z_mul", "pass_yi", "pass_xi"]
@@ -58,6 +58,7 @@ def lib():
     L.svh_setup_tensors.argtypes = [vp, vp]
     L.svh_green_toeplitz.argtypes = [i32, i32, i32, vp]
     L.svh_get_toeplitz.argtypes = [vp, vp]
+    L.svh_get_family.argtypes = [vp, i32, vp]
     L.svh_tucker_compress.argtypes = [vp, dbl, vp, vp]
     L.svh_workspace_bytes.argtypes = [vp, i32, i32]
     L.svh_workspace_bytes.restype = sz
@@ -144,12 +145,23 @@ class Problem:
         self._check(lib().svh_get_toeplitz(self._h, _ptr(T)), "svh_get_toeplitz")
         return T
 
+    def family(self, f):
+        """Voxel-pair integral family f (0 M0, 1-3 M1x..M1z, 4-6 M2x..M2z), [Kz, Ky, Kx]."""
+        T = np.zeros((self.Kz, self.Ky, self.Kx))
+        self._check(lib().svh_get_family(self._h, int(f), _ptr(T)), "svh_get_family")
+        return T
+
     def tucker_compress(self, tol):
-        ranks = np.zeros(3, dtype=np.int32)
+        """Returns (ranks, relerr): ranks (d1, d2, d3) for basis 3, a 7 x 3
+        array (one row per integral family) for basis 5."""
+        nf = 7 if self.C == 5 else 1
+        ranks = np.zeros(3 * nf, dtype=np.int32)
         err = np.zeros(1)
         self._check(lib().svh_tucker_compress(self._h, float(tol), _ptr(ranks), _ptr(err)), "svh_tucker_compress")
         self._ws.clear()
-        return tuple(int(r) for r in ranks), float(err[0])
+        if nf == 1:
+            return tuple(int(r) for r in ranks), float(err[0])
+        return ranks.reshape(nf, 3), float(err[0])
 
     def workspace_bytes(self, prec, nrhs):
         return int(lib().svh_workspace_bytes(self._h, prec, nrhs))

@@ -84,12 +84,39 @@ int choose_length(int K) {
     if (supported_length(L)) return L;
 }
 
+void free_dev_tucker(DevTucker& t) {
+  dfree(t.core);
+  dfree(t.Fz);
+  for (int a = 0; a < 3; ++a) dfree(t.F[a]);
+  t = DevTucker();
+}
+
 void free_tucker(svh_problem* p) {
-  dfree(p->tk.core);
-  dfree(p->tk.Fz);
-  for (int a = 0; a < 3; ++a) dfree(p->tk.F[a]);
-  p->tk = DevTucker();
+  free_dev_tucker(p->tk);
+  for (int f = 0; f < kNFam; ++f) free_dev_tucker(p->tk5[f]);
   p->tucker = false;
+}
+
+// Parity of the seven families per axis (x, y, z): M1 of axis a is odd along a.
+const int kOdd[kNFam][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+
+// Inverse z transform of the third Tucker factor at the plane offsets dz:
+// Fz[m][c] = (1/Lz) sum_kz F3[kz][c] cos(2 pi kz dz_m / Lz) for an even
+// family, the same with sin for a family odd in z (whose spectrum is j F).
+std::vector<double> zspace_factor(const TuckerFactors& tf, int Lz, const std::vector<int>& dz, bool odd) {
+  const int d3 = tf.d[2];
+  std::vector<double> Fz(dz.size() * (size_t)d3);
+  for (size_t m = 0; m < dz.size(); ++m)
+    for (int c = 0; c < d3; ++c) {
+      long double acc = 0;
+      for (int kz = 0; kz < Lz; ++kz) {
+        const long long r = ((long long)kz * dz[m]) % Lz;
+        const long double a = 2.0L * 3.141592653589793238462643383279502884L * r / Lz;
+        acc += (long double)tf.F[2][(size_t)kz * d3 + c] * (odd ? sinl(a) : cosl(a));
+      }
+      Fz[m * d3 + c] = (double)(acc / Lz);
+    }
+  return Fz;
 }
 
 size_t vec_bytes_AB(const svh_problem* p, size_t csize) {
@@ -112,7 +139,7 @@ svh_status svh_create(svh_problem** out, int Kx, int Ky, int Kz, double dx_m, in
   if (!out) return SVH_EINVAL;
   *out = nullptr;
   if (Kx < 1 || Ky < 1 || Kz < 1 || !(dx_m > 0) || !mask_host) return SVH_EINVAL;
-  if (basis != 3) return SVH_EINVAL;
+  if (basis != 3 && basis != 5) return SVH_EINVAL;
   if (Kx > 512 || Ky > 512 || Kz > 512) return SVH_EINVAL;
   std::unique_ptr<svh_problem> up(new svh_problem());
   svh_problem* p = up.get();
@@ -121,7 +148,7 @@ svh_status svh_create(svh_problem** out, int Kx, int Ky, int Kz, double dx_m, in
   p->K[2] = Kz;
   p->dx = dx_m;
   p->basis = basis;
-  p->C = 3;
+  p->C = basis;
   HIPCHK(hipGetDevice(&p->device));
   HIPCHK(hipDeviceGetAttribute(&p->ncu, hipDeviceAttributeMultiprocessorCount, p->device));
   const size_t Kt = (size_t)Kx * Ky * Kz;
@@ -147,6 +174,28 @@ svh_status svh_create(svh_problem** out, int Kx, int Ky, int Kz, double dx_m, in
     if (zocc[z]) p->zlist.push_back(z);
   p->zslot.assign(p->L[2], -1);
   for (size_t s = 0; s < p->zlist.size(); ++s) p->zslot[p->zlist[s]] = (int32_t)s;
+  if (basis == 5 && p->zlist.size() <= (size_t)kMaxDirectPlanes) {
+    // distinct plane offsets |z_i - z_j| and the per-(i, j) slot codes of the
+    // coupled z step
+    const int nzp = (int)p->zlist.size();
+    std::vector<int> slot(Kz, -1);
+    for (int i = 0; i < nzp; ++i)
+      for (int j = 0; j < nzp; ++j) slot[std::abs(p->zlist[i] - p->zlist[j])] = 1;
+    for (int d = 0; d < Kz; ++d)
+      if (slot[d] >= 0) {
+        slot[d] = (int)p->dzset.size();
+        p->dzset.push_back(d);
+      }
+    if (p->dzset.size() <= (size_t)kMaxDz5) {
+      std::vector<uint8_t> q(32 * 32, 0);
+      for (int i = 0; i < nzp; ++i)
+        for (int j = 0; j < nzp; ++j) {
+          const int d = p->zlist[j] - p->zlist[i];
+          q[i * 32 + j] = (uint8_t)(slot[std::abs(d)] | (d < 0 ? 0x80 : 0));
+        }
+      HIPCHK(upload(&p->d_qtab, q.data(), q.size()));
+    }
+  }
   HIPCHK(upload(&p->d_vidx, p->vidx.data(), Kt));
   HIPCHK(upload(&p->d_zlist, p->zlist.data(), p->zlist.size()));
   HIPCHK(upload(&p->d_zslot, p->zslot.data(), p->zslot.size()));
@@ -214,6 +263,57 @@ svh_status svh_set_material(svh_problem* p, int nfreq, const double* f_hz, const
   return SVH_OK;
 }
 
+namespace {
+// Piecewise-linear basis: the seven family tables and their z-space kernels at
+// the occupied plane offsets.
+svh_status setup_tensors5(svh_problem* p, hipStream_t s) {
+  const int nzp = (int)p->zlist.size();
+  if (nzp > kMaxDirectPlanes || !p->d_qtab)
+    return fail(p, SVH_EINVAL, "setup_tensors: the piecewise-linear basis needs at most 32 occupied z planes "
+                               "with at most 64 distinct plane offsets");
+  const size_t Kt = (size_t)p->K[0] * p->K[1] * p->K[2];
+  const int nd = (int)p->dzset.size();
+  const size_t rows = (size_t)nd * p->K[1] * p->K[0];
+  const size_t gsz = (size_t)kNFam * nd * p->L[1] * p->L[0];
+  double *dF = nullptr, *dR = nullptr, *dT = nullptr;
+  HIPCHK(hipMalloc(&dF, kNFam * Kt * sizeof(double)));
+  hipError_t e = family_tables(p->K, dF, s);
+  p->Tf.assign(kNFam * Kt, 0.0);
+  if (e == hipSuccess) e = hipMemcpy(p->Tf.data(), dF, kNFam * Kt * sizeof(double), hipMemcpyDeviceToHost);
+  hipFree(dF);
+  HIPCHK(e);
+  // M0 from its closed form; exact zeros where an odd family vanishes
+  std::copy(p->T.begin(), p->T.end(), p->Tf.begin());
+  for (int f = 1; f <= 3; ++f) {
+    const int a = f - 1;
+    for (int z = 0; z < p->K[2]; ++z)
+      for (int y = 0; y < p->K[1]; ++y)
+        for (int x = 0; x < p->K[0]; ++x) {
+          const int d[3] = {x, y, z};
+          if (d[a] == 0) p->Tf[f * Kt + ((size_t)z * p->K[1] + y) * p->K[0] + x] = 0.0;
+        }
+  }
+  std::vector<double> hr(kNFam * rows);
+  for (int f = 0; f < kNFam; ++f)
+    for (int q = 0; q < nd; ++q)
+      std::copy(p->Tf.begin() + f * Kt + (size_t)p->dzset[q] * p->K[1] * p->K[0],
+                p->Tf.begin() + f * Kt + (size_t)(p->dzset[q] + 1) * p->K[1] * p->K[0],
+                hr.begin() + ((size_t)f * nd + q) * p->K[1] * p->K[0]);
+  HIPCHK(hipMalloc(&p->d_g5_64, gsz * sizeof(double)));
+  HIPCHK(hipMalloc(&p->d_g5_32, gsz * sizeof(float)));
+  HIPCHK(hipMalloc(&dR, hr.size() * sizeof(double)));
+  e = hipMalloc(&dT, (size_t)nd * p->K[1] * p->L[0] * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpy(dR, hr.data(), hr.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_zspace_families(p, dR, nd, p->d_g5_64, dT, s);
+  if (e == hipSuccess) e = launch_to_f32(p->d_g5_64, p->d_g5_32, gsz, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(dR);
+  if (dT) hipFree(dT);
+  HIPCHK(e);
+  return SVH_OK;
+}
+}  // namespace
+
 svh_status svh_setup_tensors(svh_problem* p, void* stream) {
   if (!p) return SVH_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -225,6 +325,14 @@ svh_status svh_setup_tensors(svh_problem* p, void* stream) {
   dfree(p->d_zhat32);
   dfree(p->d_g64);
   dfree(p->d_g32);
+  dfree(p->d_g5_64);
+  dfree(p->d_g5_32);
+  p->diag_freq = -2;
+  if (p->C == 5) {
+    const svh_status st = setup_tensors5(p, s);
+    if (st != SVH_OK) p->T.clear();
+    return st;
+  }
   const size_t Lt = (size_t)p->L[0] * p->L[1] * p->L[2];
   double *dT = nullptr, *t1 = nullptr;
   const size_t n1 = (size_t)p->K[2] * p->K[1] * p->L[0];
@@ -248,6 +356,20 @@ svh_status svh_setup_tensors(svh_problem* p, void* stream) {
   return SVH_OK;
 }
 
+svh_status svh_get_family(const svh_problem* p, int family, double* T_host) {
+  if (!p || !T_host || family < 0 || family >= kNFam) return SVH_EINVAL;
+  const size_t Kt = (size_t)p->K[0] * p->K[1] * p->K[2];
+  if (family == 0) {
+    if (p->T.empty()) return SVH_ESTATE;
+    std::memcpy(T_host, p->T.data(), Kt * sizeof(double));
+    return SVH_OK;
+  }
+  if (p->C != 5) return SVH_EINVAL;
+  if (p->Tf.size() != kNFam * Kt) return SVH_ESTATE;
+  std::memcpy(T_host, p->Tf.data() + (size_t)family * Kt, Kt * sizeof(double));
+  return SVH_OK;
+}
+
 svh_status svh_green_toeplitz(int Kx, int Ky, int Kz, double* T_host) {
   if (Kx < 1 || Ky < 1 || Kz < 1 || Kx > 4096 || Ky > 4096 || Kz > 4096 || !T_host) return SVH_EINVAL;
   green_toeplitz_m0(Kx, Ky, Kz, T_host);
@@ -265,6 +387,30 @@ svh_status svh_tucker_compress(svh_problem* p, double tol, int32_t* ranks_out, d
   if (!p) return SVH_EINVAL;
   if (!(tol >= 0)) return fail(p, SVH_EINVAL, "tucker_compress: tol must be >= 0");
   if (p->T.empty()) return fail(p, SVH_ESTATE, "tucker_compress: call svh_setup_tensors first");
+  if (p->C == 5) {
+    const size_t Kt = (size_t)p->K[0] * p->K[1] * p->K[2];
+    free_tucker(p);
+    double worst = 0;
+    for (int f = 0; f < kNFam; ++f) {
+      TuckerFactors tf;
+      if (tucker_circulant(p->K, p->L, p->Tf.data() + f * Kt, kOdd[f], tol, tf) < 0)
+        return fail(p, SVH_EINVAL, "tucker_compress: factorisation failed");
+      DevTucker& t = p->tk5[f];
+      for (int a = 0; a < 3; ++a) t.d[a] = tf.d[a];
+      HIPCHK(upload(&t.core, tf.core.data(), tf.core.size()));
+      for (int a = 0; a < 3; ++a) HIPCHK(upload(&t.F[a], tf.F[a].data(), tf.F[a].size()));
+      const std::vector<double> Fz = zspace_factor(tf, p->L[2], p->dzset, kOdd[f][2] != 0);
+      HIPCHK(upload(&t.Fz, Fz.data(), Fz.size()));
+      if (ranks_out)
+        for (int a = 0; a < 3; ++a) ranks_out[3 * f + a] = tf.d[a];
+      worst = std::max(worst, tf.relerr);
+    }
+    p->tucker = true;
+    dfree(p->d_g5_64);
+    dfree(p->d_g5_32);
+    if (relerr_out) *relerr_out = worst;
+    return SVH_OK;
+  }
   TuckerFactors tf;
   if (tucker_even_circulant(p->K, p->L, p->T.data(), tol, tf) != 0)
     return fail(p, SVH_EINVAL, "tucker_compress: zero tensor");
@@ -277,18 +423,9 @@ svh_status svh_tucker_compress(svh_problem* p, double tol, int32_t* ranks_out, d
   // z-space third factor: inverse z transform of F3 at offsets dz < Kz
   // (F3 columns are real and even in kz, so the transform is a cosine sum)
   {
-    const int Lz = p->L[2], Kz = p->K[2], d3 = tf.d[2];
-    std::vector<double> Fz((size_t)Kz * d3);
-    for (int dz = 0; dz < Kz; ++dz)
-      for (int c = 0; c < d3; ++c) {
-        long double acc = 0;
-        for (int kz = 0; kz < Lz; ++kz) {
-          const long long m = ((long long)kz * dz) % Lz;
-          acc += (long double)tf.F[2][(size_t)kz * d3 + c] *
-                 cosl(2.0L * 3.141592653589793238462643383279502884L * m / Lz);
-        }
-        Fz[(size_t)dz * d3 + c] = (double)(acc / Lz);
-      }
+    std::vector<int> dz(p->K[2]);
+    for (int d = 0; d < p->K[2]; ++d) dz[d] = d;
+    const std::vector<double> Fz = zspace_factor(tf, p->L[2], dz, false);
     HIPCHK(upload(&p->tk.Fz, Fz.data(), Fz.size()));
   }
   p->tucker = true;
@@ -307,7 +444,11 @@ size_t svh_workspace_bytes(const svh_problem* p, svh_prec prec, int nrhs) {
   const size_t cs = prec == SVH_FP64 ? sizeof(double2) : sizeof(float2);
   const int cr = chunk_rhs(p, nrhs);
   size_t b = (size_t)cr * p->C * vec_bytes_AB(p, cs);
-  if (p->tucker) {
+  if (p->tucker && p->C == 5) {
+    const size_t gsz = (size_t)kNFam * p->dzset.size() * p->L[0] * p->L[1];
+    b += ((gsz * (prec == SVH_FP64 ? sizeof(double) : sizeof(float)) + 255) & ~(size_t)255) + 256;
+    b += tucker_scratch_doubles5(p) * sizeof(double);
+  } else if (p->tucker) {
     const size_t Lt = (size_t)p->L[0] * p->L[1] * (use_zdirect(p) ? p->K[2] : p->L[2]);
     b += Lt * (prec == SVH_FP64 ? sizeof(double) : sizeof(float));
     b += tucker_scratch_doubles(p) * sizeof(double);
@@ -329,7 +470,7 @@ svh_status matvec_impl(svh_problem* p, svh_prec prec, int nrhs, const int32_t* f
                        long long ldx, void* y, long long ldy, void* ws, size_t ws_bytes, hipStream_t s) {
   if (nrhs < 1 || !freq_idx || !x || !y || !ws) return fail(p, SVH_EINVAL, "matvec: bad arguments");
   if (prec != SVH_FP64 && prec != SVH_FP32) return fail(p, SVH_EINVAL, "matvec: bad precision");
-  if (!p->tucker && !p->d_zhat64) return fail(p, SVH_ESTATE, "matvec: call svh_setup_tensors first");
+  if (!p->tucker && !p->d_zhat64 && !p->d_g5_64) return fail(p, SVH_ESTATE, "matvec: call svh_setup_tensors first");
   for (int r = 0; r < nrhs; ++r) {
     if (freq_idx[r] < -1 || freq_idx[r] >= p->nfreq)
       return fail(p, SVH_EINVAL, "matvec: frequency index out of range (set the material first)");
@@ -356,8 +497,9 @@ svh_status matvec_impl(svh_problem* p, svh_prec prec, int nrhs, const int32_t* f
   char* A = w;
   char* B = w + Abytes;
   const bool zdirect = use_zdirect(p);
-  const void* zhat = zdirect ? (dbl ? (const void*)p->d_g64 : (const void*)p->d_g32)
-                             : (dbl ? (const void*)p->d_zhat64 : (const void*)p->d_zhat32);
+  const void* zhat = p->C == 5 ? (dbl ? (const void*)p->d_g5_64 : (const void*)p->d_g5_32)
+                     : zdirect ? (dbl ? (const void*)p->d_g64 : (const void*)p->d_g32)
+                               : (dbl ? (const void*)p->d_zhat64 : (const void*)p->d_zhat32);
   std::vector<hipEvent_t> evs;
   if (p->prof) {
     const int nchunk = (nrhs + cr - 1) / cr;
@@ -373,7 +515,22 @@ svh_status matvec_impl(svh_problem* p, svh_prec prec, int nrhs, const int32_t* f
     }
     HIPCHK(hipEventRecord(evs[0], s));
   }
-  if (p->tucker) {
+  if (p->tucker && p->C == 5) {
+    // restore the seven families' z-space kernels one after another
+    char* zb = B + align(Bbytes);
+    const int nd = (int)p->dzset.size();
+    const size_t rows = (size_t)nd * p->L[0] * p->L[1];
+    const size_t gbytes = align(kNFam * rows * (dbl ? 8 : 4));
+    double* V = reinterpret_cast<double*>(zb + gbytes);
+    for (int f = 0; f < kNFam; ++f) {
+      const DevTucker& t = p->tk5[f];
+      double* Wt = V + (size_t)p->L[0] * t.d[1] * t.d[2];
+      if (reinterpret_cast<char*>(Wt + (size_t)p->L[0] * p->L[1] * t.d[2]) > w + ws_bytes)
+        return fail(p, SVH_EINVAL, "matvec: workspace too small");
+      HIPCHK(launch_tucker_rebuild_rows(p, t, t.Fz, nd, !dbl, zb + f * rows * (dbl ? 8 : 4), V, Wt, s));
+    }
+    zhat = zb;
+  } else if (p->tucker) {
     char* zb = B + align(Bbytes);
     const size_t Lt = (size_t)p->L[0] * p->L[1] * (zdirect ? p->K[2] : p->L[2]);
     double* V = reinterpret_cast<double*>(zb + align(Lt * (dbl ? 8 : 4)));
@@ -469,6 +626,8 @@ svh_status svh_set_zstep(svh_problem* p, int mode) {
   if (!p) return SVH_EINVAL;
   if (mode != SVH_ZSTEP_AUTO && mode != SVH_ZSTEP_FFT && mode != SVH_ZSTEP_DIRECT)
     return fail(p, SVH_EINVAL, "set_zstep: unknown mode");
+  if (p->C == 5 && mode == SVH_ZSTEP_FFT)
+    return fail(p, SVH_EINVAL, "set_zstep: the piecewise-linear basis runs the direct z step only");
   if (mode == SVH_ZSTEP_DIRECT && (int)p->zlist.size() > kMaxDirectPlanes)
     return fail(p, SVH_EINVAL, "set_zstep: direct z sum supports at most 32 occupied planes");
   p->zstep = mode;
@@ -527,6 +686,9 @@ void svh_destroy(svh_problem* p) {
   dfree(p->d_zhat32);
   dfree(p->d_g64);
   dfree(p->d_g32);
+  dfree(p->d_g5_64);
+  dfree(p->d_g5_32);
+  dfree(p->d_qtab);
   free_tucker(p);
   svh::free_solver(p);
   for (auto& set : p->prof_events)

@@ -5,7 +5,10 @@
 // current the piecewise-constant basis f^a of voxel k (total current 1) draws
 // from node m into the voxel: +1 at its -a face, -1 at its +a face, so that
 // A I = 0 is current conservation (eq. 2) at every node and the first block
-// row of eq. 7 reads Z I - A^T Phi = V.
+// row of eq. 7 reads Z I - A^T Phi = V.  The linear functions of eqs. 5-6
+// (same normalisation) have zero net flux: f^2D draws -1/2 through each x face
+// and +1/2 through each y face, f^3D draws -1/2 through each of the four x
+// and y faces and +1 through each z face.
 #include <algorithm>
 #include <numeric>
 #include <vector>
@@ -28,7 +31,7 @@ struct FaceIndex {
 }  // namespace
 
 int build_topology(const int K[3], const int32_t* vidx, int nvox, int basis, Topology& t) {
-  if (basis != 3) return -1;
+  if (basis != 3 && basis != 5) return -1;
   FaceIndex fi;
   for (int a = 0; a < 3; ++a) fi.K[a] = K[a];
   fi.off[0] = 0;
@@ -85,6 +88,22 @@ int build_topology(const int K[3], const int32_t* vidx, int nvox, int basis, Top
       t.cval.push_back(-1.0);
       t.cptr[col + 1] = (int)t.crow.size();
     }
+  if (basis == 5) {
+    // face code f: axis f / 2; 2D: -1/2 on x faces, +1/2 on y faces;
+    // 3D: -1/2 on x and y faces, +1 on z faces
+    const double w2d[3] = {-0.5, 0.5, 0.0}, w3d[3] = {-0.5, -0.5, 1.0};
+    for (int b = 0; b < 2; ++b)
+      for (int k = 0; k < nvox; ++k) {
+        const int col = (3 + b) * nvox + k;
+        const double* wt = b == 0 ? w2d : w3d;
+        for (int f = 0; f < 6; ++f) {
+          if (wt[f / 2] == 0.0) continue;
+          t.crow.push_back(t.face_node[6 * (size_t)k + f]);
+          t.cval.push_back(wt[f / 2]);
+        }
+        t.cptr[col + 1] = (int)t.crow.size();
+      }
+  }
   // CSR from CSC
   t.rptr.assign(M + 1, 0);
   for (int r : t.crow) t.rptr[r + 1]++;

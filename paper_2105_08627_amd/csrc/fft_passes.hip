@@ -18,6 +18,7 @@
 // Stockham stage with radix R after Ns previous points (natural order out):
 //   in  v_r = src[j + r L/R],  twiddle  v_r *= w_L^(r (j mod Ns) L/(Ns R))
 //   R-point DFT, out dst[(j / Ns) Ns R + (j mod Ns) + r Ns].
+#include <type_traits>
 #include <utility>
 
 #include "svh_internal.h"
@@ -697,6 +698,150 @@ __global__ void __launch_bounds__(256) k_zdirect(Geo geo, int Lx, int Ly, int nz
   }
 }
 
+// ------------------------------- Z step, piecewise-linear basis (C = 5) --
+// The five components of one right-hand side couple through the blocks of
+// eq. 8.  With the xy-transformed family kernels G_f(kx, ky, z_j - z_i)
+// (source minus observer plane; M1x and M1y are j times the stored real
+// value, M1z is odd in the plane offset) and u = I2D + I3D, w = I2D - I3D,
+// twelve z convolutions per pencil give all blocks:
+//   a0..a2 = M0 * (Ix, Iy, Iz)   b0, b1 = M1x * (u, Ix)   c0, c1 = M1y * (w, Iy)
+//   d0, d1 = M1z * (I3D, Iz)     e0, e1, e2 = M2x * u, M2y * w, M2z * I3D
+//   y_x  = a0 + j b0            y_y = a1 - j c0          y_z = a2 - 2 d0
+//   y_2D = j (c1 - b1) + e0 + e1
+//   y_3D = -j (b1 + c1) + 2 d1 + e0 - e1 + 4 e2
+// (block (x, 2D) = +M1x, (2D, x) = -M1x, ... as the basis definitions of
+// eqs. 4-6 give them).  Block: W adjacent kx of one ky, RG row groups; the
+// block's kernels G_f[slot][w] sit in LDS for all right-hand sides, one
+// right-hand side's five components are staged in LDS at a time (the next
+// one is in flight in registers) and updated in place.
+template <typename T, int NZ, int RG>
+__global__ void __launch_bounds__(256) k_zdirect5(Geo geo, int Lx, int Ly, int nzp, int nd, int nrhs, int rpb,
+                                                  const uint8_t* __restrict__ qtab,
+                                                  const T* __restrict__ g5,
+                                                  typename CT<T>::t* __restrict__ B) {
+  typedef typename CT<T>::t C;
+  constexpr int W = 256 / RG;
+  constexpr int R = (NZ + RG - 1) / RG;
+  constexpr int NF = 7;
+  extern __shared__ unsigned char smem_raw[];
+  C* xs = reinterpret_cast<C*>(smem_raw);                  // [5][NZ][W]
+  T* gs = reinterpret_cast<T*>(xs + (size_t)5 * NZ * W);   // [7][nd][W]
+  const int t = threadIdx.x;
+  const int ntile = (Lx + W - 1) / W;
+  const int tile = blockIdx.x % ntile, ky = blockIdx.x / ntile;
+  const int kx0 = tile * W;
+  const int w = t % W, rg = t / W;
+  const bool valid = kx0 + w < Lx;
+  for (int e = t; e < NF * nd * W; e += 256) {
+    const int ww = e % W, fq = e / W;
+    gs[e] = kx0 + ww < Lx ? g5[((size_t)fq * Ly + ky) * Lx + kx0 + ww] : (T)0;
+  }
+  // offset-slot codes of this thread's rows, four per register
+  uint32_t pk[R][(NZ + 3) / 4];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = rg + r * RG;
+#pragma unroll
+    for (int q = 0; q < (NZ + 3) / 4; ++q) {
+      uint32_t v = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int j = 4 * q + b;
+        const uint32_t c = (i < nzp && j < nzp) ? qtab[i * 32 + j] : 0u;
+        v |= c << (8 * b);
+      }
+      pk[r][q] = v;
+    }
+  }
+  const size_t plane = (size_t)geo.pb;
+  C* base = B + (size_t)ky * geo.rp + kx0;
+  const int rbeg = blockIdx.y * rpb;
+  const int rend = min(nrhs, rbeg + rpb);
+  constexpr int NE = 5 * NZ * W;
+  constexpr int EPT = (NE + 255) / 256;
+  C pre[EPT];
+  auto fetch = [&](int rhs) {
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = t + 256 * q;
+      const int ww = e % W, j = (e / W) % NZ, c = e / (W * NZ);
+      pre[q] = (e < NE && j < nzp && kx0 + ww < Lx) ? base[((size_t)(rhs * 5 + c) * nzp + j) * plane + ww]
+                                                   : C{0, 0};
+    }
+  };
+  if (rbeg < rend) fetch(rbeg);
+  for (int rhs = rbeg; rhs < rend; ++rhs) {
+    __syncthreads();  // previous right-hand side's readers are done with xs (and gs is loaded)
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = t + 256 * q;
+      if (e < NE) xs[e] = pre[q];
+    }
+    __syncthreads();
+    if (rhs + 1 < rend) fetch(rhs + 1);
+    T acc[R][24];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int k = 0; k < 24; ++k) acc[r][k] = 0;
+#pragma unroll
+    for (int j = 0; j < NZ; ++j) {
+      if (j >= nzp) continue;
+      const C ix = xs[(0 * NZ + j) * W + w];
+      const C iy = xs[(1 * NZ + j) * W + w];
+      const C iz = xs[(2 * NZ + j) * W + w];
+      const C i2 = xs[(3 * NZ + j) * W + w];
+      const C i3 = xs[(4 * NZ + j) * W + w];
+      const C u = C{i2.x + i3.x, i2.y + i3.y};
+      const C v = C{i2.x - i3.x, i2.y - i3.y};
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t code = (pk[r][j >> 2] >> (8 * (j & 3))) & 0xffu;
+        const T* gq = gs + (code & 0x7fu) * W + w;
+        const T g0 = gq[0 * nd * W], g1x = gq[1 * nd * W], g1y = gq[2 * nd * W];
+        T g1z = gq[3 * nd * W];
+        const T g2x = gq[4 * nd * W], g2y = gq[5 * nd * W], g2z = gq[6 * nd * W];
+        if (code & 0x80u) g1z = -g1z;
+        T* a = acc[r];
+        a[0] += g0 * ix.x;  a[1] += g0 * ix.y;
+        a[2] += g0 * iy.x;  a[3] += g0 * iy.y;
+        a[4] += g0 * iz.x;  a[5] += g0 * iz.y;
+        a[6] += g1x * u.x;  a[7] += g1x * u.y;
+        a[8] += g1x * ix.x; a[9] += g1x * ix.y;
+        a[10] += g1y * v.x; a[11] += g1y * v.y;
+        a[12] += g1y * iy.x; a[13] += g1y * iy.y;
+        a[14] += g1z * i3.x; a[15] += g1z * i3.y;
+        a[16] += g1z * iz.x; a[17] += g1z * iz.y;
+        a[18] += g2x * u.x; a[19] += g2x * u.y;
+        a[20] += g2y * v.x; a[21] += g2y * v.y;
+        a[22] += g2z * i3.x; a[23] += g2z * i3.y;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = rg + r * RG;
+      if (i >= nzp || !valid) continue;
+      const T* a = acc[r];
+      // a0 = a[0,1], a1 = a[2,3], a2 = a[4,5], b0 = a[6,7], b1 = a[8,9],
+      // c0 = a[10,11], c1 = a[12,13], d0 = a[14,15], d1 = a[16,17],
+      // e0 = a[18,19], e1 = a[20,21], e2 = a[22,23]
+      const C yx = C{a[0] - a[7], a[1] + a[6]};
+      const C yy = C{a[2] + a[11], a[3] - a[10]};
+      const C yz = C{a[4] - 2 * a[14], a[5] - 2 * a[15]};
+      const C y2 = C{-(a[13] - a[9]) + a[18] + a[20], (a[12] - a[8]) + a[19] + a[21]};
+      const C y3 = C{(a[9] + a[13]) + 2 * a[16] + a[18] - a[20] + 4 * a[22],
+                     -(a[8] + a[12]) + 2 * a[17] + a[19] - a[21] + 4 * a[23]};
+      C* o = base + ((size_t)(rhs * 5) * nzp + i) * plane + w;
+      const size_t cs = (size_t)nzp * plane;
+      o[0] = yx;
+      o[cs] = yy;
+      o[2 * cs] = yz;
+      o[3 * cs] = y2;
+      o[4 * cs] = y3;
+    }
+  }
+}
+
 // --------------------------------------------------------------- Xi pass --
 template <typename C, typename T> struct XOut {
   C* __restrict__ y;                 // compact output of this component
@@ -704,6 +849,7 @@ template <typename C, typename T> struct XOut {
   const C* __restrict__ cd;          // c/dx per voxel (nullptr: bare)
   const int32_t* __restrict__ vrow;
   C scale;
+  T mass;                            // integral of the squared basis function (eqs. 9, 16-18)
   int Kx;
   bool valid;
   __device__ __forceinline__ void st(int n, C v) const {
@@ -711,7 +857,7 @@ template <typename C, typename T> struct XOut {
     const int k = vrow[n];
     if (k < 0) return;
     C o = cmul(v, scale);
-    if (cd) o = cadd(o, cmul(cd[k], x[k]));
+    if (cd) o = cadd(o, cscale(cmul(cd[k], x[k]), mass));
     y[k] = o;
   }
 };
@@ -758,8 +904,10 @@ __global__ void __launch_bounds__(256) k_pass_xi(FftPlan pl, Geo geo, int WX, in
     const C scale = f >= 0 ? cscale(sconv[f], inv_n) : C{inv_n, 0};
     const C* cd = f >= 0 ? cdiag + (size_t)f * K : nullptr;
     const int rhs = vec / ep.C, comp = vec % ep.C;
+    // 1 for the constant functions, 1/6 and 1/2 for the linear ones of eqs. 5-6
+    const T mass = comp < 3 ? (T)1 : comp == 3 ? (T)(1.0 / 6.0) : (T)0.5;
     return XOut<C, T>{y + (size_t)rhs * ep.ldy + (size_t)comp * K, x + (size_t)rhs * ep.ldx + (size_t)comp * K, cd,
-                      vidx + ((size_t)zlist[zp] * Ky + yy) * Kx, scale, Kx, valid};
+                      vidx + ((size_t)zlist[zp] * Ky + yy) * Kx, scale, mass, Kx, valid};
   };
   Lds<C, false> acc{lds, WX, pencil_pitch(Lx), w};
   run_items<P, C, +1, false>(pl, j0, ngrp * nvec, mk_in, mk_out, acc, tw);
@@ -854,7 +1002,36 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
   if (ev) hipEventRecord(ev[2], s);
   // Z step: padded FFT along z with the spectrum product, or the direct sum
   const bool zdirect = use_zdirect(p);
-  if (zdirect) {
+  if (p->C == 5) {
+    // coupled five-component direct sum; double: 8 pencils x 32 row groups
+    // (one row each), float: 16 pencils x 16 row groups
+    const int nd = (int)p->dzset.size();
+    const int nrhs = nvec / 5;
+    const int NZ = nzp <= 8 ? 8 : nzp <= 16 ? 16 : nzp <= 24 ? 24 : 32;
+    auto go = [&](auto nzt, auto rgt) {
+      constexpr int NZc = decltype(nzt)::value, RGc = decltype(rgt)::value;
+      constexpr int W = 256 / RGc;
+      const int ntile = (Lx + W - 1) / W;
+      const int nblk = ntile * Ly;
+      int rpb = nrhs;
+      while (rpb > 1 && (long long)nblk * ((nrhs + rpb - 1) / rpb) < 4096) rpb = (rpb + 1) / 2;
+      dim3 grid(nblk, (nrhs + rpb - 1) / rpb);
+      const size_t sh = (size_t)5 * NZc * W * sizeof(C) + (size_t)7 * nd * W * sizeof(T);
+      hipLaunchKernelGGL((k_zdirect5<T, NZc, RGc>), grid, dim3(256), sh, s, geo, Lx, Ly, nzp, nd, nrhs, rpb,
+                         p->d_qtab, static_cast<const T*>(zhat), B);
+    };
+    using I8 = std::integral_constant<int, 8>;
+    using I16 = std::integral_constant<int, 16>;
+    using I24 = std::integral_constant<int, 24>;
+    using I32 = std::integral_constant<int, 32>;
+    using RGmax = std::integral_constant<int, sizeof(T) == 8 ? 32 : 16>;
+    switch (NZ) {
+      case 8: go(I8{}, I8{}); break;
+      case 16: go(I16{}, I16{}); break;
+      case 24: go(I24{}, RGmax{}); break;
+      default: go(I32{}, RGmax{}); break;
+    }
+  } else if (zdirect) {
     // double: 16 pencils x 16 row groups; float: 32 pencils x 8 row groups
     constexpr int RG = sizeof(T) == 8 ? 16 : 8;
     constexpr int W = 256 / RG;
@@ -913,7 +1090,8 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const int g = persistent_grid((const void*)k_pass_xi<T, P>, WX * tp, sh, nitems, p->ncu, tn.grid_mult[3]);
     // the direct z sum uses the z-space kernel, so only the x and y
     // transforms leave a factor to divide out
-    const T inv_n = (T)(1.0 / ((double)p->L[0] * p->L[1] * (zdirect ? 1.0 : (double)p->L[2])));
+    const T inv_n =
+        (T)(1.0 / ((double)p->L[0] * p->L[1] * (zdirect || p->C == 5 ? 1.0 : (double)p->L[2])));
     const C* sc = dbl ? reinterpret_cast<const C*>(p->d_sconv64) : reinterpret_cast<const C*>(p->d_sconv32);
     const C* cd = dbl ? reinterpret_cast<const C*>(p->d_cdiag64) : reinterpret_cast<const C*>(p->d_cdiag32);
     hipLaunchKernelGGL((k_pass_xi<T, P>), dim3(g), dim3(WX * tp), sh, s, pl, geo, WX, Kx, Ky, nzp, K, nvec, ep,

@@ -289,10 +289,11 @@ __global__ void k_zero(long long n, double2* __restrict__ a) {
 }
 
 // Derivative of the admittance with respect to p_k = lambda_k^-2 (London
-// depth): only the voxel self terms c_k / dx of Z depend on p_k, with
-// dc/dp = j c^2 / (w mu0) (from eq. 3, c = 1/sigma).  With the adjoint
-// solutions y_q of K^T y_q = [b_q; 0],
-//   dY[q][p][k] = - sum_beta y_q[beta, k] x_p[beta, k] * j c_k^2 / (w mu0 dx).
+// depth): only the voxel self terms m_beta c_k / dx of Z depend on p_k
+// (m_beta = 1 for the constant basis functions, 1/6 and 1/2 for the linear
+// ones), with dc/dp = j c^2 / (w mu0) (from eq. 3, c = 1/sigma).  With the
+// adjoint solutions y_q of K^T y_q = [b_q; 0],
+//   dY[q][p][k] = - sum_beta m_beta y_q[beta, k] x_p[beta, k] * j c_k^2 / (w mu0 dx).
 __global__ void k_port_grad(int nports, int C, int K, long long N, const double2* __restrict__ cdiag,
                             double inv_wmu, const double2* __restrict__ xf, const double2* __restrict__ xa,
                             double2* __restrict__ dY) {
@@ -301,8 +302,11 @@ __global__ void k_port_grad(int nports, int C, int K, long long N, const double2
     const long long qp = i / K;
     const int q = (int)(qp / nports), pp = (int)(qp % nports);
     double2 acc = make_double2(0, 0);
-    for (int b = 0; b < C; ++b)
-      acc = zadd(acc, zmul(xa[q * N + (long long)b * K + k], xf[pp * N + (long long)b * K + k]));
+    for (int b = 0; b < C; ++b) {
+      const double m = b < 3 ? 1.0 : b == 3 ? 1.0 / 6.0 : 0.5;
+      const double2 t = zmul(xa[q * N + (long long)b * K + k], xf[pp * N + (long long)b * K + k]);
+      acc = zadd(acc, make_double2(m * t.x, m * t.y));
+    }
     // cdiag holds c / dx; dz/dp = j c^2 / (w mu0 dx) = j (c/dx)^2 dx / (w mu0)
     const double2 cd = cdiag[k];
     const double2 c2 = zmul(cd, cd);
@@ -580,10 +584,21 @@ svh_status prepare_diag(svh_problem* p, int f) {
   if (p->diag_freq == f && p->d_ydiag) return SVH_OK;
   const int K = p->nvox, CK = p->C * K, M = p->topo.M;
   const std::complex<double> s = p->sconv[f];  // j w mu0 dx
-  const double T0 = p->T[0];
+  // self block of each basis function at offset 0 (eq. 8): M0 for the
+  // constant ones, M2x + M2y and M2x + M2y + 4 M2z for the linear ones, and
+  // its mass weight 1, 1/6, 1/2
+  double self[5] = {p->T[0], p->T[0], p->T[0], 0, 0};
+  const double mass[5] = {1.0, 1.0, 1.0, 1.0 / 6.0, 0.5};
+  if (p->C == 5) {
+    const size_t Kt = (size_t)p->K[0] * p->K[1] * p->K[2];
+    const double m2x = p->Tf[4 * Kt], m2y = p->Tf[5 * Kt], m2z = p->Tf[6 * Kt];
+    self[3] = m2x + m2y;
+    self[4] = m2x + m2y + 4 * m2z;
+  }
   std::vector<double> yd(CK), sd(M, 1.0);
   for (int a = 0; a < p->C; ++a)
-    for (int k = 0; k < K; ++k) yd[(size_t)a * K + k] = std::abs(p->cdiag_host[(size_t)f * K + k] + s * T0);
+    for (int k = 0; k < K; ++k)
+      yd[(size_t)a * K + k] = std::abs(mass[a] * p->cdiag_host[(size_t)f * K + k] + s * self[a]);
   for (int m = 0; m < M; ++m) {
     if (p->dirichlet[m]) continue;
     double acc = 0;
@@ -973,12 +988,14 @@ svh_status svh_gradient_contract(svh_problem* p, const void* dY_dev, const doubl
 
 svh_status svh_matvec_adjoint(svh_problem* p, svh_prec prec, int nrhs, const int32_t* freq_idx_host,
                               const void* x_dev, void* y_dev, void* ws_dev, size_t ws_bytes, void* stream) {
-  // Every block of the piecewise-constant operator depends on the offset only
-  // through the even integral M0 and the diagonal is symmetric, so Z^T = Z
-  // (transpose, not conjugate) and the transposed block table is the block
-  // table itself: the adjoint product runs the same kernels.
+  // The Galerkin blocks satisfy B^{alpha beta}(-d) = B^{beta alpha}(d): the
+  // constant-basis blocks depend on the offset through the even M0, and a
+  // block with an odd M1 family changes sign both under d -> -d and under the
+  // exchange of the two basis functions (eq. 8: (x, 2D) = +M1x, (2D, x) =
+  // -M1x).  The diagonal is symmetric, so Z^T = Z (transpose, not conjugate)
+  // and the transposed block table is the block table itself: the adjoint
+  // product runs the same kernels.
   if (!p) return SVH_EINVAL;
-  if (p->basis != 3) return sfail(p, SVH_EINVAL, "matvec_adjoint: basis not supported");
   return svh_matvec(p, prec, nrhs, freq_idx_host, x_dev, y_dev, ws_dev, ws_bytes, stream);
 }
 

@@ -19,6 +19,10 @@ constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;  // H/m (mu = mu0, Sec.
 constexpr int kMaxVecsPerChunk = 256;  // component vectors per pass launch
 constexpr int kMaxStages = 8;
 constexpr int kMaxDirectPlanes = 32;  // direct z sum when at most this many planes are occupied
+// Piecewise-linear basis (eqs. 4-8): seven voxel-pair integral families
+// M0, M1x, M1y, M1z, M2x, M2y, M2z; the M1 family of axis a is odd along a.
+constexpr int kNFam = 7;
+constexpr int kMaxDz5 = 64;  // distinct plane offsets of the coupled direct z step
 
 // Mixed-radix Stockham plan: L = prod r[s], radices in {8, 4, 2, 3}.
 struct FftPlan {
@@ -95,6 +99,16 @@ struct svh_problem {
   float2* d_cdiag32 = nullptr;
   // tensors
   std::vector<double> T;        // Toeplitz tensor, host [Kz][Ky][Kx]
+  // piecewise-linear basis (C = 5): family tables (host, [f][Kz][Ky][Kx];
+  // f = 0 is T), the distinct plane offsets |z_i - z_j| of the occupied planes,
+  // the (row, column) -> offset-slot codes of the coupled z step and the
+  // z-space kernels [f][slot][Ly][Lx] (for M1x, M1y the coefficient of j)
+  std::vector<double> Tf;
+  std::vector<int32_t> dzset;
+  uint8_t* d_qtab = nullptr;    // [32][32]: slot | 0x80 when z_j < z_i
+  double* d_g5_64 = nullptr;
+  float* d_g5_32 = nullptr;
+  svh::DevTucker tk5[svh::kNFam];
   double* d_zhat64 = nullptr;   // dense spectrum [Lz][Ly][Lx] (real)
   float* d_zhat32 = nullptr;
   double* d_g64 = nullptr;      // dense z-space kernel [Kz][Ly][Lx] (real)
@@ -133,6 +147,18 @@ hipError_t launch_even_spectrum(const svh_problem* p, const double* d_T, double*
                                 double* d_tmp1, double* d_tmp2, hipStream_t s);
 hipError_t launch_tucker_rebuild(const svh_problem* p, bool fp32_out, bool zspace, void* d_out,
                                  double* d_V, double* d_W, hipStream_t s);
+// Tucker restoration of one family's z-space kernel rows (factor Fz3 has M3
+// rows): out[m][ky][kx] = sum core F1 F2 Fz3.
+hipError_t launch_tucker_rebuild_rows(const svh_problem* p, const DevTucker& t, const double* Fz3, int M3,
+                                      bool fp32_out, void* d_out, double* d_V, double* d_W, hipStream_t s);
+// Seven family tables [f][Kz][Ky][Kx] on the device (quadrature; f = 0 is
+// recomputed by the caller from the closed form).
+hipError_t family_tables(const int K[3], double* d_out, hipStream_t s);
+// z-space kernels of the seven families at the plane offsets dzset:
+// rows [f][q][Ky][Kx] (device) -> out [f][q][Ly][Lx].
+hipError_t launch_zspace_families(const svh_problem* p, const double* d_rows, int nd, double* d_out,
+                                  double* d_tmp, hipStream_t s);
+size_t tucker_scratch_doubles5(const svh_problem* p);
 bool use_zdirect(const svh_problem* p);
 Geo make_geo(const svh_problem* p, size_t csize);
 void free_solver(svh_problem* p);

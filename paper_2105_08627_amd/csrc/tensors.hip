@@ -1,8 +1,10 @@
 // Circulant spectrum construction and Tucker restoration kernels (gfx950).
 //
-//  * k_even_axis: one axis of the real spectrum of the even circulant
-//    embedding (Sec. II.A): out[k] = sum_{n<K} w_n T[n] cos(2 pi k n / L),
-//    w_0 = 1, w_n = 2 (the entries at n and L - n of the embedding).
+//  * k_even_axis: one axis of the spectrum of the circulant embedding
+//    (Sec. II.A): out[k] = sum_{n<K} w_n T[n] cos(2 pi k n / L), w_0 = 1,
+//    w_n = 2 (the entries at n and L - n of the embedding); for a tensor odd
+//    along the axis the same sum over n >= 1 with sin, which is the spectrum
+//    divided by j.
 //  * k_gemm_f64_mfma: strided batched FP64 GEMM on the matrix cores
 //    (v_mfma_f64_16x16x4f64), used for the three mode products of the Tucker
 //    restoration Z = core x1 F1 x2 F2 x3 F3 (eqs. 10-11).  The last product
@@ -13,7 +15,7 @@
 namespace svh {
 
 __global__ void k_even_axis(const double* __restrict__ in, double* __restrict__ out, int nouter, int Kin,
-                            int L, int ninner, const double* __restrict__ cosT) {
+                            int L, int ninner, const double* __restrict__ tab, int odd) {
   const size_t total = (size_t)nouter * L * ninner;
   for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < total;
        id += (size_t)gridDim.x * blockDim.x) {
@@ -22,12 +24,12 @@ __global__ void k_even_axis(const double* __restrict__ in, double* __restrict__ 
     const int k = (int)(rest % L);
     const size_t o = rest / L;
     const double* src = in + o * (size_t)Kin * ninner + i;
-    double s = src[0];
+    double s = odd ? 0.0 : src[0];
     long long m = 0;
     for (int n = 1; n < Kin; ++n) {
       m += k;
       if (m >= L) m -= L;
-      s += 2.0 * src[(size_t)n * ninner] * cosT[m];
+      s += 2.0 * src[(size_t)n * ninner] * tab[m];
     }
     out[id] = s;
   }
@@ -115,13 +117,13 @@ hipError_t launch_even_spectrum(const svh_problem* p, const double* d_T, double*
   e = hipMemcpyAsync(d_cos, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) {
     // x: [Kz][Ky][Kx] -> [Kz][Ky][Lx]
-    hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, d_T, d_tmp1, Kz * Ky, Kx, Lx, 1, d_cos);
+    hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, d_T, d_tmp1, Kz * Ky, Kx, Lx, 1, d_cos, 0);
     // y: [Kz][Ky][Lx] -> [Kz][Ly][Lx]  (this is the z-space kernel)
     hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, d_tmp1, d_tmp2, Kz, Ky, Ly, Lx,
-                       d_cos + Lmax);
+                       d_cos + Lmax, 0);
     // z: [Kz][Ly][Lx] -> [Lz][Ly][Lx]
     hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, d_tmp2, d_out, 1, Kz, Lz, Ly * Lx,
-                       d_cos + 2 * Lmax);
+                       d_cos + 2 * Lmax, 0);
     e = hipGetLastError();
   }
   hipError_t e2 = hipStreamSynchronize(s);
@@ -134,23 +136,72 @@ size_t tucker_scratch_doubles(const svh_problem* p) {
   return (size_t)p->L[0] * t.d[1] * t.d[2] + (size_t)p->L[0] * p->L[1] * t.d[2];
 }
 
-hipError_t launch_tucker_rebuild(const svh_problem* p, bool fp32_out, bool zspace, void* d_out, double* d_V,
-                                 double* d_W, hipStream_t s) {
-  const DevTucker& t = p->tk;
-  const int L1 = p->L[0], L2 = p->L[1], L3 = p->L[2];
+size_t tucker_scratch_doubles5(const svh_problem* p) {
+  size_t m = 0;
+  for (int f = 0; f < kNFam; ++f) {
+    const DevTucker& t = p->tk5[f];
+    m = std::max(m, (size_t)p->L[0] * t.d[1] * t.d[2] + (size_t)p->L[0] * p->L[1] * t.d[2]);
+  }
+  return m;
+}
+
+hipError_t launch_tucker_rebuild_rows(const svh_problem* p, const DevTucker& t, const double* Fz3, int M3,
+                                      bool fp32_out, void* d_out, double* d_V, double* d_W, hipStream_t s) {
+  const int L1 = p->L[0], L2 = p->L[1];
   const int d1 = t.d[0], d2 = t.d[1], d3 = t.d[2];
   hipError_t e;
-  // V[kx][c][b] = sum_a F1[kx][a] core[c][b][a]
   GemmArgs g1{L1, d2 * d3, d1, t.F[0], d1, 1, 0, t.core, 1, d1, 0, d_V, (long long)d2 * d3, 1, 0};
   if ((e = gemm(g1, 1, false, s)) != hipSuccess) return e;
-  // W[ky][kx][c] = sum_b F2[ky][b] V[kx][c][b]   (batched over kx)
   GemmArgs g2{L2, d3, d2, t.F[1], d2, 1, 0, d_V, 1, d2, (long long)d2 * d3, d_W, (long long)L1 * d3, 1, d3};
   if ((e = gemm(g2, L1, false, s)) != hipSuccess) return e;
+  GemmArgs g3{M3, L1 * L2, d3, Fz3, d3, 1, 0, d_W, 1, d3, 0, d_out, (long long)L1 * L2, 1, 0};
+  return gemm(g3, 1, fp32_out, s);
+}
+
+hipError_t launch_tucker_rebuild(const svh_problem* p, bool fp32_out, bool zspace, void* d_out, double* d_V,
+                                 double* d_W, hipStream_t s) {
   // Z[kz][ky][kx] = sum_c F3[kz][c] W[ky][kx][c]; in z space the third
   // factor is its inverse z transform and only offsets dz < Kz are restored
-  const int M3 = zspace ? p->K[2] : L3;
-  GemmArgs g3{M3, L1 * L2, d3, zspace ? t.Fz : t.F[2], d3, 1, 0, d_W, 1, d3, 0, d_out, (long long)L1 * L2, 1, 0};
-  return gemm(g3, 1, fp32_out, s);
+  const DevTucker& t = p->tk;
+  return launch_tucker_rebuild_rows(p, t, zspace ? t.Fz : t.F[2], zspace ? p->K[2] : p->L[2], fp32_out, d_out,
+                                    d_V, d_W, s);
+}
+
+// Parity of the seven families per axis (x, y, z): M1 of axis a is odd along a.
+static const int kFamOdd[kNFam][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1},
+                                      {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+
+hipError_t launch_zspace_families(const svh_problem* p, const double* d_rows, int nd, double* d_out,
+                                  double* d_tmp, hipStream_t s) {
+  const int Kx = p->K[0], Ky = p->K[1];
+  const int Lx = p->L[0], Ly = p->L[1];
+  const int Lmax = std::max(Lx, Ly);
+  std::vector<double> tab(4 * (size_t)Lmax, 0.0);  // cos x, sin x, cos y, sin y
+  for (int a = 0; a < 2; ++a)
+    for (int m = 0; m < p->L[a]; ++m) {
+      const long double ang = 2.0L * 3.141592653589793238462643383279502884L * m / p->L[a];
+      tab[(size_t)(2 * a) * Lmax + m] = (double)cosl(ang);
+      tab[(size_t)(2 * a + 1) * Lmax + m] = (double)sinl(ang);
+    }
+  double* d_tab = nullptr;
+  hipError_t e = hipMalloc(&d_tab, sizeof(double) * tab.size());
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(d_tab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, s);
+  for (int f = 0; f < kNFam && e == hipSuccess; ++f) {
+    const double* in = d_rows + (size_t)f * nd * Ky * Kx;
+    double* out = d_out + (size_t)f * nd * Ly * Lx;
+    const int ox = kFamOdd[f][0], oy = kFamOdd[f][1];
+    // x: [nd][Ky][Kx] -> [nd][Ky][Lx]
+    hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, in, d_tmp, nd * Ky, Kx, Lx, 1,
+                       d_tab + (size_t)ox * Lmax, ox);
+    // y: [nd][Ky][Lx] -> [nd][Ly][Lx]
+    hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, d_tmp, out, nd, Ky, Ly, Lx,
+                       d_tab + (size_t)(2 + oy) * Lmax, oy);
+    e = hipGetLastError();
+  }
+  hipError_t e2 = hipStreamSynchronize(s);
+  hipFree(d_tab);
+  return e != hipSuccess ? e : e2;
 }
 
 }  // namespace svh

@@ -13,6 +13,12 @@
 // therefore gives exactly the factors computed here from the K1 x K2 x K3
 // tensor Tw instead of the eight times larger L1 x L2 x L3 tensor Z.
 //
+// An axis on which T is odd (T(-n) = -T(n), so T(0) = 0) embeds as
+// E(n) = -T(n), E(L - n) = T(n); its spectrum is j times the sine series
+// 2 sum_{n>=1} T_n sin(2 pi k n / L), the weights are w_0 = 0, w_n = 2 and the
+// factor columns are  sqrt(2) sum_{n>=1} u_n sin(2 pi k n / L) / sqrt(L).  The
+// stored factors are real; the caller keeps track of the factor j per odd axis.
+//
 // Each mode's SVD: Householder QR of the transposed unfolding, then one-sided
 // (Hestenes) Jacobi on the triangular factor, which keeps small singular
 // values accurate relative to the largest one (no Gram matrix is formed).
@@ -188,10 +194,18 @@ static double cos2pi_frac(long long num, long long den) {
   return (double)cosl(a);
 }
 
-// Tucker factors of the real spectrum of the even circulant embedding of T
-// (T: [K3][K2][K1], x fastest; L: FFT lengths, L[i] >= 2 K[i] - 1).
-int tucker_even_circulant(const int K[3], const int L[3], const double* T, double tol,
-                          TuckerFactors& out) {
+static double sin2pi_frac(long long num, long long den) {
+  long long m = num % den;
+  if (m < 0) m += den;
+  const long double a = 2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)den;
+  return (double)sinl(a);
+}
+
+// Tucker factors of the spectrum of the circulant embedding of T (T:
+// [K3][K2][K1], x fastest; L: FFT lengths, L[i] >= 2 K[i] - 1; odd[i] != 0
+// where T is odd along axis i).
+int tucker_circulant(const int K[3], const int L[3], const double* T, const int odd[3], double tol,
+                     TuckerFactors& out) {
   const size_t n = (size_t)K[0] * K[1] * K[2];
   std::vector<double> Tw(n);
   const double r2 = std::sqrt(2.0);
@@ -199,13 +213,25 @@ int tucker_even_circulant(const int K[3], const int L[3], const double* T, doubl
   for (int k = 0; k < K[2]; ++k)
     for (int j = 0; j < K[1]; ++j)
       for (int i = 0; i < K[0]; ++i) {
-        const double w = (i ? r2 : 1.0) * (j ? r2 : 1.0) * (k ? r2 : 1.0);
+        const int idx[3] = {i, j, k};
+        double w = 1.0;
+        for (int a = 0; a < 3; ++a) w *= idx[a] ? r2 : (odd[a] ? 0.0 : 1.0);
         const size_t b = ((size_t)k * K[1] + j) * K[0] + i;
         Tw[b] = T[b] * w;
         nrm2 += Tw[b] * Tw[b];
       }
   const double nrm = std::sqrt(nrm2);
-  if (!(nrm > 0)) return -1;
+  if (!(nrm > 0)) {
+    // zero tensor (an odd family on a grid one voxel wide along its axis):
+    // rank one with zero factors
+    for (int m = 0; m < 3; ++m) {
+      out.d[m] = 1;
+      out.F[m].assign((size_t)L[m], 0.0);
+    }
+    out.core.assign(1, 0.0);
+    out.relerr = 0;
+    return 1;
+  }
   const double thr = tol / std::sqrt(3.0) * nrm;
   std::vector<double> U[3];
   double tails2 = 0;
@@ -253,20 +279,29 @@ int tucker_even_circulant(const int K[3], const int L[3], const double* T, doubl
         for (int k = 0; k < K[2]; ++k) s += U[2][(size_t)k * d3 + c] * G2[((size_t)k * d2 + b) * d1 + a];
         out.core[((size_t)c * d2 + b) * d1 + a] = s * scale;
       }
-  // circulant factors: cosine series of the Toeplitz factors
+  // circulant factors: cosine (even axis) or sine (odd axis) series of the
+  // Toeplitz factors
   for (int m = 0; m < 3; ++m) {
     const int d = out.d[m];
     out.F[m].assign((size_t)L[m] * d, 0.0);
     const double inv = 1.0 / std::sqrt((double)L[m]);
+    const bool od = odd[m] != 0;
 #pragma omp parallel for
     for (int k = 0; k < L[m]; ++k)
       for (int c = 0; c < d; ++c) {
-        double s = U[m][c];
-        for (int j = 1; j < K[m]; ++j) s += r2 * U[m][(size_t)j * d + c] * cos2pi_frac((long long)k * j, L[m]);
+        double s = od ? 0.0 : U[m][c];
+        for (int j = 1; j < K[m]; ++j)
+          s += r2 * U[m][(size_t)j * d + c] *
+               (od ? sin2pi_frac((long long)k * j, L[m]) : cos2pi_frac((long long)k * j, L[m]));
         out.F[m][(size_t)k * d + c] = s * inv;
       }
   }
   return 0;
+}
+
+int tucker_even_circulant(const int K[3], const int L[3], const double* T, double tol, TuckerFactors& out) {
+  const int even[3] = {0, 0, 0};
+  return tucker_circulant(K, L, T, even, tol, out);
 }
 
 }  // namespace svh

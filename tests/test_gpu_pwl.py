@@ -1,0 +1,281 @@
+"""Piecewise-linear basis (five components per voxel, eqs. 4-8) on the GPU
+against the FP64 CPU oracle: the seven voxel-pair integral families, the
+coupled matvec (dense O(N^2) oracle sum), its Tucker-compressed form, the
+port solve of a corner-turning strip against the dense LU solve, and the
+admittance gradient against the dense adjoint.
+
+Tolerances (relative L2 per right-hand side): FP64 1e-12, FP32 1e-5.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import circuit as cc
+from oracle import green
+from oracle import operator as op
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+FREQS = [10e9, 3e9]
+SIGMA0, LAM = 1e7, 90e-9
+FAMS = ["M0", "M1x", "M1y", "M1z", "M2x", "M2y", "M2z"]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU test needs a device"
+    return torch.device("cuda")
+
+
+def _problem(mask, dx, tol=None):
+    import paper_2105_08627_amd as svh
+    p = svh.Problem(mask, dx, basis=5)
+    p.set_material(FREQS, SIGMA0, LAM)
+    p.setup_tensors()
+    if tol is not None:
+        p.tucker_compress(tol)
+    return p
+
+
+def _oracle(mask, dx, x, fidx):
+    K = int(mask.sum())
+    fam = op.FamilyCache(mask.shape[2], mask.shape[1], mask.shape[0])
+    out = np.zeros_like(x)
+    for r, f in enumerate(fidx):
+        if f < 0:
+            out[r] = op.dense_matvec(mask, 5, x[r].reshape(-1), fam).reshape(5, K)
+        else:
+            w = 2 * np.pi * FREQS[f]
+            c = op.material_c(FREQS[f], SIGMA0, LAM) * np.ones(K)
+            out[r] = op.dense_matvec(mask, 5, x[r].reshape(-1), fam, 1j * w * op.MU0 * dx, c, dx).reshape(5, K)
+    return out
+
+
+def _run(p, x, fidx, dev, dtype):
+    xt = torch.from_numpy(x.astype(np.complex128)).to(dev).to(dtype).contiguous()
+    y = p.matvec(xt, fidx)
+    torch.cuda.synchronize()
+    return y.cpu().numpy().astype(np.complex128)
+
+
+def _relerr(a, b):
+    return np.array([np.linalg.norm(a[r] - b[r]) / np.linalg.norm(b[r]) for r in range(a.shape[0])])
+
+
+def _planes_mask(seed, Kx, Ky, Kz, nocc, fill=0.5):
+    """Random mask with exactly `nocc` occupied z planes (irregular spacing)."""
+    g = np.random.default_rng(seed)
+    m = (g.random((Kz, Ky, Kx)) < fill).astype(np.uint8)
+    planes = np.sort(g.choice(Kz, size=nocc, replace=False))
+    keep = np.zeros(Kz, dtype=bool)
+    keep[planes] = True
+    m[~keep] = 0
+    for z in planes:
+        if m[z].sum() == 0:
+            m[z, 0, 0] = 1
+    return m
+
+
+def test_family_tables_match_oracle(dev):
+    """All seven families on a 9 x 7 x 6 grid: device quadrature (and the
+    closed form for M0) against the oracle's quadrature, to 1e-14 of the
+    largest M0 value."""
+    mask = wl.full_box(9, 7, 6)
+    p = _problem(mask, 0.5e-6)
+    scale = green.family_table("M0", 1, 1, 1)[0, 0, 0]
+    for f, name in enumerate(FAMS):
+        ref = green.family_table(name, 9, 7, 6)
+        got = p.family(f)
+        err = np.abs(got - ref).max() / scale
+        print(name, err)
+        assert err <= 1e-14, (name, err)
+
+
+MV_CASES = [
+    ((6, 5, 4), None, 1.0, 21),        # filled box, L = (12, 10, 8)
+    ((20, 13, 9), None, 0.3, 22),      # L = (40, 27, 18): radix 3, ragged tiles, 9 planes
+    ((7, 5, 3), None, 0.8, 23),
+    ((9, 7, 1), None, 1.0, 24),        # one plane: a single plane offset
+    ((1, 6, 5), None, 1.0, 25),        # one voxel wide in x: M1x vanishes
+    ((5, 4, 30), 24, 0.5, 26),         # 24 irregular planes, 24 x 24 block per pencil
+    ((4, 4, 40), 32, 0.5, 27),         # 32 planes (largest direct z step)
+]
+
+
+def _case_mask(shape, nocc, fill, seed):
+    if nocc is not None:
+        return _planes_mask(seed, *shape, nocc, fill)
+    if fill >= 1.0:
+        return wl.full_box(*shape)
+    return wl.random_mask(seed, *shape, fill=fill)
+
+
+@pytest.mark.parametrize("shape,nocc,fill,seed", MV_CASES)
+def test_pwl_matvec_fp64_and_fp32(dev, shape, nocc, fill, seed):
+    mask = _case_mask(shape, nocc, fill, seed)
+    dx = 0.25e-6
+    p = _problem(mask, dx)
+    K = p.K
+    x = wl.random_currents(seed, (3, 5, K))
+    fidx = [-1, 0, 1]
+    ref = _oracle(mask, dx, x, fidx)
+    e64 = _relerr(_run(p, x, fidx, dev, torch.complex128), ref)
+    e32 = _relerr(_run(p, x, fidx, dev, torch.complex64), ref)
+    print(shape, "K", K, "fp64", e64, "fp32", e32)
+    assert np.all(e64 <= 1e-12)
+    assert np.all(e32 <= 1e-5)
+
+
+def test_pwl_multi_chunk_batch(dev):
+    """More right-hand sides than one pass launch holds (51 five-component
+    vectors per chunk), mixed frequency slots; checked per RHS against the
+    single-RHS product and a few against the oracle."""
+    mask = wl.random_mask(31, 10, 9, 6, fill=0.5)
+    dx = 0.25e-6
+    p = _problem(mask, dx)
+    n = 60
+    x = wl.random_currents(31, (n, 5, p.K))
+    fidx = [r % 2 for r in range(n)]
+    y = _run(p, x, fidx, dev, torch.complex128)
+    for r in (0, 37, 59):
+        single = _run(p, x[r:r + 1], [fidx[r]], dev, torch.complex128)
+        assert np.array_equal(single[0], y[r])
+    ref = _oracle(mask, dx, x[[0, 51, 59]], [fidx[0], fidx[51], fidx[59]])
+    assert np.all(_relerr(y[[0, 51, 59]], ref) <= 1e-12)
+
+
+def test_pwl_tucker(dev):
+    """Per-family Tucker compression: tol 1e-12 reproduces the uncompressed
+    operator; tol 1e-6 stays within 10 * tol of the oracle."""
+    mask = wl.random_mask(41, 24, 20, 8, fill=0.5)
+    dx = 0.25e-6
+    p = _problem(mask, dx)
+    x = wl.random_currents(41, (2, 5, p.K))
+    fidx = [-1, 0]
+    y0 = _run(p, x, fidx, dev, torch.complex128)
+    ranks, err = p.tucker_compress(1e-12)
+    assert ranks.shape == (7, 3)
+    y1 = _run(p, x, fidx, dev, torch.complex128)
+    assert np.all(_relerr(y1, y0) <= 1e-10)
+    ranks6, err6 = p.tucker_compress(1e-6)
+    print("ranks 1e-12", ranks.tolist(), "ranks 1e-6", ranks6.tolist(), err6)
+    assert np.all(ranks6 <= ranks) and err6 <= 1e-6
+    ref = _oracle(mask, dx, x, fidx)
+    assert np.all(_relerr(_run(p, x, fidx, dev, torch.complex128), ref) <= 1e-5)
+    assert np.all(_relerr(_run(p, x, fidx, dev, torch.complex64), ref) <= 1e-5)
+
+
+def test_pwl_adjoint_dot_test(dev):
+    mask = wl.random_mask(51, 8, 7, 5, fill=0.6)
+    p = _problem(mask, 0.5e-6)
+    u = torch.from_numpy(wl.random_currents(1, (1, 5, p.K))).to(dev)
+    v = torch.from_numpy(wl.random_currents(2, (1, 5, p.K))).to(dev)
+    a = torch.sum(v * p.matvec(u, [0])).item()
+    b = torch.sum(u * p.matvec_adjoint(v, [0])).item()
+    assert abs(a - b) <= 1e-13 * abs(a)
+
+
+def bend(width=2, arm=8, thick=2):
+    """90-degree bend: an x-directed arm along y in [0, width) and a
+    y-directed arm along x in [arm - width, arm); port + on the -x end faces,
+    - on the +y end faces.  With the piecewise-constant basis alone no
+    current can turn the corner."""
+    mask = np.zeros((thick, arm, arm), dtype=np.uint8)
+    mask[:, 0:width, :] = 1
+    mask[:, :, arm - width:arm] = 1
+    P = op.voxel_coords(mask)
+    plus = [(k, 0) for k in range(P.shape[0]) if P[k, 0] == 0]
+    minus = [(k, 3) for k in range(P.shape[0]) if P[k, 1] == arm - 1]
+    return mask, [(plus, minus)]
+
+
+def _oracle_saddle(mask, ports, dx, f, lam):
+    K = int(mask.sum())
+    fam = op.FamilyCache(mask.shape[2], mask.shape[1], mask.shape[0])
+    c = op.material_c(f, SIGMA0, lam) * np.ones(K)
+    w = 2 * np.pi * f
+    Z = op.dense_rows(mask, 5, np.arange(5 * K), fam, 1j * w * op.MU0 * dx, c, dx)
+    A, node_of, _ = cc.incidence(mask, 5)
+    pn = cc.port_nodes(mask, node_of, ports)
+    return Z, A, pn, c
+
+
+def test_pwl_bend_solve_matches_dense_lu(dev):
+    import paper_2105_08627_amd as svh
+    dx = 0.5e-6
+    mask, ports = bend()
+    Z, A, pn, _ = _oracle_saddle(mask, ports, dx, FREQS[0], LAM)
+    Yo, Xo, free, b = cc.solve_ports(Z, A, pn)
+    p = svh.Problem(mask, dx, basis=5)
+    p.set_material([FREQS[0]], SIGMA0, LAM)
+    p.setup_tensors()
+    p.set_ports(ports)
+    X, Y, info = p.solve(0, rre=1e-10, restart=50, maxit=400)
+    print("bend", info["iterations"], info["inner_iterations"], Y, Yo)
+    assert info["converged"] and info["relres"] <= 2e-10
+    assert np.abs(Y - Yo).max() <= 1e-8 * np.abs(Yo).max()
+    K5 = 5 * p.K
+    Xg = X.cpu().numpy()
+    assert np.linalg.norm(Xg[0, :K5] - Xo[:K5, 0]) <= 1e-8 * np.linalg.norm(Xo[:K5, 0])
+    # the linear functions carry the current round the corner: the same
+    # structure with the constant basis alone passes (almost) nothing
+    p3 = svh.Problem(mask, dx)
+    p3.set_material([FREQS[0]], SIGMA0, LAM)
+    p3.setup_tensors()
+    p3.set_ports(ports)
+    _, Y3, _ = p3.solve(0, rre=1e-10, restart=50, maxit=400)
+    assert np.abs(Y3).max() <= 1e-6 * np.abs(Y).max()
+
+
+def test_pwl_fp32_refinement_bend(dev):
+    import paper_2105_08627_amd as svh
+    dx = 0.5e-6
+    mask, ports = bend(width=2, arm=10)
+    p = svh.Problem(mask, dx, basis=5)
+    p.set_material([FREQS[0]], SIGMA0, LAM)
+    p.setup_tensors()
+    p.set_ports(ports)
+    _, Y64, i64 = p.solve(0, rre=1e-10, restart=30)
+    _, Yir, iir = p.solve(0, rre=1e-10, restart=30, refine=True)
+    assert iir["converged"] and iir["relres"] <= 2e-10
+    assert np.abs(Yir - Y64).max() <= 1e-8 * np.abs(Y64).max()
+
+
+def test_pwl_gradient_matches_dense_adjoint(dev):
+    """dY/dp_k (p = lambda^-2) for the bend with per-voxel London depths,
+    against the oracle's dense forward and transposed solves; the linear
+    functions enter with their mass weights 1/6 and 1/2."""
+    import paper_2105_08627_amd as svh
+    dx = 0.5e-6
+    mask, ports = bend()
+    K = int(mask.sum())
+    lam = np.random.default_rng(61).uniform(80e-9, 120e-9, K)
+    F = FREQS[0]
+    p = svh.Problem(mask, dx, basis=5)
+    p.set_material([F], np.full(K, SIGMA0), lam, per_voxel=True)
+    p.setup_tensors()
+    p.set_ports(ports)
+    X, _, _ = p.solve(0, rre=1e-12)
+    Xa, _, _ = p.solve(0, rre=1e-12, transpose=True)
+    dY = p.port_gradient(0, X, Xa).cpu().numpy()
+    fam = op.FamilyCache(mask.shape[2], mask.shape[1], mask.shape[0])
+    c = op.material_c(F, SIGMA0, lam)
+    w = 2 * np.pi * F
+    Z = op.dense_rows(mask, 5, np.arange(5 * K), fam, 1j * w * op.MU0 * dx, c, dx)
+    A, node_of, _ = cc.incidence(mask, 5)
+    pn = cc.port_nodes(mask, node_of, ports)
+    dirn = cc.ground_floating(A, sorted({m for pl, mi in pn for m in pl + mi}))
+    Kmat, _ = cc.saddle_system(Z, A, dirn)
+    bq = np.stack([A[pl].sum(axis=0) for pl, _ in pn], axis=1)
+    rhs = np.zeros((Kmat.shape[0], len(pn)), dtype=complex)
+    rhs[:5 * K] = bq
+    Xo = np.linalg.solve(Kmat, rhs)[:5 * K]
+    Ya = np.linalg.solve(Kmat.T, rhs)[:5 * K]
+    mass = np.array([1, 1, 1, 1 / 6, 1 / 2])
+    dz = 1j * c ** 2 / (w * op.MU0 * dx)
+    s = (mass[:, None] * (Ya[:, 0] * Xo[:, 0]).reshape(5, K)).sum(axis=0)
+    ref = -s * dz
+    err = np.abs(dY[0, 0] - ref).max() / np.abs(ref).max()
+    print("pwl gradient vs dense adjoint", err)
+    assert err <= 1e-8
