@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 
 
 def log(msg):
@@ -84,6 +85,69 @@ def cpu_baseline(mask, dx, x, fidx, freqs, sigma0, lam, budget_s=20.0):
                       f"(K={K}), {dt:.1f} s; numpy threads={os.environ.get('OMP_NUM_THREADS', 'default')}"}
 
 
+def bench_basis5(args, cfg, mask, fidx, dev):
+    """The same workload with the piecewise-linear basis (five components per
+    voxel, eqs. 5-6): seven integral families, each Tucker-compressed to the
+    same tolerance, coupled five-component z step."""
+    import torch
+    import paper_2105_08627_amd as svh
+    import workloads as wl
+    dx, freqs, sigma0, lam = cfg["dx"], cfg["freqs"], cfg["sigma0"], cfg["lam"]
+    nrhs = len(fidx)
+    t = time.perf_counter()
+    p = svh.Problem(mask, dx, basis=5)
+    p.set_material(freqs, sigma0, lam)
+    p.setup_tensors()
+    t_setup = time.perf_counter() - t
+    t = time.perf_counter()
+    ranks, terr = p.tucker_compress(args.tol)
+    t_tucker = time.perf_counter() - t
+    log(f"[bench] basis5 setup {t_setup:.1f}s tucker {t_tucker:.1f}s ranks {ranks.tolist()} bound {terr:.2e}")
+    K = p.K
+    nzp = int(np.count_nonzero(mask.reshape(mask.shape[0], -1).any(axis=1)))
+    x64 = torch.from_numpy(wl.random_currents(cfg["seed"] + 5, (nrhs, 5, K))).to(dev)
+    x32 = x64.to(torch.complex64)
+    y32, y64 = torch.empty_like(x32), torch.empty_like(x64)
+    p.autotune(x32, fidx)
+    p.autotune(x64, fidx)
+    res = {}
+    for name, x, y, steps in (("fp32", x32, y32, max(args.steps // 2, 1)), ("fp64", x64, y64, args.fp64_steps)):
+        p.matvec(x, fidx, out=y)
+        torch.cuda.synchronize()
+        p.profile(True)
+        p.profile_read()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            p.matvec(x, fidx, out=y)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof, ncall = p.profile_read()
+        p.profile(False)
+        per = {k: v / steps for k, v in prof.items()}  # one profile set per launch chunk
+        res[name] = {"value": nrhs * steps / dt, "unit": "matvecs/s", "ms_per_step": dt * 1e3 / steps,
+                     "kernels_ms_per_step": per}
+        log(f"[bench] basis5 {name} {steps} steps {dt * 1e3 / steps:.3f} ms/step  "
+            + " ".join(f"{k}={v:.3f}" for k, v in per.items()))
+    rel = (torch.linalg.vector_norm((y32.to(torch.complex128) - y64).flatten())
+           / torch.linalg.vector_norm(y64.flatten())).item()
+    Lx, Ly, _ = p.L
+    # coupled z step: 12 z convolutions of complex data with real kernels per
+    # pencil, i.e. 48 flops per (pencil, RHS, observer plane, source plane)
+    zflops = 48.0 * nrhs * Lx * Ly * nzp * nzp
+    zms = res["fp32"]["kernels_ms_per_step"]["pass_z_mul"]
+    by = pass_bytes(p, 5 * nrhs, 8, 4, K, nzp)
+    zs = np.nonzero(mask.reshape(mask.shape[0], -1).any(axis=1))[0]
+    nd = len({abs(int(a) - int(b)) for a in zs for b in zs})
+    by["pass_z_mul"] = 5 * nrhs * 2 * nzp * Ly * Lx * 8 + 7 * nd * Lx * Ly * 4
+    return {"workload": f"same grid and RHS, piecewise-linear basis: 5 components, K={K}, "
+                        f"7 integral families, Tucker tol {args.tol:g}",
+            "setup_s": t_setup, "tucker_s": t_tucker, "tucker_ranks": ranks.tolist(),
+            **res, "rel_err_fp32_vs_fp64": rel,
+            "z_step_fp32": {"ms": zms, "tflops": zflops / (zms * 1e-3) / 1e12,
+                            "alu_frac": zflops / (zms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+                            "hbm_gbs": by["pass_z_mul"] / (zms * 1e-3) / 1e9}}
+
+
 def bench_solve(args):
     """Port solve (eq. 7) of 16 coupled strips (256 x 128 x 4 grid, 16 ports),
     plain FP64 vs FP32 products inside FP64 refinement, both to relative
@@ -128,6 +192,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-basis5", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -191,7 +256,7 @@ def main():
     prof32, ncall = p.profile_read()
     p.profile(False)
     log(f"[bench] fp32 {args.steps} steps {dt32 * 1e3 / args.steps:.3f} ms/step  per-kernel ms/call "
-        + " ".join(f"{k}={v / max(ncall, 1):.3f}" for k, v in prof32.items()))
+        + " ".join(f"{k}={v / args.steps:.3f}" for k, v in prof32.items()))
 
     # FP64 path
     for _ in range(1):
@@ -214,7 +279,7 @@ def main():
     mv64 = nrhs * args.fp64_steps / dt64
     nvec = 3 * nrhs
     by32 = pass_bytes(p, nvec, 8, 4, K, nzp)
-    per_call = {k: v / max(ncall, 1) for k, v in prof32.items()}
+    per_call = {k: v / args.steps for k, v in prof32.items()}
     dom = max(by32, key=lambda k: per_call[k])
     ach = by32[dom] / (per_call[dom] * 1e-3) / 1e9
     total_bytes = sum(by32.values())
@@ -252,6 +317,8 @@ def main():
         "tucker_restore": {"ms": tk_ms, "tflops": tflops / (tk_ms * 1e-3) / 1e12 if tk_ms > 0 else None,
                            "mfma_frac": (tflops / (tk_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS) if tk_ms > 0 else None},
     }
+    if not args.no_basis5:
+        out["basis5"] = bench_basis5(args, cfg, mask, fidx, dev)
     if not args.no_solve:
         out["solve"] = bench_solve(args)
     if not args.no_cpu:

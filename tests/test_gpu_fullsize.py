@@ -86,3 +86,76 @@ def test_operator_symmetry_whole_grid(stack):
     a = np.sum(v * Zu)
     b = np.sum(u * Zv)
     assert abs(a - b) <= 1e-12 * abs(a), (a, b)
+
+
+@pytest.fixture(scope="module")
+def stack5():
+    """The same workload with the piecewise-linear basis (five components)."""
+    import paper_2105_08627_amd as svh
+    dev = torch.device("cuda")
+    cfg = wl.WORKLOADS["c5_stack"]
+    mask = cfg["mask"]()
+    p = svh.Problem(mask, cfg["dx"], basis=5)
+    p.set_material(cfg["freqs"], cfg["sigma0"], cfg["lam"])
+    p.setup_tensors()
+    ranks, bound = p.tucker_compress(1e-8)
+    nrhs = 64
+    fidx = [r % 8 for r in range(nrhs)]
+    x = wl.random_currents(cfg["seed"] + 5, (nrhs, 5, p.K))
+    x64 = torch.from_numpy(x).to(dev)
+    x32 = x64.to(torch.complex64)
+    p.autotune(x32, fidx)
+    y64 = p.matvec(x64, fidx).cpu().numpy()
+    y32 = p.matvec(x32, fidx).cpu().numpy().astype(np.complex128)
+    print(f"[fullsize5] K={p.K} ranks={ranks.tolist()} bound={bound:.2e}", flush=True)
+    return dict(p=p, mask=mask, cfg=cfg, x=x, fidx=fidx, y64=y64, y32=y32, dev=dev)
+
+
+def test_basis5_sampled_outputs_match_oracle(stack5):
+    """One sampled observer voxel, all 5 components x 64 RHS, against the
+    oracle's row sums built from its seven family rows (687,600 offsets each)
+    and the block table of eq. 8; Tucker tolerance 1e-8 per family, so the
+    bound is 1e-7 of the row scale (FP64) and 1e-5 (FP32)."""
+    cfg, mask, x = stack5["cfg"], stack5["mask"], stack5["x"]
+    P = op.voxel_coords(mask)
+    dx = cfg["dx"]
+    l = int(np.random.default_rng(78).integers(P.shape[0]))
+    off = P - P[l]
+    names = op.BASIS_SETS[5]
+    fam = {}
+    for n in green.FAMILIES:
+        fam[n] = green.family_values(n, off)
+        print(f"[fullsize5] observer {l} family {n}", flush=True)
+    for r, f in enumerate(stack5["fidx"]):
+        w = 2 * np.pi * cfg["freqs"][f]
+        c = op.material_c(cfg["freqs"][f], cfg["sigma0"], cfg["lam"])
+        s = 1j * w * op.MU0 * dx
+        for b in range(5):
+            conv = 0
+            mag = 0
+            for a in range(5):
+                row = sum(coef * fam[n] for coef, n in op.block_terms(names[b], names[a])) \
+                    if op.block_terms(names[b], names[a]) else None
+                if row is None:
+                    continue
+                conv = conv + row @ x[r, a]
+                mag += np.sum(row ** 2) * np.mean(np.abs(x[r, a]) ** 2)
+            diag = sum(op.mass_coefficient(names[b], names[a]) * x[r, a, l] for a in range(5)) * c / dx
+            ref = s * conv + diag
+            scale = abs(s) * np.sqrt(mag) + abs(ref)
+            e64 = abs(stack5["y64"][r, b, l] - ref) / scale
+            e32 = abs(stack5["y32"][r, b, l] - ref) / scale
+            assert e64 <= 1e-7, (l, r, b, e64)
+            assert e32 <= 1e-5, (l, r, b, e32)
+
+
+def test_basis5_operator_symmetry_whole_grid(stack5):
+    """u^T Z v = v^T Z u for the five-component operator over the full grid."""
+    p, dev = stack5["p"], stack5["dev"]
+    u = wl.random_currents(7, (1, 5, p.K))
+    v = wl.random_currents(8, (1, 5, p.K))
+    Zu = p.matvec(torch.from_numpy(u).to(dev), [2]).cpu().numpy()
+    Zv = p.matvec(torch.from_numpy(v).to(dev), [2]).cpu().numpy()
+    a = np.sum(v * Zu)
+    b = np.sum(u * Zv)
+    assert abs(a - b) <= 1e-12 * abs(a), (a, b)
