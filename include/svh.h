@@ -172,17 +172,23 @@ svh_status svh_profile_read(svh_problem* p, double* ms_out, int* ncalls_out);
 
 /* Choice of the z-direction step of the product (all choices give the same
  * operator up to rounding):
- *  SVH_ZSTEP_AUTO   (default) direct sum when at most 32 z planes hold voxels,
- *                   else the FFT along z;
+ *  SVH_ZSTEP_AUTO   (default) FUSED when it applies (basis 3, at most 32
+ *                   occupied z planes with at most 64 distinct plane
+ *                   offsets), else DIRECT when at most 32 planes are
+ *                   occupied, else FFT;
  *  SVH_ZSTEP_FFT    zero-padded FFT along z, product with the circulant
  *                   spectrum, inverse FFT (eq. 9 literally);
  *  SVH_ZSTEP_DIRECT after the x and y transforms, the Toeplitz sum along z
  *                   over the occupied planes with the inverse z transform of
- *                   the circulant spectrum (EINVAL if more than 32 planes).
+ *                   the circulant spectrum (EINVAL if more than 32 planes);
+ *  SVH_ZSTEP_FUSED  the same sum, with the y transform, the z sum and the
+ *                   inverse y transform of one x frequency in one kernel
+ *                   (EINVAL where it does not apply).
  * Basis 5 accepts AUTO and DIRECT only. */
 #define SVH_ZSTEP_AUTO 0
 #define SVH_ZSTEP_FFT 1
 #define SVH_ZSTEP_DIRECT 2
+#define SVH_ZSTEP_FUSED 3
 svh_status svh_set_zstep(svh_problem* p, int mode);
 
 /* ---------------------------------------------------------------- solve --

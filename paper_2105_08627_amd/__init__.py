@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsvh.so")
 
 SVH_FP64, SVH_FP32, SVH_FP32_IR = 0, 1, 2
-ZSTEP = {"auto": 0, "fft": 1, "direct": 2}
+ZSTEP = {"auto": 0, "fft": 1, "direct": 2, "fused": 3}
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: "ESTATE"}
 
 EXPORTED = [
@@ -201,7 +201,8 @@ class Problem:
         return y
 
     def set_zstep(self, mode):
-        """'auto', 'fft' (padded z FFT) or 'direct' (z-space sum over occupied planes)."""
+        """'auto', 'fft' (padded z FFT), 'direct' (z-space sum over occupied
+        planes) or 'fused' (that sum with the y transforms in one kernel)."""
         self._check(lib().svh_set_zstep(self._h, ZSTEP[mode]), "svh_set_zstep")
         self._ws.clear()
 

@@ -87,6 +87,7 @@ int choose_length(int K) {
 void free_dev_tucker(DevTucker& t) {
   dfree(t.core);
   dfree(t.Fz);
+  dfree(t.Fzd);
   for (int a = 0; a < 3; ++a) dfree(t.F[a]);
   t = DevTucker();
 }
@@ -174,7 +175,7 @@ svh_status svh_create(svh_problem** out, int Kx, int Ky, int Kz, double dx_m, in
     if (zocc[z]) p->zlist.push_back(z);
   p->zslot.assign(p->L[2], -1);
   for (size_t s = 0; s < p->zlist.size(); ++s) p->zslot[p->zlist[s]] = (int32_t)s;
-  if (basis == 5 && p->zlist.size() <= (size_t)kMaxDirectPlanes) {
+  if (p->zlist.size() <= (size_t)kMaxDirectPlanes) {
     // distinct plane offsets |z_i - z_j| and the per-(i, j) slot codes of the
     // coupled z step
     const int nzp = (int)p->zlist.size();
@@ -194,6 +195,27 @@ svh_status svh_create(svh_problem** out, int Kx, int Ky, int Kz, double dx_m, in
           q[i * 32 + j] = (uint8_t)(slot[std::abs(d)] | (d < 0 ? 0x80 : 0));
         }
       HIPCHK(upload(&p->d_qtab, q.data(), q.size()));
+    }
+  }
+  if (basis == 3 && p->d_qtab) {
+    // frequency phases of the fused y / z / inverse-y step per precision and
+    // the twiddles of the phase length Ly / phases
+    p->fused_r[SVH_FP64] = fused_phases(p, sizeof(double2), sizeof(double));
+    p->fused_r[SVH_FP32] = fused_phases(p, sizeof(float2), sizeof(float));
+    if (p->fused_r[0] > 0 && p->fused_r[1] > 0) {
+      const int P64 = p->L[1] / p->fused_r[0], P32 = p->L[1] / p->fused_r[1];
+      std::vector<double2> t64(P64);
+      std::vector<float2> t32(P32);
+      for (int m = 0; m < P64; ++m) {
+        const long double ang = 2.0L * 3.141592653589793238462643383279502884L * m / P64;
+        t64[m] = make_double2((double)cosl(ang), (double)-sinl(ang));
+      }
+      for (int m = 0; m < P32; ++m) {
+        const long double ang = 2.0L * 3.141592653589793238462643383279502884L * m / P32;
+        t32[m] = make_float2((float)cosl(ang), (float)-sinl(ang));
+      }
+      HIPCHK(upload(&p->d_twp64, t64.data(), t64.size()));
+      HIPCHK(upload(&p->d_twp32, t32.data(), t32.size()));
     }
   }
   HIPCHK(upload(&p->d_vidx, p->vidx.data(), Kt));
@@ -327,6 +349,8 @@ svh_status svh_setup_tensors(svh_problem* p, void* stream) {
   dfree(p->d_g32);
   dfree(p->d_g5_64);
   dfree(p->d_g5_32);
+  dfree(p->d_gt64);
+  dfree(p->d_gt32);
   p->diag_freq = -2;
   if (p->C == 5) {
     const svh_status st = setup_tensors5(p, s);
@@ -349,6 +373,13 @@ svh_status svh_setup_tensors(svh_problem* p, void* stream) {
   if (e == hipSuccess) e = launch_even_spectrum(p, dT, p->d_zhat64, t1, p->d_g64, s);
   if (e == hipSuccess) e = launch_to_f32(p->d_zhat64, p->d_zhat32, Lt, s);
   if (e == hipSuccess) e = launch_to_f32(p->d_g64, p->d_g32, n2, s);
+  if (e == hipSuccess && p->fused_r[0] > 0) {
+    const size_t ng = p->dzset.size() * (size_t)p->L[0] * p->L[1];
+    e = hipMalloc(&p->d_gt64, ng * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&p->d_gt32, ng * sizeof(float));
+    if (e == hipSuccess) e = launch_gather_transposed(p, p->d_g64, p->d_gt64, s);
+    if (e == hipSuccess) e = launch_to_f32(p->d_gt64, p->d_gt32, ng, s);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   hipFree(dT);
   if (t1) hipFree(t1);
@@ -427,12 +458,18 @@ svh_status svh_tucker_compress(svh_problem* p, double tol, int32_t* ranks_out, d
     for (int d = 0; d < p->K[2]; ++d) dz[d] = d;
     const std::vector<double> Fz = zspace_factor(tf, p->L[2], dz, false);
     HIPCHK(upload(&p->tk.Fz, Fz.data(), Fz.size()));
+    if (!p->dzset.empty()) {
+      const std::vector<double> Fzd = zspace_factor(tf, p->L[2], p->dzset, false);
+      HIPCHK(upload(&p->tk.Fzd, Fzd.data(), Fzd.size()));
+    }
   }
   p->tucker = true;
   dfree(p->d_zhat64);
   dfree(p->d_zhat32);
   dfree(p->d_g64);
   dfree(p->d_g32);
+  dfree(p->d_gt64);
+  dfree(p->d_gt32);
   if (ranks_out)
     for (int a = 0; a < 3; ++a) ranks_out[a] = tf.d[a];
   if (relerr_out) *relerr_out = tf.relerr;
@@ -443,6 +480,18 @@ size_t svh_workspace_bytes(const svh_problem* p, svh_prec prec, int nrhs) {
   if (!p || nrhs < 1) return 0;
   const size_t cs = prec == SVH_FP64 ? sizeof(double2) : sizeof(float2);
   const int cr = chunk_rhs(p, nrhs);
+  size_t bf = 0;  // the fused path's need (AUTO may switch to it after svh_autotune)
+  if (fused_eligible(p) && (p->zstep == SVH_ZSTEP_AUTO || p->zstep == SVH_ZSTEP_FUSED)) {
+    const GeoT gt = make_geo_t(p, cs);
+    bf = 2 * (((size_t)cr * p->C * p->zlist.size() * gt.pq * cs + 255) & ~(size_t)255);
+    if (p->tucker) {
+      const size_t ng = p->dzset.size() * (size_t)p->L[0] * p->L[1];
+      bf += ((ng * (prec == SVH_FP64 ? sizeof(double) : sizeof(float)) + 255) & ~(size_t)255);
+      bf += tucker_scratch_doubles(p) * sizeof(double);
+    }
+    bf += 1024;
+    if (p->zstep == SVH_ZSTEP_FUSED) return bf;
+  }
   size_t b = (size_t)cr * p->C * vec_bytes_AB(p, cs);
   if (p->tucker && p->C == 5) {
     const size_t gsz = (size_t)kNFam * p->dzset.size() * p->L[0] * p->L[1];
@@ -453,7 +502,7 @@ size_t svh_workspace_bytes(const svh_problem* p, svh_prec prec, int nrhs) {
     b += Lt * (prec == SVH_FP64 ? sizeof(double) : sizeof(float));
     b += tucker_scratch_doubles(p) * sizeof(double);
   }
-  return b + 1024;
+  return std::max(b + 1024, bf);
 }
 
 svh_status svh_matvec(svh_problem* p, svh_prec prec, int nrhs, const int32_t* freq_idx, const void* x,
@@ -466,6 +515,79 @@ svh_status svh_matvec(svh_problem* p, svh_prec prec, int nrhs, const int32_t* fr
 }  // extern "C"
 
 namespace svh {
+// Fused path: X pass (transposed store), fused y / z / inverse-y, inverse X
+// pass; the z-space kernel of the occupied plane offsets comes from setup or
+// from the Tucker factors.
+static svh_status matvec_fused(svh_problem* p, svh_prec prec, int nrhs, const int32_t* freq_idx, const void* x,
+                               long long ldx, void* y, long long ldy, void* ws, size_t ws_bytes, hipStream_t s,
+                               int cr) {
+  const bool dbl = prec == SVH_FP64;
+  const size_t cs = dbl ? sizeof(double2) : sizeof(float2);
+  auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const GeoT gt = make_geo_t(p, cs);
+  const size_t buf = align((size_t)cr * p->C * p->zlist.size() * gt.pq * cs);
+  char* w = static_cast<char*>(ws);
+  char* A = w;
+  char* O = w + buf;
+  const void* gk = dbl ? (const void*)p->d_gt64 : (const void*)p->d_gt32;
+  std::vector<hipEvent_t> evs;
+  if (p->prof) {
+    const int nchunk = (nrhs + cr - 1) / cr;
+    for (int i = 0; i < 8 * nchunk; ++i) {
+      hipEvent_t e;
+      if (!p->prof_pool.empty()) {
+        e = p->prof_pool.back();
+        p->prof_pool.pop_back();
+      } else {
+        HIPCHK(hipEventCreate(&e));
+      }
+      evs.push_back(e);
+    }
+    HIPCHK(hipEventRecord(evs[0], s));
+  }
+  if (p->tucker) {
+    char* zb = O + buf;
+    const size_t ng = p->dzset.size() * (size_t)p->L[0] * p->L[1];
+    double* V = reinterpret_cast<double*>(zb + align(ng * (dbl ? 8 : 4)));
+    double* Wt = V + (size_t)p->L[0] * p->tk.d[1] * p->tk.d[2];
+    if (reinterpret_cast<char*>(Wt + (size_t)p->L[0] * p->L[1] * p->tk.d[2]) > w + ws_bytes)
+      return fail(p, SVH_EINVAL, "matvec: workspace too small");
+    HIPCHK(launch_tucker_rebuild_rows(p, p->tk, p->tk.Fzd, (int)p->dzset.size(), !dbl, zb, V, Wt, s, true));
+    gk = zb;
+  } else if (!gk) {
+    return fail(p, SVH_ESTATE, "matvec: no z-space kernel");
+  }
+  if (p->prof) HIPCHK(hipEventRecord(evs[1], s));
+  const char* xb = static_cast<const char*>(x);
+  for (int r0 = 0; r0 < nrhs; r0 += cr) {
+    const int nr = std::min(cr, nrhs - r0);
+    hipEvent_t* ev = nullptr;
+    if (p->prof) {
+      ev = &evs[8 * (r0 / cr) + 2];
+      if (r0 > 0) {
+        HIPCHK(hipEventRecord(evs[8 * (r0 / cr)], s));
+        HIPCHK(hipEventRecord(evs[8 * (r0 / cr) + 1], s));
+      }
+    }
+    EpiParams ep;
+    ep.C = p->C;
+    ep.K = p->nvox;
+    ep.vec0 = 0;
+    ep.ldx = ldx;
+    ep.ldy = ldy;
+    for (int i = 0; i < kMaxVecsPerChunk; ++i) ep.fidx[i] = -1;
+    for (int i = 0; i < nr; ++i) ep.fidx[i] = freq_idx[r0 + i];
+    const char* xc = xb + (size_t)r0 * ldx * cs;
+    char* yc = static_cast<char*>(y) + (size_t)r0 * ldy * cs;
+    hipError_t e = dbl ? launch_matvec_chunk_fused<double>(p, nr * p->C, ep, xc, yc, A, O, gk, s, ev)
+                       : launch_matvec_chunk_fused<float>(p, nr * p->C, ep, xc, yc, A, O, gk, s, ev);
+    HIPCHK(e);
+  }
+  for (size_t i = 0; i < evs.size(); i += 8)
+    p->prof_events.push_back(std::vector<hipEvent_t>(evs.begin() + i, evs.begin() + i + 8));
+  return SVH_OK;
+}
+
 svh_status matvec_impl(svh_problem* p, svh_prec prec, int nrhs, const int32_t* freq_idx, const void* x,
                        long long ldx, void* y, long long ldy, void* ws, size_t ws_bytes, hipStream_t s) {
   if (nrhs < 1 || !freq_idx || !x || !y || !ws) return fail(p, SVH_EINVAL, "matvec: bad arguments");
@@ -491,6 +613,7 @@ svh_status matvec_impl(svh_problem* p, svh_prec prec, int nrhs, const int32_t* f
   auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
   const int cr = chunk_rhs(p, nrhs);
   const size_t nzp = p->zlist.size();
+  if (use_fused(p, prec)) return matvec_fused(p, prec, nrhs, freq_idx, x, ldx, y, ldy, ws, ws_bytes, s, cr);
   const Geo geo = make_geo(p, cs);
   const size_t Abytes = align((size_t)cr * p->C * nzp * geo.pa * cs);
   const size_t Bbytes = (size_t)cr * p->C * nzp * geo.pb * cs;
@@ -603,8 +726,24 @@ svh_status svh_autotune(svh_problem* p, svh_prec prec, int nrhs, const int32_t* 
       }
     }
   }
-  p->prof = was_prof;
   p->tune[prec] = best;
+  if (st == SVH_OK && p->zstep == SVH_ZSTEP_AUTO && fused_eligible(p)) {
+    // AUTO: keep the faster of the separate passes and the fused step
+    double tot[2] = {0, 0};
+    for (int v = 0; v < 2 && st == SVH_OK; ++v) {
+      p->auto_fused[prec] = v == 1;
+      st = svh_matvec(p, prec, nrhs, freq_idx, x, y, ws, ws_bytes, stream);  // warm-up
+      double ms[SVH_NPROF];
+      int n = 0;
+      if (st == SVH_OK) st = svh_profile_read(p, ms, &n);
+      for (int rep = 0; rep < 2 && st == SVH_OK; ++rep)
+        st = svh_matvec(p, prec, nrhs, freq_idx, x, y, ws, ws_bytes, stream);
+      if (st == SVH_OK) st = svh_profile_read(p, ms, &n);
+      for (int i = 0; i < SVH_NPROF && st == SVH_OK; ++i) tot[v] += ms[i];
+    }
+    p->auto_fused[prec] = st == SVH_OK && tot[1] < tot[0];
+  }
+  p->prof = was_prof;
   if (st != SVH_OK) return st;
   HIPCHK(hipStreamSynchronize(s));
   if (ms_out) {
@@ -624,8 +763,12 @@ svh_status svh_autotune(svh_problem* p, svh_prec prec, int nrhs, const int32_t* 
 
 svh_status svh_set_zstep(svh_problem* p, int mode) {
   if (!p) return SVH_EINVAL;
-  if (mode != SVH_ZSTEP_AUTO && mode != SVH_ZSTEP_FFT && mode != SVH_ZSTEP_DIRECT)
+  if (mode != SVH_ZSTEP_AUTO && mode != SVH_ZSTEP_FFT && mode != SVH_ZSTEP_DIRECT && mode != SVH_ZSTEP_FUSED)
     return fail(p, SVH_EINVAL, "set_zstep: unknown mode");
+  if (mode == SVH_ZSTEP_FUSED && (p->C != 3 || p->fused_r[0] <= 0 || p->fused_r[1] <= 0 ||
+                                  p->zlist.size() > (size_t)kMaxDirectPlanes))
+    return fail(p, SVH_EINVAL, "set_zstep: the fused step needs basis 3 and at most 32 occupied planes with at "
+                               "most 64 distinct plane offsets");
   if (p->C == 5 && mode == SVH_ZSTEP_FFT)
     return fail(p, SVH_EINVAL, "set_zstep: the piecewise-linear basis runs the direct z step only");
   if (mode == SVH_ZSTEP_DIRECT && (int)p->zlist.size() > kMaxDirectPlanes)
@@ -688,6 +831,10 @@ void svh_destroy(svh_problem* p) {
   dfree(p->d_g32);
   dfree(p->d_g5_64);
   dfree(p->d_g5_32);
+  dfree(p->d_gt64);
+  dfree(p->d_gt32);
+  dfree(p->d_twp64);
+  dfree(p->d_twp32);
   dfree(p->d_qtab);
   free_tucker(p);
   svh::free_solver(p);

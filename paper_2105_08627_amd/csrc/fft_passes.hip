@@ -14,347 +14,11 @@
 //        scatter to the compact output
 // Only z planes that hold at least one non-empty voxel are stored between
 // passes (the others are zero on input and not needed on output).
-//
-// Stockham stage with radix R after Ns previous points (natural order out):
-//   in  v_r = src[j + r L/R],  twiddle  v_r *= w_L^(r (j mod Ns) L/(Ns R))
-//   R-point DFT, out dst[(j / Ns) Ns R + (j mod Ns) + r Ns].
-#include <type_traits>
-#include <utility>
-
-#include "svh_internal.h"
+#include "fft_core.h"
 
 namespace svh {
 
-template <typename T> struct CT;
-template <> struct CT<double> { typedef double2 t; };
-template <> struct CT<float> { typedef float2 t; };
-
-template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
-template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
-template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
-  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-template <typename C, typename T> __device__ __forceinline__ C cscale(C a, T s) { return C{a.x * s, a.y * s}; }
-// multiply by DIR * i
-template <int DIR, typename C> __device__ __forceinline__ C mul_i(C a) {
-  return DIR < 0 ? C{a.y, -a.x} : C{-a.y, a.x};
-}
-
-template <int DIR, typename C> __device__ __forceinline__ void dft2(C* v) {
-  const C a = v[0];
-  v[0] = cadd(a, v[1]);
-  v[1] = csub(a, v[1]);
-}
-
-template <int DIR, typename C> __device__ __forceinline__ void dft4(C& v0, C& v1, C& v2, C& v3) {
-  const C a0 = cadd(v0, v2), a1 = csub(v0, v2), a2 = cadd(v1, v3);
-  const C a3 = mul_i<DIR>(csub(v1, v3));
-  v0 = cadd(a0, a2);
-  v2 = csub(a0, a2);
-  v1 = cadd(a1, a3);
-  v3 = csub(a1, a3);
-}
-
-template <int DIR, typename C> __device__ __forceinline__ void dft4(C* v) { dft4<DIR>(v[0], v[1], v[2], v[3]); }
-
-template <int DIR, typename C> __device__ __forceinline__ void dft8(C* v) {
-  typedef decltype(v[0].x) T;
-  C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
-  C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
-  dft4<DIR>(e0, e1, e2, e3);
-  dft4<DIR>(o0, o1, o2, o3);
-  const T h = (T)0.70710678118654752440;
-  // o1 *= w^1, o2 *= w^2 = DIR i, o3 *= w^3 with w = exp(DIR i pi / 4)
-  o1 = C{h * (o1.x - DIR * o1.y), h * (o1.y + DIR * o1.x)};
-  o2 = mul_i<DIR>(o2);
-  o3 = C{h * (-o3.x - DIR * o3.y), h * (-o3.y + DIR * o3.x)};
-  v[0] = cadd(e0, o0);
-  v[4] = csub(e0, o0);
-  v[1] = cadd(e1, o1);
-  v[5] = csub(e1, o1);
-  v[2] = cadd(e2, o2);
-  v[6] = csub(e2, o2);
-  v[3] = cadd(e3, o3);
-  v[7] = csub(e3, o3);
-}
-
-template <int DIR, typename C> __device__ __forceinline__ void dft3(C* v) {
-  typedef decltype(v[0].x) T;
-  const T s3 = (T)0.86602540378443864676;
-  const C t1 = cadd(v[1], v[2]);
-  const C t2 = C{v[0].x - (T)0.5 * t1.x, v[0].y - (T)0.5 * t1.y};
-  const C d = mul_i<DIR>(cscale(csub(v[1], v[2]), s3));
-  v[0] = cadd(v[0], t1);
-  v[1] = cadd(t2, d);
-  v[2] = csub(t2, d);
-}
-
-template <int R, int DIR, typename C> __device__ __forceinline__ void dft(C* v) {
-  if constexpr (R == 2) dft2<DIR>(v);
-  else if constexpr (R == 3) dft3<DIR>(v);
-  else if constexpr (R == 4) dft4<DIR>(v);
-  else dft8<DIR>(v);
-}
-
-template <int R> struct NbMax { static constexpr int v = R == 8 ? 1 : R == 4 ? 2 : R == 3 ? 3 : 4; };
-
-// LDS accessors.  Strided layout: element (n, w) at n * W + w.  Pencil
-// layout: element (n, w) at w * Lp + n + n / 8 (one pad slot every eight
-// elements keeps the stride-R writes of the first stages off a single bank).
-__host__ __device__ constexpr int pencil_pitch(int L) { return L + L / 8 + 1; }
-template <typename C, bool STRIDED> struct Lds {
-  C* base;
-  int W, Lp, w;
-  __device__ __forceinline__ C ld(int n) const {
-    return STRIDED ? base[n * W + w] : base[w * Lp + n + (n >> 3)];
-  }
-  __device__ __forceinline__ void st(int n, C v) const {
-    if (STRIDED) base[n * W + w] = v;
-    else base[w * Lp + n + (n >> 3)] = v;
-  }
-};
-
-template <typename C, int R, int DIR, bool SYNC_MID, class Src, class Dst>
-__device__ __forceinline__ void stage_r(int L, int Ns, int j0, int TP, const Src& src, const Dst& dst,
-                                        const C* __restrict__ tw) {
-  constexpr int NB = NbMax<R>::v;
-  const int LR = L / R;
-  C v[NB][R];
-#pragma unroll
-  for (int it = 0; it < NB; ++it) {
-    const int j = j0 + it * TP;
-    if (j < LR) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[it][r] = src.ld(j + r * LR);
-    }
-  }
-  if (SYNC_MID) __syncthreads();
-#pragma unroll
-  for (int it = 0; it < NB; ++it) {
-    const int j = j0 + it * TP;
-    if (j < LR) {
-      const int k = j % Ns;
-      if (Ns > 1) {
-        const int step = L / (Ns * R);
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          C t = tw[r * k * step];
-          if (DIR > 0) t.y = -t.y;
-          v[it][r] = cmul(v[it][r], t);
-        }
-      }
-      dft<R, DIR>(v[it]);
-      const int base = (j / Ns) * Ns * R + k;
-#pragma unroll
-      for (int r = 0; r < R; ++r) dst.st(base + r * Ns, v[it][r]);
-    }
-  }
-}
-
-template <typename C, int DIR, bool SYNC_MID, class Src, class Dst>
-__device__ __forceinline__ void stage_any(int R, int L, int Ns, int j0, int TP, const Src& src,
-                                          const Dst& dst, const C* tw) {
-  switch (R) {
-    case 8: stage_r<C, 8, DIR, SYNC_MID>(L, Ns, j0, TP, src, dst, tw); break;
-    case 4: stage_r<C, 4, DIR, SYNC_MID>(L, Ns, j0, TP, src, dst, tw); break;
-    case 3: stage_r<C, 3, DIR, SYNC_MID>(L, Ns, j0, TP, src, dst, tw); break;
-    default: stage_r<C, 2, DIR, SYNC_MID>(L, Ns, j0, TP, src, dst, tw); break;
-  }
-}
-
-// One full 1D transform of a group of pencils: global -> (LDS stages) -> global.
-template <typename C, int DIR, bool STRIDED, class GIn, class GOut>
-__device__ __forceinline__ void fft_group(const FftPlan& pl, int j0, const GIn& gin, const GOut& gout,
-                                          const Lds<C, STRIDED>& lds, const C* tw) {
-  const int L = pl.L, TP = pl.tp;
-  if (pl.ns == 1) {
-    stage_any<C, DIR, false>(pl.r[0], L, 1, j0, TP, gin, gout, tw);
-    return;
-  }
-  int Ns = 1;
-  stage_any<C, DIR, false>(pl.r[0], L, Ns, j0, TP, gin, lds, tw);
-  Ns *= pl.r[0];
-  __syncthreads();
-  for (int s = 1; s < pl.ns - 1; ++s) {
-    stage_any<C, DIR, true>(pl.r[s], L, Ns, j0, TP, lds, lds, tw);
-    Ns *= pl.r[s];
-    __syncthreads();
-  }
-  stage_any<C, DIR, false>(pl.r[pl.ns - 1], L, Ns, j0, TP, lds, gout, tw);
-}
-
-// First stage split into its global loads and the rest (Ns = 1: no twiddles),
-// so that a block can issue the loads of its next item before it runs the
-// LDS stages of the current one.
-template <typename C, int R, class Src>
-__device__ __forceinline__ void load0_r(int L, int j0, int TP, const Src& src, C (&v)[12]) {
-  constexpr int NB = NbMax<R>::v;
-  const int LR = L / R;
-#pragma unroll
-  for (int it = 0; it < NB; ++it) {
-    const int j = j0 + it * TP;
-    if (j < LR) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[it * R + r] = src.ld(j + r * LR);
-    }
-  }
-}
-template <typename C, int R, int DIR, class Dst>
-__device__ __forceinline__ void fin0_r(int L, int j0, int TP, C (&v)[12], const Dst& dst) {
-  constexpr int NB = NbMax<R>::v;
-  const int LR = L / R;
-#pragma unroll
-  for (int it = 0; it < NB; ++it) {
-    const int j = j0 + it * TP;
-    if (j < LR) {
-      dft<R, DIR>(&v[it * R]);
-#pragma unroll
-      for (int r = 0; r < R; ++r) dst.st(j * R + r, v[it * R + r]);
-    }
-  }
-}
-template <typename C, class Src>
-__device__ __forceinline__ void load0(int R, int L, int j0, int TP, const Src& src, C (&v)[12]) {
-  switch (R) {
-    case 8: load0_r<C, 8>(L, j0, TP, src, v); break;
-    case 4: load0_r<C, 4>(L, j0, TP, src, v); break;
-    case 3: load0_r<C, 3>(L, j0, TP, src, v); break;
-    default: load0_r<C, 2>(L, j0, TP, src, v); break;
-  }
-}
-template <typename C, int DIR, class Dst>
-__device__ __forceinline__ void fin0(int R, int L, int j0, int TP, C (&v)[12], const Dst& dst) {
-  switch (R) {
-    case 8: fin0_r<C, 8, DIR>(L, j0, TP, v, dst); break;
-    case 4: fin0_r<C, 4, DIR>(L, j0, TP, v, dst); break;
-    case 3: fin0_r<C, 3, DIR>(L, j0, TP, v, dst); break;
-    default: fin0_r<C, 2, DIR>(L, j0, TP, v, dst); break;
-  }
-}
-
-// Persistent loop over items (groups of pencils): item i's first-stage loads
-// are issued while item i-1 runs its LDS stages and stores.
-template <typename C, int DIR, bool STRIDED, class MkIn, class MkOut>
-__device__ __forceinline__ void fft_items(const FftPlan& pl, int j0, int nitems, const MkIn& mk_in,
-                                          const MkOut& mk_out, const Lds<C, STRIDED>& lds, const C* tw) {
-  const int L = pl.L, TP = pl.tp;
-  C v[12];
-  int item = blockIdx.x;
-  if (item < nitems) load0(pl.r[0], L, j0, TP, mk_in(item), v);
-  for (; item < nitems; item += gridDim.x) {
-    const int next = item + gridDim.x;
-    if (pl.ns == 1) {
-      fin0<C, DIR>(pl.r[0], L, j0, TP, v, mk_out(item));
-      if (next < nitems) load0(pl.r[0], L, j0, TP, mk_in(next), v);
-      continue;
-    }
-    fin0<C, DIR>(pl.r[0], L, j0, TP, v, lds);
-    __syncthreads();
-    if (next < nitems) load0(pl.r[0], L, j0, TP, mk_in(next), v);
-    int Ns = pl.r[0];
-    for (int s = 1; s < pl.ns - 1; ++s) {
-      stage_any<C, DIR, true>(pl.r[s], L, Ns, j0, TP, lds, lds, tw);
-      Ns *= pl.r[s];
-      __syncthreads();
-    }
-    stage_any<C, DIR, false>(pl.r[pl.ns - 1], L, Ns, j0, TP, lds, mk_out(item), tw);
-    __syncthreads();
-  }
-}
-
-// Compile-time plans for the common lengths: all radices, strides and trip
-// counts are constants, which keeps every stage in registers (the runtime
-// plan above is the fallback for other lengths).
-__host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
-template <int R0, int R1 = 1, int R2 = 1, int R3 = 1>
-struct PlanC {
-  static constexpr bool rt = false;
-  static constexpr int ns = R1 == 1 ? 1 : R2 == 1 ? 2 : R3 == 1 ? 3 : 4;
-  static constexpr int L = R0 * R1 * R2 * R3;
-  static constexpr int r(int s) { return s == 0 ? R0 : s == 1 ? R1 : s == 2 ? R2 : R3; }
-  static constexpr int tp = cmin(cmin(L / R0, R1 > 1 ? L / R1 : L), cmin(R2 > 1 ? L / R2 : L, R3 > 1 ? L / R3 : L));
-  __host__ __device__ static constexpr int Lof(const FftPlan&) { return L; }
-  __host__ __device__ static constexpr int tpof(const FftPlan&) { return tp; }
-};
-struct PlanRT {
-  static constexpr bool rt = true;
-  __host__ __device__ static int Lof(const FftPlan& p) { return p.L; }
-  __host__ __device__ static int tpof(const FftPlan& p) { return p.tp; }
-};
-
-template <class P, typename C, int DIR, bool STRIDED, class MkIn, class MkOut>
-__device__ __forceinline__ void fft_items_c(int j0, int nitems, const MkIn& mk_in, const MkOut& mk_out,
-                                            const Lds<C, STRIDED>& lds, const C* tw) {
-  constexpr int L = P::L, TP = P::tp;
-  constexpr int R0 = P::r(0);
-  C v[12];
-  int item = blockIdx.x;
-  if (item < nitems) load0_r<C, R0>(L, j0, TP, mk_in(item), v);
-  for (; item < nitems; item += gridDim.x) {
-    const int next = item + gridDim.x;
-    if constexpr (P::ns == 1) {
-      fin0_r<C, R0, DIR>(L, j0, TP, v, mk_out(item));
-      if (next < nitems) load0_r<C, R0>(L, j0, TP, mk_in(next), v);
-    } else {
-      fin0_r<C, R0, DIR>(L, j0, TP, v, lds);
-      __syncthreads();
-      if (next < nitems) load0_r<C, R0>(L, j0, TP, mk_in(next), v);
-      constexpr int N1 = R0;
-      if constexpr (P::ns == 2) {
-        stage_r<C, P::r(1), DIR, false>(L, N1, j0, TP, lds, mk_out(item), tw);
-      } else {
-        stage_r<C, P::r(1), DIR, true>(L, N1, j0, TP, lds, lds, tw);
-        __syncthreads();
-        constexpr int N2 = N1 * P::r(1);
-        if constexpr (P::ns == 3) {
-          stage_r<C, P::r(2), DIR, false>(L, N2, j0, TP, lds, mk_out(item), tw);
-        } else {
-          stage_r<C, P::r(2), DIR, true>(L, N2, j0, TP, lds, lds, tw);
-          __syncthreads();
-          constexpr int N3 = N2 * P::r(2);
-          stage_r<C, P::r(3), DIR, false>(L, N3, j0, TP, lds, mk_out(item), tw);
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-template <class P, typename C, int DIR, bool STRIDED, class MkIn, class MkOut>
-__device__ __forceinline__ void run_items(const FftPlan& pl, int j0, int nitems, const MkIn& mk_in,
-                                          const MkOut& mk_out, const Lds<C, STRIDED>& lds, const C* tw) {
-  if constexpr (P::rt) fft_items<C, DIR, STRIDED>(pl, j0, nitems, mk_in, mk_out, lds, tw);
-  else fft_items_c<P, C, DIR, STRIDED>(j0, nitems, mk_in, mk_out, lds, tw);
-}
-
-// Calls f(PlanC<...>{}) for the lengths with a compile-time plan, else f(PlanRT{}).
-template <class F>
-void with_plan(int L, F&& f) {
-  switch (L) {
-    case 16: f(PlanC<4, 4>{}); break;
-    case 32: f(PlanC<8, 4>{}); break;
-    case 64: f(PlanC<8, 8>{}); break;
-    case 128: f(PlanC<8, 4, 4>{}); break;
-    case 192: f(PlanC<8, 8, 3>{}); break;
-    case 256: f(PlanC<8, 8, 4>{}); break;
-    case 512: f(PlanC<8, 8, 8>{}); break;
-    case 1024: f(PlanC<8, 8, 4, 4>{}); break;
-    default: f(PlanRT{}); break;
-  }
-}
-
 // ----------------------------------------------------------------- X pass --
-template <typename C> struct XIn {
-  const C* __restrict__ x;       // compact vector of this component
-  const int32_t* __restrict__ vrow;  // voxel index row (Kx entries)
-  int Kx;
-  bool valid;
-  __device__ __forceinline__ C ld(int n) const {
-    if (!valid || n >= Kx) return C{0, 0};
-    const int k = vrow[n];
-    return k >= 0 ? x[k] : C{0, 0};
-  }
-};
 template <typename C> struct RowOut {
   C* __restrict__ row;
   int lim;
@@ -427,10 +91,6 @@ template <typename C> struct ColOut {
 
 // DIR = -1: A[vec][zp][y < Ky][kx] -> B[vec][zp][ky < Ly][kx]
 // DIR = +1: B -> A (crop to y < Ky)
-// Block size limit: 1024 threads for FP32, 512 for FP64 (which leaves 256
-// VGPRs per lane for the double-width butterflies).
-template <typename T> struct MaxThreads { static constexpr int v = sizeof(T) == 8 ? 512 : 1024; };
-
 template <typename T, int DIR, class P>
 __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_y(FftPlan pl, Geo geo, int W, int Lx, int Ky, int nzp, int nvec,
                                                  const typename CT<T>::t* __restrict__ in,
@@ -843,25 +503,6 @@ __global__ void __launch_bounds__(256) k_zdirect5(Geo geo, int Lx, int Ly, int n
 }
 
 // --------------------------------------------------------------- Xi pass --
-template <typename C, typename T> struct XOut {
-  C* __restrict__ y;                 // compact output of this component
-  const C* __restrict__ x;           // compact input (diagonal term)
-  const C* __restrict__ cd;          // c/dx per voxel (nullptr: bare)
-  const int32_t* __restrict__ vrow;
-  C scale;
-  T mass;                            // integral of the squared basis function (eqs. 9, 16-18)
-  int Kx;
-  bool valid;
-  __device__ __forceinline__ void st(int n, C v) const {
-    if (!valid || n >= Kx) return;
-    const int k = vrow[n];
-    if (k < 0) return;
-    C o = cmul(v, scale);
-    if (cd) o = cadd(o, cscale(cmul(cd[k], x[k]), mass));
-    y[k] = o;
-  }
-};
-
 template <typename T, class P>
 __global__ void __launch_bounds__(256) k_pass_xi(FftPlan pl, Geo geo, int WX, int Kx, int Ky, int nzp, int K, int nvec,
                                                   EpiParams ep, const int32_t* __restrict__ zlist,
@@ -920,16 +561,6 @@ Geo make_geo(const svh_problem* p, size_t csize) {
   g.pa = (long long)p->K[1] * g.rp + (long long)(256 / csize);
   g.pb = (long long)p->L[1] * g.rp + (long long)(256 / csize);
   return g;
-}
-
-// Blocks of a persistent launch: as many as can be resident at once.
-static int persistent_grid(const void* kernel, int threads, size_t shmem, int nitems, int ncu, int mult) {
-  if (mult <= 0) return nitems;
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, shmem) != hipSuccess || per_cu < 1)
-    per_cu = 1;
-  const long long g = (long long)per_cu * ncu * mult;
-  return (int)(g < nitems ? g : nitems);
 }
 
 bool use_zdirect(const svh_problem* p) {

@@ -41,6 +41,7 @@ struct DevTucker {
   double* core = nullptr;  // [c][b][a]
   double* F[3] = {nullptr, nullptr, nullptr};  // [k][c]
   double* Fz = nullptr;  // [dz][c], dz < Kz: inverse z transform of F[2] (z-space factor)
+  double* Fzd = nullptr; // [slot][c]: the same at the occupied plane offsets only
 };
 
 // Per-call kernel parameters of the final (x-inverse) pass.
@@ -60,6 +61,13 @@ struct Geo {
   int rp;          // row pitch
   long long pa;    // plane stride of A
   long long pb;    // plane stride of B
+};
+
+// Transposed buffers of the fused path: element (vec, plane, kx, y) at
+// (vec * nzp + plane) * pq + kx * cp + y.
+struct GeoT {
+  int cp;          // column pitch (>= Ky)
+  long long pq;    // plane stride
 };
 
 // Launch choices of the FFT passes, picked by svh_autotune per precision.
@@ -113,6 +121,15 @@ struct svh_problem {
   float* d_zhat32 = nullptr;
   double* d_g64 = nullptr;      // dense z-space kernel [Kz][Ly][Lx] (real)
   float* d_g32 = nullptr;
+  // fused y / z / inverse-y path: z-space kernel at the occupied plane
+  // offsets, transposed in (x, y): [slot][kx][ky]; frequency phases per
+  // precision (index SVH_FP64, SVH_FP32) and twiddles of length Ly / phases
+  double* d_gt64 = nullptr;
+  float* d_gt32 = nullptr;
+  int fused_r[2] = {0, 0};
+  bool auto_fused[2] = {false, false};  // AUTO mode: the autotuner timed FUSED faster
+  double2* d_twp64 = nullptr;
+  float2* d_twp32 = nullptr;
   int zstep = 0;                // SVH_ZSTEP_AUTO / _FFT / _DIRECT
   svh::Tune tune[2];            // per precision (SVH_FP64, SVH_FP32)
   bool tucker = false;
@@ -150,7 +167,14 @@ hipError_t launch_tucker_rebuild(const svh_problem* p, bool fp32_out, bool zspac
 // Tucker restoration of one family's z-space kernel rows (factor Fz3 has M3
 // rows): out[m][ky][kx] = sum core F1 F2 Fz3.
 hipError_t launch_tucker_rebuild_rows(const svh_problem* p, const DevTucker& t, const double* Fz3, int M3,
-                                      bool fp32_out, void* d_out, double* d_V, double* d_W, hipStream_t s);
+                                      bool fp32_out, void* d_out, double* d_V, double* d_W, hipStream_t s,
+                                      bool xy_transposed = false);
+// out[q][kx][ky] = in[dz_q][ky][kx] (z-space kernel rows of the fused path)
+hipError_t launch_gather_transposed(const svh_problem* p, const double* d_in, double* d_out, hipStream_t s);
+GeoT make_geo_t(const svh_problem* p, size_t csize);
+int fused_phases(const svh_problem* p, size_t cs, size_t ts);
+bool fused_eligible(const svh_problem* p);
+bool use_fused(const svh_problem* p, svh_prec prec);
 // Seven family tables [f][Kz][Ky][Kx] on the device (quadrature; f = 0 is
 // recomputed by the caller from the closed form).
 hipError_t family_tables(const int K[3], double* d_out, hipStream_t s);
@@ -168,6 +192,9 @@ svh_status matvec_impl(svh_problem* p, svh_prec prec, int nrhs, const int32_t* f
 size_t tucker_scratch_doubles(const svh_problem* p);
 hipError_t launch_to_f32(const double* in, float* out, size_t n, hipStream_t s);
 
+template <typename T>
+hipError_t launch_matvec_chunk_fused(const svh_problem* p, int nvec, const EpiParams& ep, const void* x, void* y,
+                                     void* A, void* O, const void* gk, hipStream_t s, hipEvent_t* ev);
 template <typename T>
 hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& ep,
                                const void* x, void* y, void* A, void* B, const void* zhat,

@@ -146,13 +146,17 @@ size_t tucker_scratch_doubles5(const svh_problem* p) {
 }
 
 hipError_t launch_tucker_rebuild_rows(const svh_problem* p, const DevTucker& t, const double* Fz3, int M3,
-                                      bool fp32_out, void* d_out, double* d_V, double* d_W, hipStream_t s) {
+                                      bool fp32_out, void* d_out, double* d_V, double* d_W, hipStream_t s,
+                                      bool xy_transposed) {
   const int L1 = p->L[0], L2 = p->L[1];
   const int d1 = t.d[0], d2 = t.d[1], d3 = t.d[2];
   hipError_t e;
   GemmArgs g1{L1, d2 * d3, d1, t.F[0], d1, 1, 0, t.core, 1, d1, 0, d_V, (long long)d2 * d3, 1, 0};
   if ((e = gemm(g1, 1, false, s)) != hipSuccess) return e;
-  GemmArgs g2{L2, d3, d2, t.F[1], d2, 1, 0, d_V, 1, d2, (long long)d2 * d3, d_W, (long long)L1 * d3, 1, d3};
+  // W[ky][kx][c] (or W[kx][ky][c] when transposed) = sum_b F2[ky][b] V[kx][c][b]
+  const long long scm = xy_transposed ? d3 : (long long)L1 * d3;
+  const long long scb = xy_transposed ? (long long)L2 * d3 : d3;
+  GemmArgs g2{L2, d3, d2, t.F[1], d2, 1, 0, d_V, 1, d2, (long long)d2 * d3, d_W, scm, 1, scb};
   if ((e = gemm(g2, L1, false, s)) != hipSuccess) return e;
   GemmArgs g3{M3, L1 * L2, d3, Fz3, d3, 1, 0, d_W, 1, d3, 0, d_out, (long long)L1 * L2, 1, 0};
   return gemm(g3, 1, fp32_out, s);
@@ -165,6 +169,33 @@ hipError_t launch_tucker_rebuild(const svh_problem* p, bool fp32_out, bool zspac
   const DevTucker& t = p->tk;
   return launch_tucker_rebuild_rows(p, t, zspace ? t.Fz : t.F[2], zspace ? p->K[2] : p->L[2], fp32_out, d_out,
                                     d_V, d_W, s);
+}
+
+__global__ void k_gather_t(const double* __restrict__ in, double* __restrict__ out, const int32_t* __restrict__ dz,
+                           int nd, int Lx, int Ly) {
+  const size_t total = (size_t)nd * Lx * Ly;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < total; id += (size_t)gridDim.x * blockDim.x) {
+    const int ky = (int)(id % Ly);
+    const size_t rest = id / Ly;
+    const int kx = (int)(rest % Lx);
+    const int q = (int)(rest / Lx);
+    out[id] = in[((size_t)dz[q] * Ly + ky) * Lx + kx];
+  }
+}
+
+hipError_t launch_gather_transposed(const svh_problem* p, const double* d_in, double* d_out, hipStream_t s) {
+  int32_t* d_dz = nullptr;
+  const int nd = (int)p->dzset.size();
+  hipError_t e = hipMalloc(&d_dz, sizeof(int32_t) * nd);
+  if (e != hipSuccess) return e;
+  e = hipMemcpy(d_dz, p->dzset.data(), sizeof(int32_t) * nd, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_gather_t, dim3(2048), dim3(256), 0, s, d_in, d_out, d_dz, nd, p->L[0], p->L[1]);
+    e = hipGetLastError();
+  }
+  hipError_t e2 = hipStreamSynchronize(s);
+  hipFree(d_dz);
+  return e != hipSuccess ? e : e2;
 }
 
 // Parity of the seven families per axis (x, y, z): M1 of axis a is odd along a.

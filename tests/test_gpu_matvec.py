@@ -84,7 +84,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("zstep", ["fft", "direct"])
+@pytest.mark.parametrize("zstep", ["fft", "direct", "fused"])
 @pytest.mark.parametrize("K,fill,seed", CASES)
 def test_random_masks_multi_rhs(K, fill, seed, zstep, dev):
     mask = wl.random_mask(seed, *K, fill=fill)
@@ -103,7 +103,7 @@ def test_random_masks_multi_rhs(K, fill, seed, zstep, dev):
     assert np.all(e32 <= 1e-5)
 
 
-@pytest.mark.parametrize("zstep", ["fft", "direct"])
+@pytest.mark.parametrize("zstep", ["fft", "direct", "fused"])
 def test_empty_planes_pruned(dev, zstep):
     """Only z planes 0, 4 and 9 hold voxels; the others are skipped."""
     mask = np.zeros((10, 12, 16), dtype=np.uint8)
@@ -120,7 +120,7 @@ def test_empty_planes_pruned(dev, zstep):
     assert np.all(err <= 1e-12), err
 
 
-@pytest.mark.parametrize("zstep", ["fft", "direct"])
+@pytest.mark.parametrize("zstep", ["fft", "direct", "fused"])
 @pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)])
 def test_tucker_full_rank_matches_exact(dev, dtype, tol, zstep):
     """Untruncated Tucker factors restore the spectrum exactly (eq. 10), so the
@@ -138,7 +138,7 @@ def test_tucker_full_rank_matches_exact(dev, dtype, tol, zstep):
     assert np.all(err <= tol)
 
 
-@pytest.mark.parametrize("zstep", ["fft", "direct"])
+@pytest.mark.parametrize("zstep", ["fft", "direct", "fused"])
 @pytest.mark.parametrize("ttol", [1e-4, 1e-6, 1e-8])
 def test_tucker_truncated_error_tracks_tolerance(dev, ttol, zstep):
     """Truncated factors (Algorithm 1 at tol): the operator error stays at the
@@ -190,3 +190,29 @@ def test_autotuned_launch_shapes_keep_parity(dev):
         assert ms > 0
         err = _relerr(_run(p, x, fidx, dev, dtype), ref)
         assert np.all(err <= tol), err
+
+
+def test_fused_step_multi_chunk_and_single_plane(dev):
+    """The fused y / z / inverse-y step over more right-hand sides than one
+    launch chunk holds (85 three-component RHS per chunk), checked per RHS
+    against single-RHS products and a few against the oracle; and a grid with
+    one occupied plane."""
+    mask = wl.random_mask(51, 18, 11, 5, fill=0.5)
+    dx = 0.25e-6
+    p = _problem(mask, dx)
+    p.set_zstep("fused")
+    n = 100
+    x = wl.random_currents(52, (n, 3, p.K))
+    fidx = [r % 2 for r in range(n)]
+    y = _run(p, x, fidx, dev, torch.complex128)
+    for r in (0, 85, 99):
+        assert np.array_equal(_run(p, x[r:r + 1], [fidx[r]], dev, torch.complex128)[0], y[r])
+    ref = _oracle(mask, dx, x[[3, 90]], [fidx[3], fidx[90]])
+    assert np.all(_relerr(y[[3, 90]], ref) <= 1e-12)
+    flat = wl.random_mask(53, 21, 14, 1, fill=0.7)
+    q = _problem(flat, dx)
+    q.set_zstep("fused")
+    xf = wl.random_currents(54, (2, 3, q.K))
+    reff = _oracle(flat, dx, xf, [0, -1])
+    assert np.all(_relerr(_run(q, xf, [0, -1], dev, torch.complex128), reff) <= 1e-12)
+    assert np.all(_relerr(_run(q, xf, [0, -1], dev, torch.complex64), reff) <= 1e-5)
