@@ -23,12 +23,55 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# device kernel of each timed step on the stack workload, FP32
+KERNEL_NAMES_FP32 = {
+    "pass_x": "svh::k_pass_x<float, svh::PlanC<8, 8, 8, 1> >",
+    "pass_y": "svh::k_pass_y<float, -1, svh::PlanC<8, 8, 8, 1> >",
+    "pass_z_mul": "svh::k_zdirect<float, 24, 8, 4>",
+    "pass_yi": "svh::k_pass_y<float, 1, svh::PlanC<8, 8, 8, 1> >",
+    "pass_xi": "svh::k_pass_xi<float, svh::PlanC<8, 8, 8, 1> >",
+}
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    """sha256 of the library's kernel sources (csrc/*, sorted by name)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2105_08627_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_name):
+    """HBM bytes per launch of `kernel_name` from the committed counter summary
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the factors a
+    plain device copy of known size gives), or None when the summary was taken
+    from other kernel sources than the ones built now."""
+    path = os.path.join(ROOT, "profiles", "counters_c5_stack.txt")
+    if not os.path.exists(path):
+        return None
+    rows, meta = {}, {}
+    with open(path) as f:
+        for line in f:
+            parts = line.split("\t")
+            if len(parts) == 2:
+                meta[parts[0].strip()] = parts[1].strip()
+            elif len(parts) == 3 and parts[0] != "kernel":
+                rows[parts[0].strip()] = (float(parts[1]), float(parts[2]))
+    if meta.get("source_sha256") != kernel_source_hash() or kernel_name not in rows:
+        return None
+    fk, wk = rows[kernel_name]
+    return 1024.0 * (fk * float(meta["fetch_factor"]) + wk * float(meta["write_factor"]))
 
 
 def pass_bytes(p, nvec, cs, ts, K, nzp):
@@ -312,7 +355,7 @@ def main():
                                 "fp64_Kt": mv64 * mask.size},
         "kernels_ms_per_step": per_call,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(KERNEL_NAMES_FP32.get(dom)),
                      "all_passes_frac": total_bytes / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "tucker_restore": {"ms": tk_ms, "tflops": tflops / (tk_ms * 1e-3) / 1e12 if tk_ms > 0 else None,
                            "mfma_frac": (tflops / (tk_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS) if tk_ms > 0 else None},

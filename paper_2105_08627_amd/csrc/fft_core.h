@@ -233,6 +233,17 @@ __device__ __forceinline__ void fin0(int R, int L, int j0, int TP, C (&v)[12], c
   }
 }
 
+// First item of a block in the persistent loops.  Blocks are dispatched to
+// the 8 XCDs round-robin (block b on XCD b mod 8), each XCD with its own L2;
+// when the grid is a multiple of 8, block b starts at item
+// (b mod 8) * (grid / 8) + b / 8, so that consecutive items (neighbouring
+// column tiles, which share DRAM pages) run on the same XCD.  Each later round
+// adds the grid size, so every item is still taken exactly once.
+__device__ __forceinline__ int first_item() {
+  const int g = gridDim.x, b = blockIdx.x;
+  return (g & 7) ? b : (b & 7) * (g >> 3) + (b >> 3);
+}
+
 // Persistent loop over items (groups of pencils): item i's first-stage loads
 // are issued while item i-1 runs its LDS stages and stores.
 template <typename C, int DIR, bool STRIDED, class MkIn, class MkOut>
@@ -240,7 +251,7 @@ __device__ __forceinline__ void fft_items(const FftPlan& pl, int j0, int nitems,
                                           const MkOut& mk_out, const Lds<C, STRIDED>& lds, const C* tw) {
   const int L = pl.L, TP = pl.tp;
   C v[12];
-  int item = blockIdx.x;
+  int item = first_item();
   if (item < nitems) load0(pl.r[0], L, j0, TP, mk_in(item), v);
   for (; item < nitems; item += gridDim.x) {
     const int next = item + gridDim.x;
@@ -289,7 +300,7 @@ __device__ __forceinline__ void fft_items_c(int j0, int nitems, const MkIn& mk_i
   constexpr int L = P::L, TP = P::tp;
   constexpr int R0 = P::r(0);
   C v[12];
-  int item = blockIdx.x;
+  int item = first_item();
   if (item < nitems) load0_r<C, R0>(L, j0, TP, mk_in(item), v);
   for (; item < nitems; item += gridDim.x) {
     const int next = item + gridDim.x;

@@ -208,7 +208,8 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_z(FftPlan pl, FftPlan
   const int t = threadIdx.x;
   const int w = t % W, j0 = t / W;
   const int ntile = (Lx + W - 1) / W;
-  const int tile = blockIdx.x % ntile, ky = blockIdx.x / ntile;
+  const int bid = first_item();  // XCD-aware order of the (tile, ky) blocks
+  const int tile = bid % ntile, ky = bid / ntile;
   const int kx = tile * W + w;
   const bool valid = kx < Lx;
   const int kxc = valid ? kx : 0;
@@ -288,7 +289,8 @@ __global__ void __launch_bounds__(256) k_zdirect(Geo geo, int Lx, int Ly, int nz
   int* zl = reinterpret_cast<int*>(xs + (size_t)V * NZ * W); // [NZ]
   const int t = threadIdx.x;
   const int ntile = (Lx + W - 1) / W;
-  const int tile = blockIdx.x % ntile, ky = blockIdx.x / ntile;
+  const int bid = first_item();  // XCD-aware order of the (tile, ky) blocks
+  const int tile = bid % ntile, ky = bid / ntile;
   const int kx0 = tile * W;
   for (int i = t; i < NZ; i += 256) zl[i] = i < nzp ? zlist[i] : 0;
   __syncthreads();
@@ -388,7 +390,8 @@ __global__ void __launch_bounds__(256) k_zdirect5(Geo geo, int Lx, int Ly, int n
   T* gs = reinterpret_cast<T*>(xs + (size_t)5 * NZ * W);   // [7][nd][W]
   const int t = threadIdx.x;
   const int ntile = (Lx + W - 1) / W;
-  const int tile = blockIdx.x % ntile, ky = blockIdx.x / ntile;
+  const int bid = first_item();  // XCD-aware order of the (tile, ky) blocks
+  const int tile = bid % ntile, ky = bid / ntile;
   const int kx0 = tile * W;
   const int w = t % W, rg = t / W;
   const bool valid = kx0 + w < Lx;
