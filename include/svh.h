@@ -148,11 +148,13 @@ svh_status svh_matvec(svh_problem* p, svh_prec prec, int nrhs,
                       void* ws_dev, size_t ws_bytes, void* stream);
 
 /* Autotuner: times the launch shapes of the FFT passes (persistent grids of
- * 1, 2 or 4 resident waves of blocks, or one block per pencil group) on this
- * exact batch (same arguments as svh_matvec), keeps the fastest shape per
- * pass for later svh_matvec calls in precision prec, and synchronises the
- * stream.  y_dev is overwritten.  ms_out (may be NULL): kernel time of one
- * tuned matvec in milliseconds. */
+ * 1, 2 or 4 resident waves of blocks, or one block per pencil group; full or
+ * half column tiles for the y passes) on this exact batch (same arguments as
+ * svh_matvec), keeps the fastest shape per pass for later svh_matvec calls in
+ * precision prec, in SVH_ZSTEP_AUTO mode also times the fused step against the
+ * separate passes and keeps the faster, and synchronises the stream.  y_dev
+ * is overwritten.  ms_out (may be NULL): kernel time of one tuned matvec in
+ * milliseconds. */
 svh_status svh_autotune(svh_problem* p, svh_prec prec, int nrhs, const int32_t* freq_idx_host,
                         const void* x_dev, void* y_dev, void* ws_dev, size_t ws_bytes, void* stream,
                         double* ms_out);

@@ -708,8 +708,11 @@ svh_status svh_autotune(svh_problem* p, svh_prec prec, int nrhs, const int32_t* 
   double best_ms[4] = {1e30, 1e30, 1e30, 1e30};
   svh_status st = SVH_OK;
   p->prof = true;
-  for (int c = 0; c < 4 && st == SVH_OK; ++c) {
-    for (int i = 0; i < 4; ++i) p->tune[prec].grid_mult[i] = kTuneCandidates[c];
+  // candidates: persistent grid multiplier x column width of the y passes
+  for (int c = 0; c < 8 && st == SVH_OK; ++c) {
+    const int mult = kTuneCandidates[c % 4], shift = c / 4;
+    for (int i = 0; i < 4; ++i) p->tune[prec].grid_mult[i] = mult;
+    p->tune[prec].ycols_shift[0] = p->tune[prec].ycols_shift[1] = shift;
     st = svh_matvec(p, prec, nrhs, freq_idx, x, y, ws, ws_bytes, stream);  // warm-up
     double ms[SVH_NPROF];
     int n = 0;
@@ -722,7 +725,9 @@ svh_status svh_autotune(svh_problem* p, svh_prec prec, int nrhs, const int32_t* 
       const double t = ms[1 + (i == 0 ? 0 : i == 1 ? 1 : i == 2 ? 3 : 4)];  // X, Y, Yi, Xi slots
       if (t < best_ms[i]) {
         best_ms[i] = t;
-        best.grid_mult[i] = kTuneCandidates[c];
+        best.grid_mult[i] = mult;
+        if (i == 1) best.ycols_shift[0] = shift;
+        if (i == 2) best.ycols_shift[1] = shift;
       }
     }
   }

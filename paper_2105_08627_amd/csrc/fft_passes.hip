@@ -626,7 +626,7 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     using P = decltype(tag);
     const FftPlan& pl = p->plan[1];
     const int tp = P::tpof(pl);
-    const int W = cols_per_block(tp, Ly, sizeof(C));
+    const int W = std::max(1, cols_per_block(tp, Ly, sizeof(C)) >> tn.ycols_shift[0]);
     const int nitems = ((Lx + W - 1) / W) * nzp * nvec;
     const size_t sh = (size_t)W * Ly * sizeof(C);
     const int g = persistent_grid((const void*)k_pass_y<T, -1, P>, W * tp, sh, nitems, p->ncu, tn.grid_mult[1]);
@@ -704,7 +704,7 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     using P = decltype(tag);
     const FftPlan& pl = p->plan[1];
     const int tp = P::tpof(pl);
-    const int W = cols_per_block(tp, Ly, sizeof(C));
+    const int W = std::max(1, cols_per_block(tp, Ly, sizeof(C)) >> tn.ycols_shift[1]);
     const int nitems = ((Lx + W - 1) / W) * nzp * nvec;
     const size_t sh = (size_t)W * Ly * sizeof(C);
     const int g = persistent_grid((const void*)k_pass_y<T, +1, P>, W * tp, sh, nitems, p->ncu, tn.grid_mult[2]);

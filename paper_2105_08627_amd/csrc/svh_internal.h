@@ -76,6 +76,7 @@ struct GeoT {
 constexpr int kTuneCandidates[4] = {1, 2, 4, 0};
 struct Tune {
   int grid_mult[4] = {1, 1, 1, 1};
+  int ycols_shift[2] = {0, 0};  // Y, Yi: columns per block = widest >> shift
 };
 
 }  // namespace svh
