@@ -191,6 +191,47 @@ def bench_basis5(args, cfg, mask, fidx, dev):
                             "hbm_gbs": by["pass_z_mul"] / (zms * 1e-3) / 1e9}}
 
 
+def bench_table2(args):
+    """Table II (Sec. III.B.3) on synthetic cubes of edge n voxels (dx = 1 um):
+    the seven unit-voxel tables computed directly (device quadrature) against
+    restored from an Algorithm 2 store (Tucker tol 1e-8, built once for the
+    largest cube, as at installation), with their memory."""
+    import tempfile
+    import torch
+    import paper_2105_08627_amd as svh
+    sizes = [int(v) for v in args.table2.split(",")]
+    big = max(sizes)
+    path = os.path.join(tempfile.mkdtemp(), "store.svh")
+    t = time.perf_counter()
+    err = svh.toeplitz_store_build((big, big, big), 7, 1e-8, path)
+    t_build = time.perf_counter() - t
+    log(f"[bench] table2 store {big}^3 built in {t_build:.1f}s, {os.path.getsize(path) / 2**20:.2f} MB")
+    rows = []
+    for n in sizes:
+        buf = torch.empty(7 * n ** 3, dtype=torch.float64, device="cuda")
+        ref = torch.empty_like(buf)
+        svh.green_tables((n, n, n), 7, ref)  # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        svh.green_tables((n, n, n), 7, ref)
+        torch.cuda.synchronize()
+        t_direct = time.perf_counter() - t
+        svh.toeplitz_store_restore(path, (n, n, n), 7, buf)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        svh.toeplitz_store_restore(path, (n, n, n), 7, buf)
+        torch.cuda.synchronize()
+        t_restore = time.perf_counter() - t
+        rel = (torch.linalg.vector_norm(buf - ref) / torch.linalg.vector_norm(ref)).item()
+        row = {"edge_voxels": n, "tables_MB": 7 * n ** 3 * 8 / 2 ** 20, "store_MB": os.path.getsize(path) / 2 ** 20,
+               "direct_s": t_direct, "restore_s": t_restore, "restore_relerr": rel}
+        log(f"[bench] table2 {row}")
+        rows.append(row)
+        del buf, ref
+    os.remove(path)
+    return {"store_domain": big, "store_build_s": t_build, "store_relerr_bound": err, "rows": rows}
+
+
 def bench_solve(args):
     """Port solve (eq. 7) of 16 coupled strips (256 x 128 x 4 grid, 16 ports),
     plain FP64 vs FP32 products inside FP64 refinement, both to relative
@@ -236,6 +277,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-basis5", action="store_true")
+    ap.add_argument("--table2", default="",
+                    help="comma-separated cube edges (voxels) for the Toeplitz-store experiment, e.g. 100,200")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -267,8 +310,11 @@ def main():
     p = svh.Problem(mask, dx)
     p.set_material(freqs, sigma0, lam)
     p.setup_tensors()
+    t_setup = time.perf_counter() - t
+    t = time.perf_counter()
     ranks, terr = p.tucker_compress(args.tol)
-    log(f"[bench] setup {time.perf_counter() - t:.1f}s  L={p.L} tucker ranks {ranks} bound {terr:.2e}")
+    t_tucker = time.perf_counter() - t
+    log(f"[bench] setup {t_setup:.1f}s tucker {t_tucker:.1f}s  L={p.L} tucker ranks {ranks} bound {terr:.2e}")
     K = p.K
     nzp = int(np.count_nonzero(mask.reshape(mask.shape[0], -1).any(axis=1)))
     x64_h = wl.random_currents(cfg["seed"], (nrhs, 3, K))
@@ -349,6 +395,7 @@ def main():
                                f"K={K} voxels, 3 components, {nrhs} RHS (8 ports x {nf} frequencies), "
                                f"Tucker tol {args.tol:g}",
                    "fft_grid": list(p.L), "tucker_ranks": list(ranks), "occupied_z_planes": nzp},
+        "setup_s": {"green_tables_and_spectrum": t_setup, "tucker_compress": t_tucker},
         "fp64": {"value": mv64, "unit": "matvecs/s", "ms_per_step": dt64 * 1e3 / args.fp64_steps},
         "rel_err_fp32_vs_fp64": rel,
         "voxel_matvecs_per_s": {"fp32_Kt": mv32 * mask.size, "fp32_K": mv32 * K,
@@ -364,6 +411,8 @@ def main():
         out["basis5"] = bench_basis5(args, cfg, mask, fidx, dev)
     if not args.no_solve:
         out["solve"] = bench_solve(args)
+    if args.table2:
+        out["table2"] = bench_table2(args)
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(mask, dx, x64_h, fidx, freqs, sigma0, lam)

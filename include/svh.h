@@ -86,12 +86,62 @@ svh_status svh_set_material(svh_problem* p, int nfreq, const double* f_hz_host,
                             int per_voxel);
 
 /* Toeplitz tensor of the unit-voxel Green integral (eq. 19 with the App. B
- * scaling, positive sign) for offsets [0,Kx) x [0,Ky) x [0,Kz), its circulant
- * embedding (Sec. II.A) and the real spectrum of that circulant (the tensor
- * Z of eq. 9 divided by j*w*mu0*dx), kept on the device in FP64.
+ * scaling, positive sign) for offsets [0,Kx) x [0,Ky) x [0,Kz) (with basis 5
+ * also the M1/M2 families of eqs. 20-21), its circulant embedding (Sec. II.A)
+ * and the spectrum of that circulant (the tensor Z of eq. 9 divided by
+ * j*w*mu0*dx), or its z-space form, kept on the device in FP64.  The integrals
+ * come from the method chosen with svh_set_green_method.
  * stream: a hipStream_t (NULL = default stream); the call returns after the
  * spectrum is complete. */
 svh_status svh_setup_tensors(svh_problem* p, void* stream);
+
+/* How svh_setup_tensors evaluates the voxel-pair integrals:
+ *  SVH_GREEN_QUADRATURE  (default) all families on the device: tensor
+ *                        Gauss-Legendre on the 8 polynomial boxes of the
+ *                        overlap-weighted 3D form, point counts by distance
+ *                        to the singular point; the 8 offsets whose boxes
+ *                        touch it by Duffy pyramids on the host;
+ *  SVH_GREEN_CLOSED_FORM M0 from the closed-form Coulomb box-box potential in
+ *                        binary128 on the host (svh_green_toeplitz); the M1/M2
+ *                        families still by quadrature.
+ * The two agree to about 1e-15 of M0(0); the closed form is slower (seconds
+ * for 8 M offsets on the host). */
+#define SVH_GREEN_QUADRATURE 0
+#define SVH_GREEN_CLOSED_FORM 1
+svh_status svh_set_green_method(svh_problem* p, int method);
+
+/* Toeplitz store (Algorithm 2, Sec. II.B.1).  Installation step: computes the
+ * first nfam (1: M0; 7: all families of the linear basis) unit-voxel tables
+ * for offsets [0,Kx) x [0,Ky) x [0,Kz) on the current device (quadrature),
+ * Tucker-compresses each (Algorithm 1 on the Toeplitz tensor itself, relative
+ * Frobenius tolerance tol), and writes the cores and factors to the file
+ * `path` (overwritten).  relerr_out (may be NULL): largest bound-level error
+ * estimate of the families.  Uses the device; returns when the file is
+ * written. */
+svh_status svh_toeplitz_store_build(int Kx, int Ky, int Kz, int nfam, double tol, const char* path,
+                                    void* stream, double* relerr_out);
+
+/* Algorithm 2, execution step on its own: restore the first nfam tables for
+ * offsets [0,Kx) x [0,Ky) x [0,Kz) from the store file into T_dev (nfam*Kt
+ * doubles, [f][z][y][x], device memory the caller owns).  EINVAL if the file
+ * is unreadable, covers a smaller domain or holds fewer families.  Returns
+ * when the tables are complete. */
+svh_status svh_toeplitz_store_restore(const char* path, int Kx, int Ky, int Kz, int nfam, double* T_dev,
+                                      void* stream);
+
+/* The first nfam (1 or 7) unit-voxel tables computed directly (device
+ * quadrature, as in svh_setup_tensors) into T_dev (nfam*Kt doubles, device).
+ * Returns when they are complete. */
+svh_status svh_green_tables(int Kx, int Ky, int Kz, int nfam, double* T_dev, void* stream);
+
+/* Use the store file `path` in later svh_setup_tensors calls of p: the tables
+ * of p's grid are restored from the factors' leading rows (the trim of
+ * Algorithm 2) on the device instead of being computed.  The stored domain
+ * must cover the grid, and basis 5 needs a seven-family store (EINVAL
+ * otherwise).  The factors are read now and kept in host memory; path = NULL
+ * stops using a store.  (The (dx)^5 scale of Algorithm 2 is part of the
+ * coupling j*w*mu0*dx applied per frequency.) */
+svh_status svh_set_toeplitz_store(svh_problem* p, const char* path);
 
 /* Host-only: the unit-voxel Green integral of eq. 19 (positive sign, App. B
  * with dx = 1) for offsets [0,Kx) x [0,Ky) x [0,Kz), written to T_host

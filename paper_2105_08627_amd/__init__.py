@@ -21,7 +21,8 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: 
 
 EXPORTED = [
     "svh_create", "svh_get_sizes", "svh_set_material", "svh_setup_tensors", "svh_green_toeplitz",
-    "svh_get_toeplitz", "svh_get_family", "svh_tucker_compress", "svh_workspace_bytes", "svh_matvec",
+    "svh_get_toeplitz", "svh_get_family", "svh_set_green_method", "svh_toeplitz_store_build",
+    "svh_set_toeplitz_store", "svh_toeplitz_store_restore", "svh_green_tables", "svh_tucker_compress", "svh_workspace_bytes", "svh_matvec",
     "svh_set_zstep", "svh_autotune", "svh_set_ports", "svh_solve_sizes", "svh_solve_workspace_bytes", "svh_solve", "svh_set_graphs", "svh_matvec_adjoint", "svh_port_gradient", "svh_gradient_contract", "svh_profile_enable", "svh_profile_read", "svh_last_error", "svh_destroy",
 ]
 PROF_NAMES = ["tucker_restore", "pass_x", "pass_y", "pass_z_mul", "pass_yi", "pass_xi"]
@@ -59,6 +60,11 @@ def lib():
     L.svh_green_toeplitz.argtypes = [i32, i32, i32, vp]
     L.svh_get_toeplitz.argtypes = [vp, vp]
     L.svh_get_family.argtypes = [vp, i32, vp]
+    L.svh_set_green_method.argtypes = [vp, i32]
+    L.svh_toeplitz_store_build.argtypes = [i32, i32, i32, i32, dbl, ctypes.c_char_p, vp, vp]
+    L.svh_set_toeplitz_store.argtypes = [vp, ctypes.c_char_p]
+    L.svh_toeplitz_store_restore.argtypes = [ctypes.c_char_p, i32, i32, i32, i32, vp, vp]
+    L.svh_green_tables.argtypes = [i32, i32, i32, i32, vp, vp]
     L.svh_tucker_compress.argtypes = [vp, dbl, vp, vp]
     L.svh_workspace_bytes.argtypes = [vp, i32, i32]
     L.svh_workspace_bytes.restype = sz
@@ -100,6 +106,37 @@ def green_toeplitz(Kx, Ky, Kz):
     return T
 
 
+def toeplitz_store_build(K, nfam, tol, path, stream=None):
+    """Algorithm 2, installation: Tucker-compressed unit-voxel tables of a
+    K = (Kx, Ky, Kz) domain (nfam = 1 or 7 families) written to `path`.
+    Returns the largest relative error bound of the families."""
+    err = np.zeros(1)
+    st = lib().svh_toeplitz_store_build(int(K[0]), int(K[1]), int(K[2]), int(nfam), float(tol),
+                                        os.fsencode(path), _stream_handle(stream), _ptr(err))
+    if st != 0:
+        raise SvhError(f"svh_toeplitz_store_build: {_STATUS.get(st, st)}")
+    return float(err[0])
+
+
+def toeplitz_store_restore(path, K, nfam, out, stream=None):
+    """Algorithm 2, execution: the first nfam tables for a K grid restored from
+    the store into the device tensor `out` (float64, nfam * Kx * Ky * Kz)."""
+    st = lib().svh_toeplitz_store_restore(os.fsencode(path), int(K[0]), int(K[1]), int(K[2]), int(nfam),
+                                          ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+    if st != 0:
+        raise SvhError(f"svh_toeplitz_store_restore: {_STATUS.get(st, st)}")
+    return out
+
+
+def green_tables(K, nfam, out, stream=None):
+    """The first nfam unit-voxel tables computed on the device into `out`."""
+    st = lib().svh_green_tables(int(K[0]), int(K[1]), int(K[2]), int(nfam), ctypes.c_void_p(out.data_ptr()),
+                                _stream_handle(stream))
+    if st != 0:
+        raise SvhError(f"svh_green_tables: {_STATUS.get(st, st)}")
+    return out
+
+
 def _stream_handle(stream=None):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -136,6 +173,17 @@ class Problem:
         la = np.ascontiguousarray(np.atleast_1d(np.asarray(lam, dtype=np.float64)))
         self._check(lib().svh_set_material(self._h, f.size, _ptr(f), _ptr(s0), _ptr(la), int(per_voxel)),
                     "svh_set_material")
+
+    def set_toeplitz_store(self, path):
+        """Restore the tables from an Algorithm 2 store in later setup_tensors calls
+        (None: compute them)."""
+        self._check(lib().svh_set_toeplitz_store(self._h, None if path is None else os.fsencode(path)),
+                    "svh_set_toeplitz_store")
+
+    def set_green_method(self, method):
+        """'quadrature' (device, default) or 'closed_form' (host binary128 M0)."""
+        m = {"quadrature": 0, "closed_form": 1}[method]
+        self._check(lib().svh_set_green_method(self._h, m), "svh_set_green_method")
 
     def setup_tensors(self, stream=None):
         self._check(lib().svh_setup_tensors(self._h, _stream_handle(stream)), "svh_setup_tensors")

@@ -299,13 +299,15 @@ svh_status setup_tensors5(svh_problem* p, hipStream_t s) {
   const size_t gsz = (size_t)kNFam * nd * p->L[1] * p->L[0];
   double *dF = nullptr, *dR = nullptr, *dT = nullptr;
   HIPCHK(hipMalloc(&dF, kNFam * Kt * sizeof(double)));
-  hipError_t e = family_tables(p->K, dF, s);
+  hipError_t e = p->store.empty() ? family_tables(p->K, kNFam, dF, s) : store_tables(p, kNFam, dF, s);
   p->Tf.assign(kNFam * Kt, 0.0);
   if (e == hipSuccess) e = hipMemcpy(p->Tf.data(), dF, kNFam * Kt * sizeof(double), hipMemcpyDeviceToHost);
   hipFree(dF);
   HIPCHK(e);
-  // M0 from its closed form; exact zeros where an odd family vanishes
-  std::copy(p->T.begin(), p->T.end(), p->Tf.begin());
+  // M0 from the closed form if chosen, else from the same quadrature; exact
+  // zeros where an odd family vanishes
+  if (p->green == SVH_GREEN_CLOSED_FORM && p->store.empty()) std::copy(p->T.begin(), p->T.end(), p->Tf.begin());
+  else std::copy(p->Tf.begin(), p->Tf.begin() + Kt, p->T.begin());
   for (int f = 1; f <= 3; ++f) {
     const int a = f - 1;
     for (int z = 0; z < p->K[2]; ++z)
@@ -341,7 +343,8 @@ svh_status svh_setup_tensors(svh_problem* p, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t Kt = (size_t)p->K[0] * p->K[1] * p->K[2];
   p->T.assign(Kt, 0.0);
-  green_toeplitz_m0(p->K[0], p->K[1], p->K[2], p->T.data());
+  const bool closed = p->green == SVH_GREEN_CLOSED_FORM && p->store.empty();
+  if (closed) green_toeplitz_m0(p->K[0], p->K[1], p->K[2], p->T.data());
   free_tucker(p);
   dfree(p->d_zhat64);
   dfree(p->d_zhat32);
@@ -367,7 +370,14 @@ svh_status svh_setup_tensors(svh_problem* p, void* stream) {
   HIPCHK(hipMalloc(&p->d_g32, n2 * sizeof(float)));
   HIPCHK(hipMalloc(&dT, Kt * sizeof(double)));
   hipError_t e = hipMalloc(&t1, n1 * sizeof(double));
-  if (e == hipSuccess) e = hipMemcpyAsync(dT, p->T.data(), Kt * sizeof(double), hipMemcpyHostToDevice, s);
+  if (closed) {
+    if (e == hipSuccess) e = hipMemcpyAsync(dT, p->T.data(), Kt * sizeof(double), hipMemcpyHostToDevice, s);
+  } else {
+    // the Toeplitz tensor on the device, restored from the store (Algorithm 2)
+    // or by quadrature; a host copy for the Tucker factorisation and the getters
+    if (e == hipSuccess) e = p->store.empty() ? family_tables(p->K, 1, dT, s) : store_tables(p, 1, dT, s);
+    if (e == hipSuccess) e = hipMemcpy(p->T.data(), dT, Kt * sizeof(double), hipMemcpyDeviceToHost);
+  }
   // the x and y axes of the spectrum give the z-space kernel; the z axis
   // then gives the full circulant spectrum
   if (e == hipSuccess) e = launch_even_spectrum(p, dT, p->d_zhat64, t1, p->d_g64, s);
@@ -384,6 +394,14 @@ svh_status svh_setup_tensors(svh_problem* p, void* stream) {
   hipFree(dT);
   if (t1) hipFree(t1);
   HIPCHK(e);
+  return SVH_OK;
+}
+
+svh_status svh_set_green_method(svh_problem* p, int method) {
+  if (!p) return SVH_EINVAL;
+  if (method != SVH_GREEN_QUADRATURE && method != SVH_GREEN_CLOSED_FORM)
+    return fail(p, SVH_EINVAL, "set_green_method: unknown method");
+  p->green = method;
   return SVH_OK;
 }
 

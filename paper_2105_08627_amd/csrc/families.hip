@@ -135,8 +135,8 @@ __host__ __device__ inline void family_far(const double d[3], const double* glx,
   for (int f = 0; f < kNFam; ++f) out[f] = acc[f] * inv4pi;
 }
 
-// out[f * Kt + idx] for offsets idx = (dz * Ky + dy) * Kx + dx with max |d| >= 2
-__global__ void k_family_quad(int Kx, int Ky, int Kz, double* __restrict__ out) {
+// out[f * Kt + idx], f < nfam, for offsets idx = (dz * Ky + dy) * Kx + dx with max |d| >= 2
+__global__ void k_family_quad(int Kx, int Ky, int Kz, int nfam, double* __restrict__ out) {
   const long long Kt = (long long)Kx * Ky * Kz;
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < Kt;
        idx += (long long)gridDim.x * blockDim.x) {
@@ -145,7 +145,7 @@ __global__ void k_family_quad(int Kx, int Ky, int Kz, double* __restrict__ out) 
     const double d[3] = {(double)dx, (double)dy, (double)dz};
     double v[kNFam];
     family_far(d, c_glx, c_glw, v);
-    for (int f = 0; f < kNFam; ++f) out[f * Kt + idx] = v[f];
+    for (int f = 0; f < nfam; ++f) out[f * Kt + idx] = v[f];
   }
 }
 
@@ -212,37 +212,36 @@ static void family_near(const int d[3], double out[kNFam]) {
   for (int f = 0; f < kNFam; ++f) out[f] = (double)(acc[f] / (4.0L * 3.141592653589793238462643383279502884L));
 }
 
-hipError_t family_tables(const int K[3], double* d_out, hipStream_t s) {
-  static bool init = false;
-  if (!init) {
-    double x[kGlTotal], w[kGlTotal];
-    for (int q = 0; q < kTiers; ++q) gauss_legendre01(kTierN[q], x + kTierOff[q], w + kTierOff[q]);
-    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_glx), x, sizeof(x));
-    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_glw), w, sizeof(w));
-    if (e != hipSuccess) return e;
-    init = true;
-  }
+hipError_t family_tables(const int K[3], int nfam, double* d_out, hipStream_t s) {
+  // Gauss-Legendre tiers into this device's constant memory (a few hundred bytes)
+  double x[kGlTotal], w[kGlTotal];
+  for (int q = 0; q < kTiers; ++q) gauss_legendre01(kTierN[q], x + kTierOff[q], w + kTierOff[q]);
+  hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_glx), x, sizeof(x), 0, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_glw), w, sizeof(w), 0, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // x, w live on this frame
+  if (e != hipSuccess) return e;
   const long long Kt = (long long)K[0] * K[1] * K[2];
   hipLaunchKernelGGL(k_family_quad, dim3((unsigned)std::min<long long>((Kt + 255) / 256, 65536)), dim3(256), 0, s,
-                     K[0], K[1], K[2], d_out);
-  hipError_t e = hipGetLastError();
+                     K[0], K[1], K[2], nfam, d_out);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   // near offsets on the host
+  std::vector<double> near;  // [f][8 offsets]
+  std::vector<long long> idx;
   for (int dz = 0; dz < 2 && dz < K[2]; ++dz)
     for (int dy = 0; dy < 2 && dy < K[1]; ++dy)
       for (int dx = 0; dx < 2 && dx < K[0]; ++dx) {
         const int d[3] = {dx, dy, dz};
         double v[kNFam];
         family_near(d, v);
-        const long long idx = ((long long)dz * K[1] + dy) * K[0] + dx;
-        for (int f = 0; f < kNFam; ++f) {
-          e = hipMemcpyAsync(d_out + f * Kt + idx, &v[f], sizeof(double), hipMemcpyHostToDevice, s);
-          if (e != hipSuccess) return e;
-          e = hipStreamSynchronize(s);  // v lives on this frame
-          if (e != hipSuccess) return e;
-        }
+        idx.push_back(((long long)dz * K[1] + dy) * K[0] + dx);
+        for (int f = 0; f < kNFam; ++f) near.push_back(v[f]);
       }
-  return hipStreamSynchronize(s);
+  for (size_t i = 0; i < idx.size() && e == hipSuccess; ++i)
+    for (int f = 0; f < nfam && e == hipSuccess; ++f)
+      e = hipMemcpyAsync(d_out + f * Kt + idx[i], &near[i * kNFam + f], sizeof(double), hipMemcpyHostToDevice, s);
+  hipError_t e2 = hipStreamSynchronize(s);  // near lives on this frame
+  return e != hipSuccess ? e : e2;
 }
 
 }  // namespace svh

@@ -36,6 +36,9 @@ void green_toeplitz_m0(int Kx, int Ky, int Kz, double* T);
 // Tucker-SVD (Algorithm 1) of the spectrum of the even circulant embedding of T.
 int tucker_even_circulant(const int K[3], const int L[3], const double* T, double tol,
                           TuckerFactors& out);
+// Tucker-SVD of the Toeplitz tensor itself (Algorithm 1; Algorithm 2's store):
+// factors F[i][k * d_i + c] for k < K[i].  Returns 0, or 1 for a zero tensor.
+int tucker_plain(const int K[3], const double* T, double tol, TuckerFactors& out);
 // Same for a tensor that is odd along the axes with odd[i] != 0 (sine factors).
 // Returns 0, or 1 for a zero tensor (rank-one zero factors).
 int tucker_circulant(const int K[3], const int L[3], const double* T, const int odd[3], double tol,

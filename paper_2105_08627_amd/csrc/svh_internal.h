@@ -131,7 +131,12 @@ struct svh_problem {
   bool auto_fused[2] = {false, false};  // AUTO mode: the autotuner timed FUSED faster
   double2* d_twp64 = nullptr;
   float2* d_twp32 = nullptr;
-  int zstep = 0;                // SVH_ZSTEP_AUTO / _FFT / _DIRECT
+  int zstep = 0;                // SVH_ZSTEP_AUTO / _FFT / _DIRECT / _FUSED
+  int green = 0;                // SVH_GREEN_QUADRATURE (device) / SVH_GREEN_CLOSED_FORM (host, M0)
+  // Toeplitz store (Algorithm 2): Tucker factors of the tables on a large
+  // unit-voxel domain, read by svh_set_toeplitz_store; empty = not used
+  int store_K[3] = {0, 0, 0};
+  std::vector<svh::TuckerFactors> store;
   svh::Tune tune[2];            // per precision (SVH_FP64, SVH_FP32)
   bool tucker = false;
   svh::DevTucker tk;
@@ -170,15 +175,21 @@ hipError_t launch_tucker_rebuild(const svh_problem* p, bool fp32_out, bool zspac
 hipError_t launch_tucker_rebuild_rows(const svh_problem* p, const DevTucker& t, const double* Fz3, int M3,
                                       bool fp32_out, void* d_out, double* d_V, double* d_W, hipStream_t s,
                                       bool xy_transposed = false);
+// Restoration of a Tucker tensor on an n1 x n2 x n3 box (the factors' first
+// n_i rows): out[k3][k2][k1]; scratch V (n1 d2 d3) and W (n1 n2 d3) doubles.
+hipError_t launch_tucker_box(int n1, int n2, int n3, const DevTucker& t, const double* F3, bool fp32_out,
+                             void* d_out, double* d_V, double* d_W, hipStream_t s);
 // out[q][kx][ky] = in[dz_q][ky][kx] (z-space kernel rows of the fused path)
 hipError_t launch_gather_transposed(const svh_problem* p, const double* d_in, double* d_out, hipStream_t s);
 GeoT make_geo_t(const svh_problem* p, size_t csize);
 int fused_phases(const svh_problem* p, size_t cs, size_t ts);
 bool fused_eligible(const svh_problem* p);
 bool use_fused(const svh_problem* p, svh_prec prec);
-// Seven family tables [f][Kz][Ky][Kx] on the device (quadrature; f = 0 is
-// recomputed by the caller from the closed form).
-hipError_t family_tables(const int K[3], double* d_out, hipStream_t s);
+// The first nfam (1 or 7) family tables [f][Kz][Ky][Kx] on the device by
+// quadrature (M0, M1x, M1y, M1z, M2x, M2y, M2z).
+hipError_t family_tables(const int K[3], int nfam, double* d_out, hipStream_t s);
+// The first nfam tables for the problem's grid from the Toeplitz store (device).
+hipError_t store_tables(const svh_problem* p, int nfam, double* d_out, hipStream_t s);
 // z-space kernels of the seven families at the plane offsets dzset:
 // rows [f][q][Ky][Kx] (device) -> out [f][q][Ly][Lx].
 hipError_t launch_zspace_families(const svh_problem* p, const double* d_rows, int nd, double* d_out,

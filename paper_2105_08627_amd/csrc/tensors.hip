@@ -145,6 +145,19 @@ size_t tucker_scratch_doubles5(const svh_problem* p) {
   return m;
 }
 
+hipError_t launch_tucker_box(int n1, int n2, int n3, const DevTucker& t, const double* F3, bool fp32_out,
+                             void* d_out, double* d_V, double* d_W, hipStream_t s) {
+  // out[k3][k2][k1] = sum core[c][b][a] F1[k1][a] F2[k2][b] F3[k3][c], k_i < n_i
+  const int d1 = t.d[0], d2 = t.d[1], d3 = t.d[2];
+  hipError_t e;
+  GemmArgs g1{n1, d2 * d3, d1, t.F[0], d1, 1, 0, t.core, 1, d1, 0, d_V, (long long)d2 * d3, 1, 0};
+  if ((e = gemm(g1, 1, false, s)) != hipSuccess) return e;
+  GemmArgs g2{n2, d3, d2, t.F[1], d2, 1, 0, d_V, 1, d2, (long long)d2 * d3, d_W, (long long)n1 * d3, 1, d3};
+  if ((e = gemm(g2, n1, false, s)) != hipSuccess) return e;
+  GemmArgs g3{n3, n1 * n2, d3, F3, d3, 1, 0, d_W, 1, d3, 0, d_out, (long long)n1 * n2, 1, 0};
+  return gemm(g3, 1, fp32_out, s);
+}
+
 hipError_t launch_tucker_rebuild_rows(const svh_problem* p, const DevTucker& t, const double* Fz3, int M3,
                                       bool fp32_out, void* d_out, double* d_V, double* d_W, hipStream_t s,
                                       bool xy_transposed) {

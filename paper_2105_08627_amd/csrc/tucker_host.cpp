@@ -299,6 +299,71 @@ int tucker_circulant(const int K[3], const int L[3], const double* T, const int 
   return 0;
 }
 
+// Tucker-SVD (Algorithm 1) of T itself: F[i] = leading left singular vectors
+// of the mode-i unfolding (K_i x d_i, [k][c]), core = T x1 F1^T x2 F2^T x3 F3^T.
+int tucker_plain(const int K[3], const double* T, double tol, TuckerFactors& out) {
+  const size_t n = (size_t)K[0] * K[1] * K[2];
+  std::vector<double> X(T, T + n);
+  double nrm2 = 0;
+  for (size_t i = 0; i < n; ++i) nrm2 += X[i] * X[i];
+  const double nrm = std::sqrt(nrm2);
+  if (!(nrm > 0)) {
+    for (int m = 0; m < 3; ++m) {
+      out.d[m] = 1;
+      out.F[m].assign((size_t)K[m], 0.0);
+    }
+    out.core.assign(1, 0.0);
+    out.relerr = 0;
+    return 1;
+  }
+  const double thr = tol / std::sqrt(3.0) * nrm;
+  double tails2 = 0;
+  for (int m = 0; m < 3; ++m) {
+    std::vector<double> sig, Ufull;
+    int r = 0;
+    mode_svd(X, K, m, Ufull, sig, r);
+    double tail = 0;
+    const int d = select_rank(sig, thr, tail);
+    tails2 += tail * tail;
+    out.d[m] = d;
+    out.F[m].resize((size_t)K[m] * d);
+    for (int j = 0; j < K[m]; ++j)
+      for (int c = 0; c < d; ++c) out.F[m][(size_t)j * d + c] = Ufull[(size_t)j * r + c];
+  }
+  out.relerr = std::sqrt(tails2) / nrm;
+  const int d1 = out.d[0], d2 = out.d[1], d3 = out.d[2];
+  const std::vector<double>&U0 = out.F[0], &U1 = out.F[1], &U2 = out.F[2];
+  std::vector<double> G1((size_t)K[2] * K[1] * d1, 0.0);
+#pragma omp parallel for collapse(2)
+  for (int k = 0; k < K[2]; ++k)
+    for (int j = 0; j < K[1]; ++j)
+      for (int a = 0; a < d1; ++a) {
+        double s = 0;
+        const double* t = &X[((size_t)k * K[1] + j) * K[0]];
+        for (int i = 0; i < K[0]; ++i) s += U0[(size_t)i * d1 + a] * t[i];
+        G1[((size_t)k * K[1] + j) * d1 + a] = s;
+      }
+  std::vector<double> G2((size_t)K[2] * d2 * d1, 0.0);
+#pragma omp parallel for collapse(2)
+  for (int k = 0; k < K[2]; ++k)
+    for (int b = 0; b < d2; ++b)
+      for (int a = 0; a < d1; ++a) {
+        double s = 0;
+        for (int j = 0; j < K[1]; ++j) s += U1[(size_t)j * d2 + b] * G1[((size_t)k * K[1] + j) * d1 + a];
+        G2[((size_t)k * d2 + b) * d1 + a] = s;
+      }
+  out.core.assign((size_t)d3 * d2 * d1, 0.0);
+#pragma omp parallel for collapse(2)
+  for (int c = 0; c < d3; ++c)
+    for (int b = 0; b < d2; ++b)
+      for (int a = 0; a < d1; ++a) {
+        double s = 0;
+        for (int k = 0; k < K[2]; ++k) s += U2[(size_t)k * d3 + c] * G2[((size_t)k * d2 + b) * d1 + a];
+        out.core[((size_t)c * d2 + b) * d1 + a] = s;
+      }
+  return 0;
+}
+
 int tucker_even_circulant(const int K[3], const int L[3], const double* T, double tol, TuckerFactors& out) {
   const int even[3] = {0, 0, 0};
   return tucker_circulant(K, L, T, even, tol, out);

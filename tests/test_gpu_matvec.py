@@ -216,3 +216,23 @@ def test_fused_step_multi_chunk_and_single_plane(dev):
     reff = _oracle(flat, dx, xf, [0, -1])
     assert np.all(_relerr(_run(q, xf, [0, -1], dev, torch.complex128), reff) <= 1e-12)
     assert np.all(_relerr(_run(q, xf, [0, -1], dev, torch.complex64), reff) <= 1e-5)
+
+
+def test_green_methods_agree(dev):
+    """Device quadrature (default) and the host binary128 closed form give the
+    same Toeplitz tensor to 2e-15 of M0(0), and the same operator to 1e-14."""
+    import paper_2105_08627_amd as svh
+    mask = wl.random_mask(61, 23, 17, 9, fill=0.5)
+    dx = 0.25e-6
+    pq = _problem(mask, dx)
+    pc = svh.Problem(mask, dx)
+    pc.set_green_method("closed_form")
+    pc.set_material(FREQS, SIGMA0, LAM)
+    pc.setup_tensors()
+    Tq, Tc = pq.toeplitz(), pc.toeplitz()
+    assert np.abs(Tq - Tc).max() <= 2e-15 * Tc[0, 0, 0]
+    assert np.array_equal(Tc, svh.green_toeplitz(23, 17, 9))
+    x = wl.random_currents(62, (2, 3, pq.K))
+    yq = _run(pq, x, [0, -1], dev, torch.complex128)
+    yc = _run(pc, x, [0, -1], dev, torch.complex128)
+    assert np.all(_relerr(yq, yc) <= 1e-14)
