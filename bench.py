@@ -232,6 +232,77 @@ def bench_table2(args):
     return {"store_domain": big, "store_build_s": t_build, "store_relerr_bound": err, "rows": rows}
 
 
+def bench_tucker_sweep(args):
+    """Figs. 2-3 (Sec. III.B.1) on synthetic cubes (3D) and 3-voxel plates
+    (2D-like), dx = 1 um: multilinear ranks of the circulant spectrum, the
+    compression ratio CR (dense circulant bytes / Tucker bytes) and the
+    overhead CO (restoration time / one convolution of one component with the
+    same tensor, both on the device, FP32 product) per Tucker tolerance."""
+    import torch
+    import paper_2105_08627_amd as svh
+    dev = torch.device("cuda:0")
+    rows = []
+    shapes = [(n, n, n) for n in (32, 64, 100, 128, 192, 256)] + [(n, n, 3) for n in (128, 256, 384, 512)]
+    for K in shapes:
+        mask = np.ones(K[::-1], dtype=np.uint8)
+        p = svh.Problem(mask, 1e-6)
+        p.set_material([1e9], 0.0, 90e-9)
+        p.setup_tensors()
+        x = torch.from_numpy(np.ones((1, 3, p.K), dtype=np.complex64)).to(dev)
+        Lt = p.L[0] * p.L[1] * p.L[2]
+        for tol in (1e-4, 1e-6, 1e-8):
+            ranks, err = p.tucker_compress(tol)
+            d1, d2, d3 = ranks
+            tucker_bytes = 8 * (d1 * d2 * d3 + p.L[0] * d1 + p.L[1] * d2 + p.L[2] * d3)
+            p.matvec(x, [-1])
+            torch.cuda.synchronize()
+            p.profile(True)
+            p.profile_read()
+            for _ in range(5):
+                p.matvec(x, [-1])
+            prof, n = p.profile_read()
+            p.profile(False)
+            conv = sum(v for k, v in prof.items() if k != "tucker_restore") / (3 * n)
+            rows.append({"shape": list(K), "Kt": int(np.prod(K)), "tol": tol, "ranks": list(ranks),
+                         "CR": Lt * 8 / tucker_bytes, "CO": prof["tucker_restore"] / n / conv,
+                         "tucker_MB": tucker_bytes / 2 ** 20, "dense_MB": Lt * 8 / 2 ** 20})
+            log(f"[bench] tucker sweep {rows[-1]}")
+        del p
+    return {"rows": rows}
+
+
+def bench_bend_study(args):
+    """Self-convergence of the 90-degree bend inductance (Sec. III.C geometry:
+    2 x 2 mm square section, 10 mm arms, lambda = 0.45 mm, sigma0 = 0) with the
+    piecewise-linear basis at dx = 0.5, 0.4, 0.25, 0.2, 0.1 mm; the finest
+    grid is the reference."""
+    import torch
+    import paper_2105_08627_amd as svh
+    import workloads as wl
+    f = 1e3
+    res = []
+    for dx_mm in (0.5, 0.4, 0.25, 0.2, 0.1):
+        mask, ports = wl.square_bend(int(round(2.0 / dx_mm)), int(round(10.0 / dx_mm)))
+        p = svh.Problem(mask, dx_mm * 1e-3, basis=5)
+        p.set_material([f], 0.0, 0.45e-3)
+        p.setup_tensors()
+        p.tucker_compress(1e-8)
+        p.set_ports(ports)
+        t = time.perf_counter()
+        X, Y, info = p.solve(0, rre=1e-8, restart=50, maxit=2000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        L = float((1.0 / Y[0, 0]).imag / (2 * np.pi * f))
+        res.append({"dx_mm": dx_mm, "K": p.K, "N": p.N, "L_nH": L * 1e9, "iterations": info["iterations"],
+                    "solve_s": dt, "relres": info["relres"]})
+        log(f"[bench] bend {res[-1]}")
+        del p
+    ref = res[-1]["L_nH"]
+    for r in res:
+        r["rel_diff_vs_finest"] = abs(r["L_nH"] - ref) / abs(ref)
+    return {"frequency_hz": f, "rows": res}
+
+
 def bench_solve(args):
     """Port solve (eq. 7) of 16 coupled strips (256 x 128 x 4 grid, 16 ports),
     plain FP64 vs FP32 products inside FP64 refinement, both to relative
@@ -277,6 +348,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-basis5", action="store_true")
+    ap.add_argument("--tucker-sweep", action="store_true", help="ranks, CR and CO vs domain size (Figs. 2-3)")
+    ap.add_argument("--bend-study", action="store_true", help="90-degree bend inductance vs voxel size")
     ap.add_argument("--table2", default="",
                     help="comma-separated cube edges (voxels) for the Toeplitz-store experiment, e.g. 100,200")
     ap.add_argument("--copy-probe", action="store_true",
@@ -413,6 +486,10 @@ def main():
         out["solve"] = bench_solve(args)
     if args.table2:
         out["table2"] = bench_table2(args)
+    if args.tucker_sweep:
+        out["tucker_sweep"] = bench_tucker_sweep(args)
+    if args.bend_study:
+        out["bend_study"] = bench_bend_study(args)
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(mask, dx, x64_h, fidx, freqs, sigma0, lam)

@@ -146,6 +146,22 @@ def strip_array(nstrip=16, length=256, width=4, thick=4, gap=4):
     return mask, ports
 
 
+def square_bend(width, arm):
+    """90-degree bend of square cross-section (width voxels) with arms of
+    `arm` voxels: one arm along x at y < width, one along y at x >= arm -
+    width.  One port: + on the -x end faces of the x arm, - on the +y end
+    faces of the y arm.  Returns (mask, ports) like strip_array."""
+    mask = np.zeros((width, arm, arm), dtype=np.uint8)
+    mask[:, 0:width, :] = 1
+    mask[:, :, arm - width:arm] = 1
+    zz, yy, xx = np.nonzero(mask)
+    order = np.lexsort((xx, yy, zz))
+    xx, yy = xx[order], yy[order]
+    plus = [(int(k), 0) for k in np.nonzero(xx == 0)[0]]
+    minus = [(int(k), 3) for k in np.nonzero(yy == arm - 1)[0]]
+    return mask, [(plus, minus)]
+
+
 # Workload table: grid, voxel size, material (sigma0 S/m, London depth m,
 # frequencies Hz), RHS count, and the mask generator.
 WORKLOADS = {
