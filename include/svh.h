@@ -267,6 +267,19 @@ svh_status svh_set_zstep(svh_problem* p, int mode);
 svh_status svh_set_ports(svh_problem* p, int nports, const int32_t* plus_ptr, const int32_t* plus_faces,
                          const int32_t* minus_ptr, const int32_t* minus_faces);
 
+/* Preconditioner of the conjugate-gradient solve of the Schur complement
+ * S = A_F Y^-1 A_F^T inside the preconditioner of eqs. 12-15:
+ *  SVH_SCHUR_JACOBI  diagonal of S;
+ *  SVH_SCHUR_AMG     (default) one symmetric V-cycle of an aggregation
+ *                    multigrid (pairwise aggregation, aggregates of up to four
+ *                    nodes, Galerkin coarse matrices, damped Jacobi smoothing,
+ *                    exact coarsest solve), built on the host at the first
+ *                    solve of a frequency.
+ * Both give the same solution to the solve tolerance. */
+#define SVH_SCHUR_JACOBI 0
+#define SVH_SCHUR_AMG 1
+svh_status svh_set_schur_precond(svh_problem* p, int kind);
+
 /* Unknowns per port column N = C K + M and node count M (after svh_set_ports). */
 svh_status svh_solve_sizes(const svh_problem* p, int* N, int* M);
 

@@ -30,6 +30,25 @@ struct Topology {
 int build_topology(const int K[3], const int32_t* vidx, int nvox, int basis, Topology& t);
 void ground_floating(const Topology& t, std::vector<char>& dirichlet);
 
+// Aggregation multigrid of the Schur complement (host setup).
+struct AmgLevel {
+  int n = 0;
+  std::vector<int> rptr, col;
+  std::vector<double> val;
+};
+constexpr int kAmgCoarse = 256;      // stop coarsening at this many nodes
+constexpr int kAmgCoarseMax = 1024;  // largest coarsest level inverted densely
+constexpr int kAmgMaxLevels = 24;
+AmgLevel schur_matrix(const Topology& t, const std::vector<char>& dirichlet, const std::vector<double>& ydiag);
+// levels[0] = fine; aggs[l][i] = aggregate (node of level l + 1) of node i of
+// level l, or -1 for a row without couplings (left out of level l + 1).  Returns how the coarsest level is solved: kAmgCoarseDense
+// (coarse_inv = its dense inverse), kAmgCoarseDiagonal (it is diagonal),
+// kAmgCoarseJacobi (kAmgCoarseSweeps damped Jacobi sweeps); -1 on failure.
+constexpr int kAmgCoarseDense = 0, kAmgCoarseDiagonal = 1, kAmgCoarseJacobi = 2;
+constexpr int kAmgCoarseSweeps = 8;
+int amg_setup(AmgLevel fine, std::vector<AmgLevel>& levels, std::vector<std::vector<int>>& aggs,
+              std::vector<double>& coarse_inv);
+
 // Unit-voxel Green integral T[dz][dy][dx] for offsets 0 <= d < K.
 void green_toeplitz_m0(int Kx, int Ky, int Kz, double* T);
 

@@ -16,6 +16,7 @@
 // currents (component-major, as for svh_matvec) then one potential per node.
 // Dirichlet (port and grounded) node entries are kept at zero.
 #include <algorithm>
+#include <numeric>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -224,6 +225,65 @@ __global__ void k_pcg_beta(int nrhs, double2* __restrict__ rho, const double2* _
 __global__ void k_pcg_dir(long long n, int M, const double* __restrict__ beta, const double2* __restrict__ z,
                           double2* __restrict__ p) {
   GRID_STRIDE(i, n) p[i] = zadd(z[i], zscale(p[i], beta[i / M]));
+}
+
+// ------------------------------------------------ multigrid V-cycle (S) --
+// Batched over right-hand sides: vectors [r][n] of complex values, level
+// matrices real CSR.  wdinv = w_i / a_ii with the Jacobi weight w_i = 0.7, or
+// 1 on rows without couplings (solved exactly); the coarse correction is
+// scaled by kAmgAlpha < 2 (plain aggregation under-corrects), which keeps the
+// cycle symmetric positive definite.
+constexpr double kAmgOmega = 0.7;
+constexpr double kAmgAlpha = 1.8;
+
+__global__ void k_amg_smooth0(int nrhs, int n, const double* __restrict__ wdinv, const double2* __restrict__ b,
+                              double2* __restrict__ x) {
+  GRID_STRIDE(i, (long long)n * nrhs) x[i] = zscale(b[i], wdinv[i % n]);
+}
+__global__ void k_amg_resid(int nrhs, int n, const int* __restrict__ rptr, const int* __restrict__ col,
+                            const double* __restrict__ val, const double2* __restrict__ b,
+                            const double2* __restrict__ x, double2* __restrict__ r) {
+  GRID_STRIDE(i, (long long)n * nrhs) {
+    const long long base = (i / n) * n;
+    const int row = (int)(i % n);
+    double2 acc = b[i];
+    for (int q = rptr[row]; q < rptr[row + 1]; ++q) acc = zsub(acc, zscale(x[base + col[q]], val[q]));
+    r[i] = acc;
+  }
+}
+__global__ void k_amg_jacobi(int nrhs, int n, const double* __restrict__ wdinv, const double2* __restrict__ r,
+                             double2* __restrict__ x) {
+  GRID_STRIDE(i, (long long)n * nrhs) x[i] = zadd(x[i], zscale(r[i], wdinv[i % n]));
+}
+// bc[I] = sum of r over the members of aggregate I
+__global__ void k_amg_restrict(int nrhs, int nf, int nc, const int* __restrict__ mptr, const int* __restrict__ mem,
+                               const double2* __restrict__ r, double2* __restrict__ bc) {
+  GRID_STRIDE(i, (long long)nc * nrhs) {
+    const long long rf = (i / nc) * nf;
+    const int I = (int)(i % nc);
+    double2 acc = make_double2(0, 0);
+    for (int k = mptr[I]; k < mptr[I + 1]; ++k) acc = zadd(acc, r[rf + mem[k]]);
+    bc[i] = acc;
+  }
+}
+// x += alpha P xc (rows left out of the coarse level have agg < 0)
+__global__ void k_amg_prolong(int nrhs, int nf, int nc, const int* __restrict__ agg, const double2* __restrict__ xc,
+                              double2* __restrict__ x) {
+  GRID_STRIDE(i, (long long)nf * nrhs) {
+    const int a = agg[i % nf];
+    if (a >= 0) x[i] = zadd(x[i], zscale(xc[(i / nf) * nc + a], kAmgAlpha));
+  }
+}
+// x = Cinv b on the coarsest level (dense, row-major)
+__global__ void k_amg_coarse(int nrhs, int n, const double* __restrict__ cinv, const double2* __restrict__ b,
+                             double2* __restrict__ x) {
+  GRID_STRIDE(i, (long long)n * nrhs) {
+    const long long base = (i / n) * n;
+    const double* row = cinv + (long long)(i % n) * n;
+    double2 acc = make_double2(0, 0);
+    for (int j = 0; j < n; ++j) acc = zadd(acc, zscale(b[base + j], row[j]));
+    x[i] = acc;
+  }
 }
 
 // ---------------------------------------------------------------- GMRES --
@@ -515,6 +575,8 @@ svh_status apply_K(Ctx& c, const double2* x, double2* y) {
 constexpr int kPcgBlock = 16;  // PCG iterations per convergence check (one graph replay)
 
 // One block of kPcgBlock conjugate-gradient iterations on S b = e, enqueued on s.
+void vcycle(Ctx& c, const double2* b0, double2* x0, hipStream_t s);
+
 void pcg_block(Ctx& c, hipStream_t s) {
   svh_problem* p = c.p;
   const long long nM = (long long)c.M * c.nr;
@@ -527,6 +589,7 @@ void pcg_block(Ctx& c, hipStream_t s) {
     hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(256), 0, s, c.nr, c.w.rho, c.w.pq, c.w.alpha);
     hipLaunchKernelGGL(k_pcg_update, dim3(nblocks(nM)), dim3(256), 0, s, nM, c.M, p->d_sdiag, p->d_free,
                        c.w.alpha, c.w.P, c.w.Q, c.w.Bs, c.w.R, c.w.Zp);
+    if (!p->amg.empty()) vcycle(c, c.w.R, c.w.Zp, s);
     mdot(c, c.M, 1, c.w.R, 0, c.M, c.w.Zp, c.M, c.w.rhon, s);
     hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(256), 0, s, c.nr, c.w.rho, c.w.rhon, c.w.beta);
     hipLaunchKernelGGL(k_pcg_dir, dim3(nblocks(nM)), dim3(256), 0, s, nM, c.M, c.w.beta, c.w.Zp, c.w.P);
@@ -554,6 +617,10 @@ svh_status apply_P(Ctx& c, const double2* in, double2* out, double itol, int ima
                      p->d_rval, p->d_free, p->d_ydiag, in, c.w.E, c.transpose);
   hipLaunchKernelGGL(k_pcg_init, dim3(nblocks(nM)), dim3(256), 0, c.s, nM, c.M, p->d_sdiag, p->d_free, c.w.E,
                      c.w.R, c.w.Zp, c.w.P, c.w.Bs);
+  if (!p->amg.empty()) {
+    vcycle(c, c.w.R, c.w.Zp, c.s);
+    hipLaunchKernelGGL(k_copy, dim3(nblocks(nM)), dim3(256), 0, c.s, nM, c.w.Zp, c.w.P);
+  }
   mdot(c, c.M, 1, c.w.R, 0, c.M, c.w.Zp, c.M, c.w.rho);
   std::vector<double2> rho0(c.nr), rhoc(c.nr);
   SCHK(hipMemcpyAsync(rho0.data(), c.w.rho, sizeof(double2) * c.nr, hipMemcpyDeviceToHost, c.s));
@@ -580,6 +647,122 @@ svh_status apply_P(Ctx& c, const double2* in, double2* out, double itol, int ima
 }
 
 // |diag Z| per basis function and the diagonal of S for frequency slot f
+void free_amg(svh_problem* p) {
+  for (auto& L : p->amg) {
+    fr(L.rptr);
+    fr(L.col);
+    fr(L.val);
+    fr(L.dinv);
+    fr(L.agg);
+    fr(L.mptr);
+    fr(L.mem);
+    fr(L.b);
+    fr(L.x);
+    fr(L.r);
+  }
+  p->amg.clear();
+  fr(p->d_amg_cinv);
+}
+
+// Multigrid hierarchy of S for the current Y and Dirichlet set, with work
+// vectors for nports right-hand sides.
+svh_status build_amg(svh_problem* p, const std::vector<double>& yd) {
+  free_amg(p);
+  std::vector<AmgLevel> levels;
+  std::vector<std::vector<int>> aggs;
+  std::vector<double> cinv;
+  const int kind = amg_setup(schur_matrix(p->topo, p->dirichlet, yd), levels, aggs, cinv);
+  if (kind < 0) return sfail(p, SVH_EINVAL, "solve: multigrid setup of the Schur complement failed");
+  p->amg_coarse = kind;
+  const int nr = p->nports;
+  p->amg.resize(levels.size());
+  for (size_t l = 0; l < levels.size(); ++l) {
+    const AmgLevel& L = levels[l];
+    auto& D = p->amg[l];
+    D.n = L.n;
+    std::vector<double> dinv(L.n, 1.0);
+    for (int i = 0; i < L.n; ++i) {
+      bool coupled = false;
+      double dg = 0;
+      for (int q = L.rptr[i]; q < L.rptr[i + 1]; ++q) {
+        if (L.col[q] == i) dg = L.val[q];
+        else if (L.val[q] != 0) coupled = true;
+      }
+      dinv[i] = dg > 0 ? (coupled ? kAmgOmega : 1.0) / dg : 1.0;
+    }
+    SCHK(up(&D.rptr, L.rptr.data(), L.rptr.size()));
+    SCHK(up(&D.col, L.col.data(), L.col.size()));
+    SCHK(up(&D.val, L.val.data(), L.val.size()));
+    SCHK(up(&D.dinv, dinv.data(), dinv.size()));
+    SCHK(hipMalloc(&D.r, sizeof(double2) * (size_t)nr * L.n));
+    if (l > 0) {
+      SCHK(hipMalloc(&D.b, sizeof(double2) * (size_t)nr * L.n));
+      SCHK(hipMalloc(&D.x, sizeof(double2) * (size_t)nr * L.n));
+    }
+    if (l + 1 < levels.size()) {
+      const std::vector<int>& agg = aggs[l];
+      const int nc = levels[l + 1].n;
+      std::vector<int> mptr(nc + 1, 0);
+      for (int i = 0; i < L.n; ++i)
+        if (agg[i] >= 0) mptr[agg[i] + 1]++;
+      std::partial_sum(mptr.begin(), mptr.end(), mptr.begin());
+      std::vector<int> mem(std::max(mptr[nc], 1), 0);
+      std::vector<int> fill(mptr.begin(), mptr.end() - 1);
+      for (int i = 0; i < L.n; ++i)
+        if (agg[i] >= 0) mem[fill[agg[i]]++] = i;
+      SCHK(up(&D.agg, agg.data(), agg.size()));
+      SCHK(up(&D.mptr, mptr.data(), mptr.size()));
+      SCHK(up(&D.mem, mem.data(), mem.size()));
+    }
+  }
+  if (!cinv.empty()) SCHK(up(&p->d_amg_cinv, cinv.data(), cinv.size()));
+  p->amg_nr = nr;
+  return SVH_OK;
+}
+
+// z = B r: one symmetric V-cycle (one damped-Jacobi sweep before and after
+// the scaled coarse correction; on the coarsest level its dense inverse, its
+// diagonal when it has no couplings, or damped Jacobi sweeps) per right-hand
+// side.
+void vcycle(Ctx& c, const double2* b0, double2* x0, hipStream_t s) {
+  svh_problem* p = c.p;
+  const int nl = (int)p->amg.size(), nr = c.nr;
+  for (int l = 0; l < nl; ++l) {
+    auto& L = p->amg[l];
+    const double2* b = l ? L.b : b0;
+    double2* x = l ? L.x : x0;
+    const long long n = (long long)L.n * nr;
+    if (l == nl - 1) {
+      if (p->amg_coarse == kAmgCoarseDense) {
+        hipLaunchKernelGGL(k_amg_coarse, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, p->d_amg_cinv, b, x);
+      } else {  // diagonal matrix (exact), or damped Jacobi sweeps
+        hipLaunchKernelGGL(k_amg_smooth0, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, b, x);
+        for (int k = 1; k < (p->amg_coarse == kAmgCoarseJacobi ? kAmgCoarseSweeps : 1); ++k) {
+          hipLaunchKernelGGL(k_amg_resid, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.rptr, L.col, L.val, b, x,
+                             L.r);
+          hipLaunchKernelGGL(k_amg_jacobi, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, L.r, x);
+        }
+      }
+      break;
+    }
+    hipLaunchKernelGGL(k_amg_smooth0, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, b, x);
+    hipLaunchKernelGGL(k_amg_resid, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.rptr, L.col, L.val, b, x, L.r);
+    auto& Cl = p->amg[l + 1];
+    hipLaunchKernelGGL(k_amg_restrict, dim3(nblocks((long long)Cl.n * nr)), dim3(256), 0, s, nr, L.n, Cl.n, L.mptr,
+                       L.mem, L.r, Cl.b);
+  }
+  for (int l = nl - 2; l >= 0; --l) {
+    auto& L = p->amg[l];
+    auto& Cl = p->amg[l + 1];
+    const double2* b = l ? L.b : b0;
+    double2* x = l ? L.x : x0;
+    const long long n = (long long)L.n * nr;
+    hipLaunchKernelGGL(k_amg_prolong, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, Cl.n, L.agg, Cl.x, x);
+    hipLaunchKernelGGL(k_amg_resid, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.rptr, L.col, L.val, b, x, L.r);
+    hipLaunchKernelGGL(k_amg_jacobi, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, L.r, x);
+  }
+}
+
 svh_status prepare_diag(svh_problem* p, int f) {
   if (p->diag_freq == f && p->d_ydiag) return SVH_OK;
   const int K = p->nvox, CK = p->C * K, M = p->topo.M;
@@ -609,6 +792,8 @@ svh_status prepare_diag(svh_problem* p, int f) {
   SCHK(up(&p->d_ydiag, yd.data(), yd.size()));
   SCHK(up(&p->d_sdiag, sd.data(), sd.size()));
   p->diag_freq = f;
+  if (p->schur_precond == SVH_SCHUR_AMG) return build_amg(p, yd);
+  free_amg(p);
   return SVH_OK;
 }
 
@@ -766,6 +951,7 @@ void free_solver(svh_problem* p) {
   fr(p->d_bport);
   fr(p->d_ydiag);
   fr(p->d_sdiag);
+  free_amg(p);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   p->cap_stream = nullptr;
 }
@@ -997,6 +1183,14 @@ svh_status svh_matvec_adjoint(svh_problem* p, svh_prec prec, int nrhs, const int
   // product runs the same kernels.
   if (!p) return SVH_EINVAL;
   return svh_matvec(p, prec, nrhs, freq_idx_host, x_dev, y_dev, ws_dev, ws_bytes, stream);
+}
+
+svh_status svh_set_schur_precond(svh_problem* p, int kind) {
+  if (!p) return SVH_EINVAL;
+  if (kind != SVH_SCHUR_JACOBI && kind != SVH_SCHUR_AMG) return sfail(p, SVH_EINVAL, "set_schur_precond: unknown kind");
+  if (kind != p->schur_precond) p->diag_freq = -2;  // rebuilt at the next solve
+  p->schur_precond = kind;
+  return SVH_OK;
 }
 
 svh_status svh_set_graphs(svh_problem* p, int enable) {

@@ -155,6 +155,19 @@ struct svh_problem {
   double* d_ydiag = nullptr;  // |diag Z| per basis function (for diag_freq)
   double* d_sdiag = nullptr;  // diagonal of the Schur complement per node
   int diag_freq = -2;
+  // aggregation multigrid preconditioner of the Schur complement CG (built for
+  // amg_freq and amg_nr right-hand sides; device copies of every level)
+  int schur_precond = 1;  // SVH_SCHUR_JACOBI / SVH_SCHUR_AMG
+  int amg_freq = -2, amg_nr = 0;
+  int amg_coarse = 0;  // kAmgCoarseDense / Diagonal / Jacobi
+  struct AmgDev {
+    int n = 0;
+    int32_t *rptr = nullptr, *col = nullptr, *agg = nullptr, *mptr = nullptr, *mem = nullptr;
+    double *val = nullptr, *dinv = nullptr;
+    double2 *b = nullptr, *x = nullptr, *r = nullptr;  // [nr][n] work vectors
+  };
+  std::vector<AmgDev> amg;
+  double* d_amg_cinv = nullptr;
   bool use_graphs = true;             // replay the captured PCG iteration block
   hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
   // per-kernel timing: one event set per enqueued chunk while enabled
