@@ -103,6 +103,19 @@ template <typename C, bool STRIDED> struct Lds {
   }
 };
 
+// Twiddle table of a length-L transform copied into LDS at `dst` (after the
+// block's work area) once per block.  The stages then read twiddles from LDS,
+// whose reads are counted apart from the global loads: a stage no longer
+// waits for the in-flight loads of the next item when it needs a twiddle
+// (vector memory loads complete in issue order).
+template <typename C>
+__device__ __forceinline__ const C* lds_twiddles(C* dst, const C* __restrict__ tw, int L) {
+  for (int i = threadIdx.x; i < L; i += blockDim.x) dst[i] = tw[i];
+  __syncthreads();
+  return dst;
+}
+inline size_t twiddle_bytes(int L, size_t csize) { return (size_t)L * csize; }
+
 // Ordering of the LDS accesses of the lanes of one wavefront: the wave's LDS
 // instructions execute in program order, so only the compiler must be kept
 // from moving accesses across this point.

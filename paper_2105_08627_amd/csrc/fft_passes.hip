@@ -68,7 +68,8 @@ __global__ void __launch_bounds__(256) k_pass_x(FftPlan pl, Geo geo, int WX, int
     return RowOut<C>{A + ((size_t)vec * nzp + zp) * geo.pa + (size_t)y * geo.rp, Lx, valid};
   };
   Lds<C, false> acc{lds, WX, pencil_pitch(Lx), w};
-  run_items<P, C, -1, false>(pl, j0, ngrp * nvec, mk_in, mk_out, acc, tw);
+  const C* twl = lds_twiddles(lds + (size_t)WX * pencil_pitch(Lx), tw, Lx);
+  run_items<P, C, -1, false>(pl, j0, ngrp * nvec, mk_in, mk_out, acc, twl);
 }
 
 // ------------------------------------------------------------ Y passes ----
@@ -124,7 +125,8 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_y(FftPlan pl, Geo geo
     return ColOut<C>{out + c.first * (DIR < 0 ? geo.pb : geo.pa) + c.second, geo.rp, rows_out, valid};
   };
   Lds<C, true> acc{lds, W, 0, w};
-  run_items<P, C, DIR, true>(pl, j0, ntile * nzp * nvec, mk_in, mk_out, acc, tw);
+  const C* twl = lds_twiddles(lds + (size_t)W * Ly, tw, Ly);
+  run_items<P, C, DIR, true>(pl, j0, ntile * nzp * nvec, mk_in, mk_out, acc, twl);
 }
 
 // ---------------------------------------------------------------- Z pass --
@@ -233,6 +235,7 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_z(FftPlan pl, FftPlan
     for (; q < 12; ++q) zv[q] = (T)0;
   }
   Lds<C, true> acc{lds, W, 0, w};
+  const C* twl = lds_twiddles(lds + (size_t)W * L, tw, L);
   const int v0 = blockIdx.y * vpb;
   const int v1 = min(nvec, v0 + vpb);
   for (int vec = v0; vec < v1; ++vec) {
@@ -240,26 +243,26 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_z(FftPlan pl, FftPlan
     ZIn<C> gin{vb, zslot, (size_t)geo.pb, valid};
     ZOut<C> gout{vb, zslot, (size_t)geo.pb, valid};
     if (pl.ns == 1) {
-      fused_mul<C, T>(Rl, L, j0, TP, gin, gout, tw, zv, false);
+      fused_mul<C, T>(Rl, L, j0, TP, gin, gout, twl, zv, false);
     } else {
       int Ns = 1;
-      stage_any<C, -1, false>(pl.r[0], L, Ns, j0, TP, gin, acc, tw);
+      stage_any<C, -1, false>(pl.r[0], L, Ns, j0, TP, gin, acc, twl);
       Ns *= pl.r[0];
       __syncthreads();
       for (int s = 1; s < pl.ns - 1; ++s) {
-        stage_any<C, -1, true>(pl.r[s], L, Ns, j0, TP, acc, acc, tw);
+        stage_any<C, -1, true>(pl.r[s], L, Ns, j0, TP, acc, acc, twl);
         Ns *= pl.r[s];
         __syncthreads();
       }
-      fused_mul<C, T>(Rl, L, j0, TP, acc, acc, tw, zv, true);
+      fused_mul<C, T>(Rl, L, j0, TP, acc, acc, twl, zv, true);
       __syncthreads();
       Ns = Rl;
       for (int s = 1; s < ipl.ns - 1; ++s) {
-        stage_any<C, +1, true>(ipl.r[s], L, Ns, j0, TP, acc, acc, tw);
+        stage_any<C, +1, true>(ipl.r[s], L, Ns, j0, TP, acc, acc, twl);
         Ns *= ipl.r[s];
         __syncthreads();
       }
-      stage_any<C, +1, false>(ipl.r[ipl.ns - 1], L, Ns, j0, TP, acc, gout, tw);
+      stage_any<C, +1, false>(ipl.r[ipl.ns - 1], L, Ns, j0, TP, acc, gout, twl);
       __syncthreads();
     }
   }
@@ -554,7 +557,8 @@ __global__ void __launch_bounds__(256) k_pass_xi(FftPlan pl, Geo geo, int WX, in
                       vidx + ((size_t)zlist[zp] * Ky + yy) * Kx, scale, mass, Kx, valid};
   };
   Lds<C, false> acc{lds, WX, pencil_pitch(Lx), w};
-  run_items<P, C, +1, false>(pl, j0, ngrp * nvec, mk_in, mk_out, acc, tw);
+  const C* twl = lds_twiddles(lds + (size_t)WX * pencil_pitch(Lx), tw, Lx);
+  run_items<P, C, +1, false>(pl, j0, ngrp * nvec, mk_in, mk_out, acc, twl);
 }
 
 // ------------------------------------------------------------- launcher ---
@@ -615,7 +619,7 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const int WX = pencils_per_block_x(tp);
     const int NP = nzp * Ky;
     const int nitems = ((NP + WX - 1) / WX) * nvec;
-    const size_t sh = (size_t)WX * pencil_pitch(Lx) * sizeof(C);
+    const size_t sh = (size_t)WX * pencil_pitch(Lx) * sizeof(C) + twiddle_bytes(Lx, sizeof(C));
     const int g = persistent_grid((const void*)k_pass_x<T, P>, WX * tp, sh, nitems, p->ncu, tn.grid_mult[0]);
     hipLaunchKernelGGL((k_pass_x<T, P>), dim3(g), dim3(WX * tp), sh, s, pl, geo, WX, Kx, Ky, nzp, K, nvec,
                        ep.C, ep.ldx, p->d_zlist, p->d_vidx, x, A, tw[0]);
@@ -628,7 +632,7 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const int tp = P::tpof(pl);
     const int W = std::max(1, cols_per_block(tp, Ly, sizeof(C)) >> tn.ycols_shift[0]);
     const int nitems = ((Lx + W - 1) / W) * nzp * nvec;
-    const size_t sh = (size_t)W * Ly * sizeof(C);
+    const size_t sh = (size_t)W * Ly * sizeof(C) + twiddle_bytes(Ly, sizeof(C));
     const int g = persistent_grid((const void*)k_pass_y<T, -1, P>, W * tp, sh, nitems, p->ncu, tn.grid_mult[1]);
     hipLaunchKernelGGL((k_pass_y<T, -1, P>), dim3(g), dim3(W * tp), sh, s, pl, geo, W, Lx, Ky, nzp, nvec, A, B,
                        tw[1]);
@@ -694,7 +698,7 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const FftPlan ipl = reversed(pl);
     const int vpb = nvec < 4 ? nvec : 4;
     dim3 grid(((Lx + W - 1) / W) * Ly, (nvec + vpb - 1) / vpb);
-    const size_t sh = (size_t)W * pl.L * sizeof(C);
+    const size_t sh = (size_t)W * pl.L * sizeof(C) + twiddle_bytes(pl.L, sizeof(C));
     hipLaunchKernelGGL(k_pass_z<T>, grid, dim3(W * pl.tp), sh, s, pl, ipl, geo, W, Lx, Ly, nzp, nvec, vpb,
                        p->d_zslot, static_cast<const T*>(zhat), B, tw[2]);
   }
@@ -706,7 +710,7 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const int tp = P::tpof(pl);
     const int W = std::max(1, cols_per_block(tp, Ly, sizeof(C)) >> tn.ycols_shift[1]);
     const int nitems = ((Lx + W - 1) / W) * nzp * nvec;
-    const size_t sh = (size_t)W * Ly * sizeof(C);
+    const size_t sh = (size_t)W * Ly * sizeof(C) + twiddle_bytes(Ly, sizeof(C));
     const int g = persistent_grid((const void*)k_pass_y<T, +1, P>, W * tp, sh, nitems, p->ncu, tn.grid_mult[2]);
     hipLaunchKernelGGL((k_pass_y<T, +1, P>), dim3(g), dim3(W * tp), sh, s, pl, geo, W, Lx, Ky, nzp, nvec, B, A,
                        tw[1]);
@@ -720,7 +724,7 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const int WX = pencils_per_block_x(tp);
     const int NP = nzp * Ky;
     const int nitems = ((NP + WX - 1) / WX) * nvec;
-    const size_t sh = (size_t)WX * pencil_pitch(Lx) * sizeof(C);
+    const size_t sh = (size_t)WX * pencil_pitch(Lx) * sizeof(C) + twiddle_bytes(Lx, sizeof(C));
     const int g = persistent_grid((const void*)k_pass_xi<T, P>, WX * tp, sh, nitems, p->ncu, tn.grid_mult[3]);
     // the direct z sum uses the z-space kernel, so only the x and y
     // transforms leave a factor to divide out

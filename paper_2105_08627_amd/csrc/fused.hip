@@ -180,6 +180,7 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_xt(FftPlan pl, GeoT g
   const int w = t / TP, j0 = t % TP;
   const int ngy = (Ky + WX - 1) / WX;
   const int nitems = nvec * nzp * ngy;
+  const C* twl = lds_twiddles(lds + (size_t)WX * PP, tw, Lx);
   for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
     const int gy = item % ngy;
     const int vz = item / ngy;  // vec * nzp + plane
@@ -190,7 +191,7 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_xt(FftPlan pl, GeoT g
       return XIn<C>{x + (size_t)(vec / ncomp) * ldx + (size_t)(vec % ncomp) * K,
                     vidx + ((size_t)zlist[zp] * Ky + (ok ? y : 0)) * Kx, Kx, ok};
     };
-    fft_batch<P, C, -1, false, false>(pl, 1, WX, w, j0, mksrc, [](int) { return NoDst<C>{}; }, lds, PP, tw);
+    fft_batch<P, C, -1, false, false>(pl, 1, WX, w, j0, mksrc, [](int) { return NoDst<C>{}; }, lds, PP, twl);
     C* col = At + (size_t)vz * gt.pq + gy * WX;
     for (int e = t; e < Lx * WX; e += nt) {
       const int yy = e % WX, kx = e / WX;
@@ -220,6 +221,7 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_xit(FftPlan pl, GeoT 
   const int w = t / TP, j0 = t % TP;
   const int ngy = (Ky + WX - 1) / WX;
   const int nitems = nvec * nzp * ngy;
+  const C* twl = lds_twiddles(lds + (size_t)WX * PP, tw, Lx);
   for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
     const int gy = item % ngy;
     const int vz = item / ngy;
@@ -241,7 +243,7 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_xit(FftPlan pl, GeoT 
       return XOut<C, T>{y + (size_t)rhs * ep.ldy + (size_t)comp * K, x + (size_t)rhs * ep.ldx + (size_t)comp * K, cd,
                         vidx + ((size_t)zlist[zp] * Ky + (ok ? yy : 0)) * Kx, scale, mass, Kx, ok};
     };
-    fft_batch<P, C, +1, true, true>(pl, 1, WX, w, j0, [](int) { return NoDst<C>{}; }, mkdst, lds, PP, tw);
+    fft_batch<P, C, +1, true, true>(pl, 1, WX, w, j0, [](int) { return NoDst<C>{}; }, mkdst, lds, PP, twl);
   }
 }
 
@@ -454,7 +456,7 @@ hipError_t launch_matvec_chunk_fused(const svh_problem* p, int nvec, const EpiPa
     const int tp = P::tpof(pl);
     const int WX = rows_per_block_xt(tp, Lx, sizeof(C));
     const int nitems = nvec * nzp * ((Ky + WX - 1) / WX);
-    const size_t sh = (size_t)WX * pencil_pitch(Lx) * sizeof(C);
+    const size_t sh = (size_t)WX * pencil_pitch(Lx) * sizeof(C) + twiddle_bytes(Lx, sizeof(C));
     const int g = persistent_grid((const void*)k_pass_xt<T, P>, WX * tp, sh, nitems, p->ncu, tn.grid_mult[0]);
     hipLaunchKernelGGL((k_pass_xt<T, P>), dim3(g), dim3(WX * tp), sh, s, pl, gt, WX, Kx, Ky, nzp, K, nvec, ep.C,
                        ep.ldx, p->d_zlist, p->d_vidx, x, At, tw[0]);
@@ -502,7 +504,7 @@ hipError_t launch_matvec_chunk_fused(const svh_problem* p, int nvec, const EpiPa
     const int tp = P::tpof(pl);
     const int WX = rows_per_block_xt(tp, Lx, sizeof(C));
     const int nitems = nvec * nzp * ((Ky + WX - 1) / WX);
-    const size_t sh = (size_t)WX * pencil_pitch(Lx) * sizeof(C);
+    const size_t sh = (size_t)WX * pencil_pitch(Lx) * sizeof(C) + twiddle_bytes(Lx, sizeof(C));
     const int g = persistent_grid((const void*)k_pass_xit<T, P>, WX * tp, sh, nitems, p->ncu, tn.grid_mult[3]);
     const T inv_n = (T)(1.0 / ((double)Lx * Ly));
     const C* sc = dbl ? reinterpret_cast<const C*>(p->d_sconv64) : reinterpret_cast<const C*>(p->d_sconv32);
