@@ -218,7 +218,32 @@ svh_status svh_create(svh_problem** out, int Kx, int Ky, int Kz, double dx_m, in
       HIPCHK(upload(&p->d_twp32, t32.data(), t32.size()));
     }
   }
-  HIPCHK(upload(&p->d_vidx, p->vidx.data(), Kt));
+  {
+    // occupancy words of the rows of the occupied planes (x pass gather and
+    // inverse x pass scatter)
+    const int nw = (Kx + 63) / 64, nzp = (int)p->zlist.size();
+    p->xrow_words = nw;
+    // one extra all-zero word at the end: the zero value that the x pass
+    // loads for empty grid positions
+    std::vector<XRowWord> xr((size_t)nzp * Ky * nw + 1, XRowWord{0, 0, 0});
+    for (int zp = 0; zp < nzp; ++zp)
+      for (int y = 0; y < Ky; ++y)
+        for (int w = 0; w < nw; ++w) {
+          XRowWord& e = xr[((size_t)zp * Ky + y) * nw + w];
+          e.bits = 0;
+          e.base = 0;
+          e.pad = 0;
+          bool first = true;
+          for (int b = 0; b < 64 && w * 64 + b < Kx; ++b) {
+            const int32_t k = p->vidx[((size_t)p->zlist[zp] * Ky + y) * Kx + w * 64 + b];
+            if (k < 0) continue;
+            if (first) e.base = k;
+            first = false;
+            e.bits |= 1ull << b;
+          }
+        }
+    HIPCHK(upload(&p->d_xrow, xr.data(), xr.size()));
+  }
   HIPCHK(upload(&p->d_zlist, p->zlist.data(), p->zlist.size()));
   HIPCHK(upload(&p->d_zslot, p->zslot.data(), p->zslot.size()));
   for (int a = 0; a < 3; ++a) {
@@ -837,7 +862,7 @@ void svh_destroy(svh_problem* p) {
   int cur = 0;
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(p->device);
-  dfree(p->d_vidx);
+  dfree(p->d_xrow);
   dfree(p->d_zlist);
   dfree(p->d_zslot);
   for (int a = 0; a < 3; ++a) {

@@ -103,6 +103,15 @@ template <typename C, bool STRIDED> struct Lds {
   }
 };
 
+// Global accessors with a split load (kGather: word(), index(), at()) or
+// store (kScatter: word(), index(), diag(), put()); the stages issue all
+// lookups of a thread before the value accesses.
+template <typename C> struct DiagPair { C c, x; };
+template <class A, class = void> struct IsGather : std::false_type {};
+template <class A> struct IsGather<A, std::void_t<decltype(A::kGather)>> : std::true_type {};
+template <class A, class = void> struct IsScatter : std::false_type {};
+template <class A> struct IsScatter<A, std::void_t<decltype(A::kScatter)>> : std::true_type {};
+
 // Twiddle table of a length-L transform copied into LDS at `dst` (after the
 // block's work area) once per block.  The stages then read twiddles from LDS,
 // whose reads are counted apart from the global loads: a stage no longer
@@ -131,7 +140,39 @@ template <typename C, int R, int DIR, int SYNC_MID, class Src, class Dst>
 __device__ __forceinline__ void stage_r(int L, int Ns, int j0, int TP, const Src& src, const Dst& dst,
                                         const C* __restrict__ tw) {
   constexpr int NB = NbMax<R>::v;
+  constexpr bool SC = IsScatter<Dst>::value;
   const int LR = L / R;
+  // scatter outputs: indices first, then (after the LDS reads) the operands
+  // of the diagonal terms, global loads that overlap the butterflies
+  int kk[SC ? NB : 1][SC ? R : 1];
+  DiagPair<C> dg[SC ? NB : 1][SC ? R : 1];
+  if constexpr (SC) {
+    int4 wd[NB][R];
+    if constexpr (Dst::kUniform) {
+      // last stage (Ns R = L, so base = j) with TP and Ns multiples of 64:
+      // the word of j0 + it TP + r Ns is uniform
+      const int wq = __builtin_amdgcn_readfirstlane(j0 >> 6);
+#pragma unroll
+      for (int it = 0; it < NB; ++it)
+#pragma unroll
+        for (int r = 0; r < R; ++r) wd[it][r] = dst.row.word_u(wq + ((it * TP + r * Ns) >> 6));
+    } else {
+#pragma unroll
+      for (int it = 0; it < NB; ++it) {
+        const int j = j0 + it * TP;
+        const int base = (j / Ns) * Ns * R + j % Ns;
+#pragma unroll
+        for (int r = 0; r < R; ++r) wd[it][r] = dst.row.word(j < LR ? base + r * Ns : 0);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < NB; ++it) {
+      const int j = j0 + it * TP;
+      const int base = (j / Ns) * Ns * R + j % Ns;
+#pragma unroll
+      for (int r = 0; r < R; ++r) kk[it][r] = j < LR ? dst.row.index(base + r * Ns, wd[it][r]) : -1;
+    }
+  }
   C v[NB][R];
 #pragma unroll
   for (int it = 0; it < NB; ++it) {
@@ -140,6 +181,12 @@ __device__ __forceinline__ void stage_r(int L, int Ns, int j0, int TP, const Src
 #pragma unroll
       for (int r = 0; r < R; ++r) v[it][r] = src.ld(j + r * LR);
     }
+  }
+  if constexpr (SC) {
+#pragma unroll
+    for (int it = 0; it < NB; ++it)
+#pragma unroll
+      for (int r = 0; r < R; ++r) dg[it][r] = dst.diag(kk[it][r]);
   }
   if constexpr (SYNC_MID == 1) __syncthreads();
   if constexpr (SYNC_MID == 2) wave_sync();
@@ -159,8 +206,13 @@ __device__ __forceinline__ void stage_r(int L, int Ns, int j0, int TP, const Src
       }
       dft<R, DIR>(v[it]);
       const int base = (j / Ns) * Ns * R + k;
+      if constexpr (SC) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst.st(base + r * Ns, v[it][r]);
+        for (int r = 0; r < R; ++r) dst.put(kk[it][r], v[it][r], dg[it][r]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst.st(base + r * Ns, v[it][r]);
+      }
     }
   }
 }
@@ -204,12 +256,41 @@ template <typename C, int R, class Src>
 __device__ __forceinline__ void load0_r(int L, int j0, int TP, const Src& src, C (&v)[12]) {
   constexpr int NB = NbMax<R>::v;
   const int LR = L / R;
+  if constexpr (IsGather<Src>::value) {
+    // all occupancy lookups first, then all value loads
+    int4 wd[NB * R];
+    if constexpr (Src::kUniform) {
+      // TP and LR are multiples of 64: word of j0 + it TP + r LR is uniform
+      const int wq = __builtin_amdgcn_readfirstlane(j0 >> 6);
 #pragma unroll
-  for (int it = 0; it < NB; ++it) {
-    const int j = j0 + it * TP;
-    if (j < LR) {
+      for (int it = 0; it < NB; ++it)
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[it * R + r] = src.ld(j + r * LR);
+        for (int r = 0; r < R; ++r) wd[it * R + r] = src.row.word_u(wq + ((it * TP + r * LR) >> 6));
+    } else {
+#pragma unroll
+      for (int it = 0; it < NB; ++it) {
+        const int j = j0 + it * TP;
+#pragma unroll
+        for (int r = 0; r < R; ++r) wd[it * R + r] = src.row.word(j < LR ? j + r * LR : 0);
+      }
+    }
+    int k[NB * R];
+#pragma unroll
+    for (int it = 0; it < NB; ++it) {
+      const int j = j0 + it * TP;
+#pragma unroll
+      for (int r = 0; r < R; ++r) k[it * R + r] = j < LR ? src.row.index(j + r * LR, wd[it * R + r]) : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < NB * R; ++q) v[q] = src.at(k[q]);
+  } else {
+#pragma unroll
+    for (int it = 0; it < NB; ++it) {
+      const int j = j0 + it * TP;
+      if (j < LR) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[it * R + r] = src.ld(j + r * LR);
+      }
     }
   }
 }
@@ -382,35 +463,98 @@ inline int persistent_grid(const void* kernel, int threads, size_t shmem, int ni
   return (int)(g < nitems ? g : nitems);
 }
 
-// Gather accessor of the forward x transform: compact vector -> x pencil.
-template <typename C> struct XIn {
-  const C* __restrict__ x;       // compact vector of this component
-  const int32_t* __restrict__ vrow;  // voxel index row (Kx entries)
+// Compact index of grid position n from its row's occupancy word (bits low,
+// bits high, base, pad), or -1.
+__device__ __forceinline__ int xrow_index(int4 wd, int n, bool ok) {
+  const unsigned long long bits = ((unsigned long long)(unsigned)wd.y << 32) | (unsigned)wd.x;
+  const int b = n & 63;
+  // branch-free: all ones when the voxel exists, else zero
+  const int sel = -(int)((unsigned)ok & (unsigned)((bits >> b) & 1ull));
+  return ((wd.z + __popcll(bits & ((1ull << b) - 1ull))) & sel) | ~sel;
+}
+
+// Occupancy words of one grid row.  With UNI, all lanes of a wavefront work
+// on the same row (one pencil per wave or more waves per pencil), so a word
+// index that is the same on every lane reads through the scalar cache
+// (word_u): scalar loads are counted apart from the vector memory accesses,
+// and a lookup does not wait for the wave's earlier global loads and stores.
+template <bool UNI> struct XRow {
+  const XRowWord* __restrict__ xrow;  // all rows (kernel argument)
+  int rowoff;                         // first word of this row (wave-uniform with UNI)
+  int nw;                             // words per row
   int Kx;
   bool valid;
-  __device__ __forceinline__ C ld(int n) const {
-    if (!valid || n >= Kx) return C{0, 0};
-    const int k = vrow[n];
-    return k >= 0 ? x[k] : C{0, 0};
+  __device__ __forceinline__ bool in(int n) const { return valid && n < Kx; }
+  // always a valid address (the last word for n >= Kx): an unconditional load
+  __device__ __forceinline__ int4 word(int n) const {
+    return reinterpret_cast<const int4*>(xrow)[rowoff + ((n < Kx ? n : Kx - 1) >> 6)];
   }
+  __device__ __forceinline__ int4 word_u(int wi) const {
+    // constant address space: a uniform load there is a scalar load
+    typedef __attribute__((address_space(4))) const int cint;
+    const cint* q = (const cint*)xrow + 4 * (rowoff + (wi < nw ? wi : nw - 1));
+    return int4{q[0], q[1], q[2], q[3]};
+  }
+  __device__ __forceinline__ int index(int n, int4 wd) const { return xrow_index(wd, n, in(n)); }
 };
-// Scatter accessor of the inverse x transform: scale, diagonal term, compact output.
-template <typename C, typename T> struct XOut {
+template <bool UNI>
+__device__ __forceinline__ XRow<UNI> make_xrow(const XRowWord* xrow, int row, int nw, int Kx, bool valid) {
+  int off = row * nw;
+  if constexpr (UNI) off = __builtin_amdgcn_readfirstlane(off);
+  return XRow<UNI>{xrow, off, nw, Kx, valid};
+}
+
+// Whether a compile-time plan keeps one grid row per wavefront in the x
+// passes, with the word index of the first stage's loads and the last stage's
+// stores uniform over the wave (threads per pencil and the strides L / r of
+// the first and the last stage multiples of 64).
+template <class P> constexpr bool uniform_rows() {
+  if constexpr (P::rt) return false;
+  else return P::tp % 64 == 0 && (P::L / P::r(0)) % 64 == 0 && (P::L / P::r(P::ns - 1)) % 64 == 0;
+}
+
+// Gather accessor of the forward x transform: compact vector -> x pencil.
+// Split into the occupancy word load, the index and the value load, so that
+// the first stage issues all word loads of a thread, then all value loads
+// (ld() does all three for other callers).
+template <typename C, bool UNI = false> struct XIn {
+  static constexpr bool kGather = true;
+  static constexpr bool kUniform = UNI;
+  const C* __restrict__ x;              // compact vector of this component
+  XRow<UNI> row;
+  const C* __restrict__ zero;           // a zero value in device memory
+  // empty positions load the zero value: the address is selected, not the
+  // value, so the load needs no wait until the value is used
+  __device__ __forceinline__ C at(int k) const { return *(k >= 0 ? x + k : zero); }
+  __device__ __forceinline__ C ld(int n) const { return at(row.index(n, row.word(n))); }
+};
+// Scatter accessor of the inverse x transform: scale, diagonal term, compact
+// output, split like XIn: a stage looks up all indices of its outputs first.
+template <typename C, typename T, bool UNI = false> struct XOut {
+  static constexpr bool kScatter = true;
+  static constexpr bool kUniform = UNI;
   C* __restrict__ y;                 // compact output of this component
   const C* __restrict__ x;           // compact input (diagonal term)
   const C* __restrict__ cd;          // c/dx per voxel (nullptr: bare)
-  const int32_t* __restrict__ vrow;
+  XRow<UNI> row;
   C scale;
   T mass;                            // integral of the squared basis function (eqs. 9, 16-18)
-  int Kx;
-  bool valid;
-  __device__ __forceinline__ void st(int n, C v) const {
-    if (!valid || n >= Kx) return;
-    const int k = vrow[n];
+  // operands of the diagonal term, loaded unconditionally (index 0 stands in
+  // for empty positions, whose outputs are not stored)
+  __device__ __forceinline__ DiagPair<C> diag(int k) const {
+    if (!cd) return DiagPair<C>{C{0, 0}, C{0, 0}};
+    const int kc = k >= 0 ? k : 0;
+    return DiagPair<C>{cd[kc], x[kc]};
+  }
+  __device__ __forceinline__ void put(int k, C v, const DiagPair<C>& d) const {
     if (k < 0) return;
     C o = cmul(v, scale);
-    if (cd) o = cadd(o, cscale(cmul(cd[k], x[k]), mass));
+    if (cd) o = cadd(o, cscale(cmul(d.c, d.x), mass));
     y[k] = o;
+  }
+  __device__ __forceinline__ void st(int n, C v) const {
+    const int k = row.index(n, row.word(n));
+    put(k, v, diag(k));
   }
 };
 

@@ -31,8 +31,7 @@ template <typename C> struct RowOut {
 template <typename T, class P>
 __global__ void __launch_bounds__(256) k_pass_x(FftPlan pl, Geo geo, int WX, int Kx, int Ky, int nzp, int K, int nvec,
                                                 int ncomp, long long ldx,
-                                                 const int32_t* __restrict__ zlist,
-                                                 const int32_t* __restrict__ vidx,
+                                                 const XRowWord* __restrict__ xrow,
                                                  const typename CT<T>::t* __restrict__ x,
                                                  typename CT<T>::t* __restrict__ A,
                                                  const typename CT<T>::t* __restrict__ tw) {
@@ -45,6 +44,9 @@ __global__ void __launch_bounds__(256) k_pass_x(FftPlan pl, Geo geo, int WX, int
   const int NP = nzp * Ky;
   const int ngrp = (NP + WX - 1) / WX;
   const int Lx = P::Lof(pl);
+  const int nw = (Kx + 63) >> 6;  // occupancy words per row
+  // the word array ends with one zero word, the zero value of empty positions
+  const typename CT<T>::t* zero = reinterpret_cast<const typename CT<T>::t*>(xrow + (size_t)nzp * Ky * nw);
   // item = vec * ngrp + pencil group
   auto where = [&](int item, int& vec, int& y, int& zp, bool& valid) {
     vec = item / ngrp;
@@ -58,8 +60,8 @@ __global__ void __launch_bounds__(256) k_pass_x(FftPlan pl, Geo geo, int WX, int
     int vec, y, zp;
     bool valid;
     where(item, vec, y, zp, valid);
-    return XIn<C>{x + (size_t)(vec / ncomp) * ldx + (size_t)(vec % ncomp) * K,
-                  vidx + ((size_t)zlist[zp] * Ky + y) * Kx, Kx, valid};
+    return XIn<C, uniform_rows<P>()>{x + (size_t)(vec / ncomp) * ldx + (size_t)(vec % ncomp) * K,
+                                     make_xrow<uniform_rows<P>()>(xrow, zp * Ky + y, nw, Kx, valid), zero};
   };
   auto mk_out = [&](int item) {
     int vec, y, zp;
@@ -509,10 +511,12 @@ __global__ void __launch_bounds__(256) k_zdirect5(Geo geo, int Lx, int Ly, int n
 }
 
 // --------------------------------------------------------------- Xi pass --
+// FP32: at least four 256-thread blocks per CU (at most 128 VGPRs), four
+// waves per SIMD to cover the scatter's loads.
+template <typename T> struct XiMinBlocks { static constexpr int v = sizeof(T) == 4 ? 4 : 1; };
 template <typename T, class P>
-__global__ void __launch_bounds__(256) k_pass_xi(FftPlan pl, Geo geo, int WX, int Kx, int Ky, int nzp, int K, int nvec,
-                                                  EpiParams ep, const int32_t* __restrict__ zlist,
-                                                  const int32_t* __restrict__ vidx,
+__global__ void __launch_bounds__(256, XiMinBlocks<T>::v) k_pass_xi(FftPlan pl, Geo geo, int WX, int Kx, int Ky, int nzp, int K, int nvec,
+                                                  EpiParams ep, const XRowWord* __restrict__ xrow,
                                                   const typename CT<T>::t* __restrict__ A,
                                                   const typename CT<T>::t* __restrict__ x,
                                                   typename CT<T>::t* __restrict__ y,
@@ -529,6 +533,7 @@ __global__ void __launch_bounds__(256) k_pass_xi(FftPlan pl, Geo geo, int WX, in
   const int NP = nzp * Ky;
   const int ngrp = (NP + WX - 1) / WX;
   const int Lx = P::Lof(pl);
+  const int nw = (Kx + 63) >> 6;  // occupancy words per row
   auto where = [&](int item, int& vec, int& yy, int& zp, bool& valid) {
     vec = item / ngrp;
     const int pen = (item % ngrp) * WX + w;
@@ -553,8 +558,10 @@ __global__ void __launch_bounds__(256) k_pass_xi(FftPlan pl, Geo geo, int WX, in
     const int rhs = vec / ep.C, comp = vec % ep.C;
     // 1 for the constant functions, 1/6 and 1/2 for the linear ones of eqs. 5-6
     const T mass = comp < 3 ? (T)1 : comp == 3 ? (T)(1.0 / 6.0) : (T)0.5;
-    return XOut<C, T>{y + (size_t)rhs * ep.ldy + (size_t)comp * K, x + (size_t)rhs * ep.ldx + (size_t)comp * K, cd,
-                      vidx + ((size_t)zlist[zp] * Ky + yy) * Kx, scale, mass, Kx, valid};
+    return XOut<C, T, uniform_rows<P>()>{y + (size_t)rhs * ep.ldy + (size_t)comp * K,
+                                         x + (size_t)rhs * ep.ldx + (size_t)comp * K, cd,
+                                         make_xrow<uniform_rows<P>()>(xrow, zp * Ky + yy, nw, Kx, valid), scale,
+                                         mass};
   };
   Lds<C, false> acc{lds, WX, pencil_pitch(Lx), w};
   const C* twl = lds_twiddles(lds + (size_t)WX * pencil_pitch(Lx), tw, Lx);
@@ -622,7 +629,7 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const size_t sh = (size_t)WX * pencil_pitch(Lx) * sizeof(C) + twiddle_bytes(Lx, sizeof(C));
     const int g = persistent_grid((const void*)k_pass_x<T, P>, WX * tp, sh, nitems, p->ncu, tn.grid_mult[0]);
     hipLaunchKernelGGL((k_pass_x<T, P>), dim3(g), dim3(WX * tp), sh, s, pl, geo, WX, Kx, Ky, nzp, K, nvec,
-                       ep.C, ep.ldx, p->d_zlist, p->d_vidx, x, A, tw[0]);
+                       ep.C, ep.ldx, p->d_xrow, x, A, tw[0]);
   });
   if (ev) hipEventRecord(ev[1], s);
   // Y forward
@@ -733,7 +740,7 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const C* sc = dbl ? reinterpret_cast<const C*>(p->d_sconv64) : reinterpret_cast<const C*>(p->d_sconv32);
     const C* cd = dbl ? reinterpret_cast<const C*>(p->d_cdiag64) : reinterpret_cast<const C*>(p->d_cdiag32);
     hipLaunchKernelGGL((k_pass_xi<T, P>), dim3(g), dim3(WX * tp), sh, s, pl, geo, WX, Kx, Ky, nzp, K, nvec, ep,
-                       p->d_zlist, p->d_vidx, A, x, y, sc, cd, inv_n, tw[0]);
+                       p->d_xrow, A, x, y, sc, cd, inv_n, tw[0]);
   });
   if (ev) hipEventRecord(ev[5], s);
   return hipGetLastError();

@@ -166,8 +166,7 @@ __device__ __forceinline__ void fft_batch(const FftPlan& pl, int nrd, int G, int
 template <typename T, class P>
 __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_xt(FftPlan pl, GeoT gt, int WX, int Kx, int Ky, int nzp, int K,
                                                   int nvec, int ncomp, long long ldx,
-                                                  const int32_t* __restrict__ zlist,
-                                                  const int32_t* __restrict__ vidx,
+                                                  const XRowWord* __restrict__ xrow,
                                                   const typename CT<T>::t* __restrict__ x,
                                                   typename CT<T>::t* __restrict__ At,
                                                   const typename CT<T>::t* __restrict__ tw) {
@@ -180,6 +179,9 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_xt(FftPlan pl, GeoT g
   const int w = t / TP, j0 = t % TP;
   const int ngy = (Ky + WX - 1) / WX;
   const int nitems = nvec * nzp * ngy;
+  const int nw = (Kx + 63) >> 6;  // occupancy words per row
+  // the word array ends with one zero word, the zero value of empty positions
+  const typename CT<T>::t* zero = reinterpret_cast<const typename CT<T>::t*>(xrow + (size_t)nzp * Ky * nw);
   const C* twl = lds_twiddles(lds + (size_t)WX * PP, tw, Lx);
   for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
     const int gy = item % ngy;
@@ -189,7 +191,7 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_xt(FftPlan pl, GeoT g
       const int y = gy * WX + jj;
       const bool ok = y < Ky;
       return XIn<C>{x + (size_t)(vec / ncomp) * ldx + (size_t)(vec % ncomp) * K,
-                    vidx + ((size_t)zlist[zp] * Ky + (ok ? y : 0)) * Kx, Kx, ok};
+                    make_xrow<false>(xrow, zp * Ky + (ok ? y : 0), nw, Kx, ok), zero};
     };
     fft_batch<P, C, -1, false, false>(pl, 1, WX, w, j0, mksrc, [](int) { return NoDst<C>{}; }, lds, PP, twl);
     C* col = At + (size_t)vz * gt.pq + gy * WX;
@@ -204,8 +206,7 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_xt(FftPlan pl, GeoT g
 // --------------------------------------------- Xi pass, transposed input --
 template <typename T, class P>
 __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_xit(FftPlan pl, GeoT gt, int WX, int Kx, int Ky, int nzp, int K,
-                                                   int nvec, EpiParams ep, const int32_t* __restrict__ zlist,
-                                                   const int32_t* __restrict__ vidx,
+                                                   int nvec, EpiParams ep, const XRowWord* __restrict__ xrow,
                                                    const typename CT<T>::t* __restrict__ Ot,
                                                    const typename CT<T>::t* __restrict__ x,
                                                    typename CT<T>::t* __restrict__ y,
@@ -221,6 +222,7 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_xit(FftPlan pl, GeoT 
   const int w = t / TP, j0 = t % TP;
   const int ngy = (Ky + WX - 1) / WX;
   const int nitems = nvec * nzp * ngy;
+  const int nw = (Kx + 63) >> 6;  // occupancy words per row
   const C* twl = lds_twiddles(lds + (size_t)WX * PP, tw, Lx);
   for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
     const int gy = item % ngy;
@@ -241,7 +243,7 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_xit(FftPlan pl, GeoT 
       const int yy = gy * WX + jj;
       const bool ok = yy < Ky;
       return XOut<C, T>{y + (size_t)rhs * ep.ldy + (size_t)comp * K, x + (size_t)rhs * ep.ldx + (size_t)comp * K, cd,
-                        vidx + ((size_t)zlist[zp] * Ky + (ok ? yy : 0)) * Kx, scale, mass, Kx, ok};
+                        make_xrow<false>(xrow, zp * Ky + (ok ? yy : 0), nw, Kx, ok), scale, mass};
     };
     fft_batch<P, C, +1, true, true>(pl, 1, WX, w, j0, [](int) { return NoDst<C>{}; }, mkdst, lds, PP, twl);
   }
@@ -459,7 +461,7 @@ hipError_t launch_matvec_chunk_fused(const svh_problem* p, int nvec, const EpiPa
     const size_t sh = (size_t)WX * pencil_pitch(Lx) * sizeof(C) + twiddle_bytes(Lx, sizeof(C));
     const int g = persistent_grid((const void*)k_pass_xt<T, P>, WX * tp, sh, nitems, p->ncu, tn.grid_mult[0]);
     hipLaunchKernelGGL((k_pass_xt<T, P>), dim3(g), dim3(WX * tp), sh, s, pl, gt, WX, Kx, Ky, nzp, K, nvec, ep.C,
-                       ep.ldx, p->d_zlist, p->d_vidx, x, At, tw[0]);
+                       ep.ldx, p->d_xrow, x, At, tw[0]);
   });
   if (ev) hipEventRecord(ev[1], s);
   {
@@ -510,7 +512,7 @@ hipError_t launch_matvec_chunk_fused(const svh_problem* p, int nvec, const EpiPa
     const C* sc = dbl ? reinterpret_cast<const C*>(p->d_sconv64) : reinterpret_cast<const C*>(p->d_sconv32);
     const C* cd = dbl ? reinterpret_cast<const C*>(p->d_cdiag64) : reinterpret_cast<const C*>(p->d_cdiag32);
     hipLaunchKernelGGL((k_pass_xit<T, P>), dim3(g), dim3(WX * tp), sh, s, pl, gt, WX, Kx, Ky, nzp, K, nvec, ep,
-                       p->d_zlist, p->d_vidx, Ot, x, y, sc, cd, inv_n, tw[0]);
+                       p->d_xrow, Ot, x, y, sc, cd, inv_n, tw[0]);
   });
   if (ev) hipEventRecord(ev[5], s);
   return hipGetLastError();

@@ -44,6 +44,16 @@ struct DevTucker {
   double* Fzd = nullptr; // [slot][c]: the same at the occupied plane offsets only
 };
 
+// Occupancy of 64 consecutive x positions of one grid row: bit b set when
+// voxel x = 64 w + b is non-empty; base = compact index of the first such
+// voxel.  Voxels are numbered z-, y-, x-major, so the voxel at bit b has the
+// compact index base + (set bits below b).
+struct alignas(16) XRowWord {
+  unsigned long long bits;
+  int base;
+  int pad;
+};
+
 // Per-call kernel parameters of the final (x-inverse) pass.
 struct EpiParams {
   int C;              // components per right-hand side
@@ -93,7 +103,8 @@ struct svh_problem {
   std::vector<int32_t> vidx;       // dense -> compact index or -1, [z][y][x]
   std::vector<int32_t> zlist;      // occupied z planes
   std::vector<int32_t> zslot;      // z -> plane slot or -1 (size L[2])
-  int32_t* d_vidx = nullptr;
+  svh::XRowWord* d_xrow = nullptr;      // [plane slot][y][x / 64] occupancy words of the occupied planes
+  int xrow_words = 0;              // words per row, ceil(Kx / 64)
   int32_t* d_zlist = nullptr;
   int32_t* d_zslot = nullptr;
   svh::FftPlan plan[3];
