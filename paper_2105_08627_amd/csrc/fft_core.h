@@ -388,11 +388,19 @@ struct PlanRT {
   __host__ __device__ static int tpof(const FftPlan& p) { return p.tp; }
 };
 
-template <class P, typename C, int DIR, bool STRIDED, class MkIn, class MkOut>
+// WAVE: every pencil belongs to one wavefront (its threads and its LDS
+// region), so the stages need only the wave's own ordering of its LDS
+// accesses instead of block barriers.
+template <class P, typename C, int DIR, bool STRIDED, bool WAVE, class MkIn, class MkOut>
 __device__ __forceinline__ void fft_items_c(int j0, int nitems, const MkIn& mk_in, const MkOut& mk_out,
                                             const Lds<C, STRIDED>& lds, const C* tw) {
   constexpr int L = P::L, TP = P::tp;
   constexpr int R0 = P::r(0);
+  constexpr int SM = WAVE ? 2 : 1;  // in-place stage: wave ordering or block barrier
+  auto sync = [] {
+    if constexpr (WAVE) wave_sync();
+    else __syncthreads();
+  };
   C v[12];
   int item = first_item();
   if (item < nitems) load0_r<C, R0>(L, j0, TP, mk_in(item), v);
@@ -403,34 +411,34 @@ __device__ __forceinline__ void fft_items_c(int j0, int nitems, const MkIn& mk_i
       if (next < nitems) load0_r<C, R0>(L, j0, TP, mk_in(next), v);
     } else {
       fin0_r<C, R0, DIR>(L, j0, TP, v, lds);
-      __syncthreads();
+      sync();
       if (next < nitems) load0_r<C, R0>(L, j0, TP, mk_in(next), v);
       constexpr int N1 = R0;
       if constexpr (P::ns == 2) {
-        stage_r<C, P::r(1), DIR, false>(L, N1, j0, TP, lds, mk_out(item), tw);
+        stage_r<C, P::r(1), DIR, 0>(L, N1, j0, TP, lds, mk_out(item), tw);
       } else {
-        stage_r<C, P::r(1), DIR, true>(L, N1, j0, TP, lds, lds, tw);
-        __syncthreads();
+        stage_r<C, P::r(1), DIR, SM>(L, N1, j0, TP, lds, lds, tw);
+        sync();
         constexpr int N2 = N1 * P::r(1);
         if constexpr (P::ns == 3) {
-          stage_r<C, P::r(2), DIR, false>(L, N2, j0, TP, lds, mk_out(item), tw);
+          stage_r<C, P::r(2), DIR, 0>(L, N2, j0, TP, lds, mk_out(item), tw);
         } else {
-          stage_r<C, P::r(2), DIR, true>(L, N2, j0, TP, lds, lds, tw);
-          __syncthreads();
+          stage_r<C, P::r(2), DIR, SM>(L, N2, j0, TP, lds, lds, tw);
+          sync();
           constexpr int N3 = N2 * P::r(2);
-          stage_r<C, P::r(3), DIR, false>(L, N3, j0, TP, lds, mk_out(item), tw);
+          stage_r<C, P::r(3), DIR, 0>(L, N3, j0, TP, lds, mk_out(item), tw);
         }
       }
-      __syncthreads();
+      sync();
     }
   }
 }
 
-template <class P, typename C, int DIR, bool STRIDED, class MkIn, class MkOut>
+template <class P, typename C, int DIR, bool STRIDED, bool WAVE = false, class MkIn, class MkOut>
 __device__ __forceinline__ void run_items(const FftPlan& pl, int j0, int nitems, const MkIn& mk_in,
                                           const MkOut& mk_out, const Lds<C, STRIDED>& lds, const C* tw) {
   if constexpr (P::rt) fft_items<C, DIR, STRIDED>(pl, j0, nitems, mk_in, mk_out, lds, tw);
-  else fft_items_c<P, C, DIR, STRIDED>(j0, nitems, mk_in, mk_out, lds, tw);
+  else fft_items_c<P, C, DIR, STRIDED, WAVE>(j0, nitems, mk_in, mk_out, lds, tw);
 }
 
 // Calls f(PlanC<...>{}) for the lengths with a compile-time plan, else f(PlanRT{}).
@@ -511,6 +519,13 @@ __device__ __forceinline__ XRow<UNI> make_xrow(const XRowWord* xrow, int row, in
 template <class P> constexpr bool uniform_rows() {
   if constexpr (P::rt) return false;
   else return P::tp % 64 == 0 && (P::L / P::r(0)) % 64 == 0 && (P::L / P::r(P::ns - 1)) % 64 == 0;
+}
+
+// Whether a compile-time plan runs each pencil of the x passes on exactly one
+// wavefront (64 threads per pencil).
+template <class P> constexpr bool wave_pencils() {
+  if constexpr (P::rt) return false;
+  else return P::tp == 64;
 }
 
 // Gather accessor of the forward x transform: compact vector -> x pencil.

@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(256) k_pass_x(FftPlan pl, Geo geo, int WX, int
   };
   Lds<C, false> acc{lds, WX, pencil_pitch(Lx), w};
   const C* twl = lds_twiddles(lds + (size_t)WX * pencil_pitch(Lx), tw, Lx);
-  run_items<P, C, -1, false>(pl, j0, ngrp * nvec, mk_in, mk_out, acc, twl);
+  run_items<P, C, -1, false, wave_pencils<P>()>(pl, j0, ngrp * nvec, mk_in, mk_out, acc, twl);
 }
 
 // ------------------------------------------------------------ Y passes ----
@@ -511,11 +511,13 @@ __global__ void __launch_bounds__(256) k_zdirect5(Geo geo, int Lx, int Ly, int n
 }
 
 // --------------------------------------------------------------- Xi pass --
-// FP32: at least four 256-thread blocks per CU (at most 128 VGPRs), four
-// waves per SIMD to cover the scatter's loads.
-template <typename T> struct XiMinBlocks { static constexpr int v = sizeof(T) == 4 ? 4 : 1; };
+// FP32 with one pencil per wavefront: at least four 256-thread blocks per CU
+// (at most 128 VGPRs), four waves per SIMD to cover the scatter's loads.
+template <typename T, class P> struct XiMinBlocks {
+  static constexpr int v = (sizeof(T) == 4 && wave_pencils<P>()) ? 4 : 1;
+};
 template <typename T, class P>
-__global__ void __launch_bounds__(256, XiMinBlocks<T>::v) k_pass_xi(FftPlan pl, Geo geo, int WX, int Kx, int Ky, int nzp, int K, int nvec,
+__global__ void __launch_bounds__(256, (XiMinBlocks<T, P>::v)) k_pass_xi(FftPlan pl, Geo geo, int WX, int Kx, int Ky, int nzp, int K, int nvec,
                                                   EpiParams ep, const XRowWord* __restrict__ xrow,
                                                   const typename CT<T>::t* __restrict__ A,
                                                   const typename CT<T>::t* __restrict__ x,
@@ -565,7 +567,7 @@ __global__ void __launch_bounds__(256, XiMinBlocks<T>::v) k_pass_xi(FftPlan pl, 
   };
   Lds<C, false> acc{lds, WX, pencil_pitch(Lx), w};
   const C* twl = lds_twiddles(lds + (size_t)WX * pencil_pitch(Lx), tw, Lx);
-  run_items<P, C, +1, false>(pl, j0, ngrp * nvec, mk_in, mk_out, acc, twl);
+  run_items<P, C, +1, false, wave_pencils<P>()>(pl, j0, ngrp * nvec, mk_in, mk_out, acc, twl);
 }
 
 // ------------------------------------------------------------- launcher ---
