@@ -202,6 +202,7 @@ svh_status svh_create(svh_problem** out, int Kx, int Ky, int Kz, double dx_m, in
     // the twiddles of the phase length Ly / phases
     p->fused_r[SVH_FP64] = fused_phases(p, sizeof(double2), sizeof(double));
     p->fused_r[SVH_FP32] = fused_phases(p, sizeof(float2), sizeof(float));
+    p->fused2_r = yzy2_phases(p);
     if (p->fused_r[0] > 0 && p->fused_r[1] > 0) {
       const int P64 = p->L[1] / p->fused_r[0], P32 = p->L[1] / p->fused_r[1];
       std::vector<double2> t64(P64);

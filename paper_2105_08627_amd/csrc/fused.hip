@@ -406,6 +406,172 @@ __global__ void __launch_bounds__(256) k_yzy(FftPlan pl, GeoT gt, int Lx, int Ky
   }
 }
 
+// ------------------------------------------- fused y/z/yi, resident kernel --
+// FP32 variant for 1024-thread blocks with 160 KiB of LDS: one kx column per
+// block with the z-space kernel values of all Ly bins resident (loaded once
+// per block, stored phase-major: [slot][q][m] for bin ky = r m + q), so only
+// the input and output columns of each vector cross HBM, once each.  With
+// r <= 2 phases of length Pn >= Ky no two input rows fold onto one bin row.
+// The input column stays in registers over the phases (the next vector's
+// column is loaded meanwhile); per phase the fold into LDS, the length-Pn
+// transforms of all planes, the z sum per bin, the inverse transforms and the
+// unfold into register accumulators.
+constexpr int kYzy2Threads = 1024;
+constexpr size_t kYzy2Lds = 160 * 1024;
+
+size_t yzy2_lds_bytes(const svh_problem* p, int r) {
+  const int Ly = p->L[1], Pn = Ly / r;
+  return (size_t)p->dzset.size() * Ly * sizeof(float) + p->zlist.size() * (size_t)pencil_pitch(Pn) * sizeof(float2) +
+         (size_t)(Pn + Ly) * sizeof(float2);
+}
+
+// Phase count for k_yzy2 (0: not applicable): r = Ly / Pn in {1, 2} with Pn
+// in {128, 256} (the instantiated transforms), Ky <= Pn, and the working set
+// within the LDS.
+int yzy2_phases(const svh_problem* p) {
+  if (p->C != 3 || p->zlist.size() > (size_t)kMaxDirectPlanes || p->dzset.empty() ||
+      p->dzset.size() > (size_t)kMaxDz5)
+    return 0;
+  const int Ly = p->L[1], Ky = p->K[1];
+  for (int r = 1; r <= 2; ++r) {
+    if (Ly % r) continue;
+    const int Pn = Ly / r;
+    if ((Pn != 128 && Pn != 256) || Ky > Pn) continue;
+    if (yzy2_lds_bytes(p, r) <= kYzy2Lds) return r;
+  }
+  return 0;
+}
+
+template <class P, int NZ>
+__global__ void __launch_bounds__(1024) k_yzy2(GeoT gt, int Lx, int Ky, int Ly, int r, int nzp, int nd, int nvec,
+                                               const uint32_t* __restrict__ qtab, const float* __restrict__ g,
+                                               const float2* __restrict__ in, float2* __restrict__ out,
+                                               const float2* __restrict__ twy) {
+  typedef float2 C;
+  constexpr int NT = kYzy2Threads;
+  constexpr int Pn = P::L, TP = P::tp, PP = pencil_pitch(Pn);
+  constexpr int TPB = NT / Pn;                 // threads per bin in the z sum
+  constexpr int RS = (NZ + TPB - 1) / TPB;     // rows per thread in the z sum
+  constexpr int KM = (NZ * Pn + NT - 1) / NT;  // owned input elements (Ky <= Pn)
+  constexpr int NW = (NZ + 3) / 4;             // code words per row
+  extern __shared__ unsigned char smem_raw[];
+  float* gs = reinterpret_cast<float*>(smem_raw);          // [slot][q][m]
+  C* work = reinterpret_cast<C*>(gs + (size_t)nd * Ly);    // [plane][PP]
+  C* tpl = work + (size_t)nzp * PP;                        // e^(-2 pi i m / Pn)
+  C* tyl = tpl + Pn;                                       // e^(-2 pi i n / Ly)
+  const int t = threadIdx.x;
+  const int kx = blockIdx.x;
+  for (int e = t; e < nd * Ly; e += NT) {
+    const int sl = e / Ly, ky = e - sl * Ly;
+    gs[(sl * r + ky % r) * Pn + ky / r] = g[((size_t)sl * Lx + kx) * Ly + ky];
+  }
+  for (int e = t; e < Pn; e += NT) tpl[e] = twy[e * r];
+  for (int e = t; e < Ly; e += NT) tyl[e] = twy[e];
+  // owned input elements e = t + NT k: plane j = e / Ky, row n = e % Ky
+  const int nel = nzp * Ky;
+  int jn[KM];  // j << 16 | n, or -1
+#pragma unroll
+  for (int k = 0; k < KM; ++k) {
+    const int e = t + NT * k;
+    jn[k] = e < nel ? ((e / Ky) << 16) | (e % Ky) : -1;
+  }
+  // transform roles: pencil w (one plane), lanes of a pencil within a wave
+  constexpr int G = NT / TP;
+  const int w = t / TP;
+  const int j0 = w < nzp ? t % TP : (1 << 20);  // threads of absent planes take no butterfly
+  // z-sum roles: bin m, rows i0 + TPB s (i0 is the same on the whole wave);
+  // the offset-slot codes of the rows, four per word (zero past nzp)
+  const int m = t % Pn;
+  const int i0 = __builtin_amdgcn_readfirstlane(t / Pn);
+  const int mo = m + (m >> 3);
+  auto nodst = [](int) { return NoDst<C>{}; };
+  C xn[KM];
+  auto fetch = [&](int vec) {
+    const C* col = in + (size_t)vec * nzp * gt.pq + (size_t)kx * gt.cp;
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+      xn[k] = jn[k] >= 0 ? col[(size_t)(jn[k] >> 16) * gt.pq + (jn[k] & 0xffff)] : C{0, 0};
+  };
+  if (nvec > 0) fetch(0);
+  for (int vec = 0; vec < nvec; ++vec) {
+    C xc[KM], acc[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      xc[k] = xn[k];
+      acc[k] = C{0, 0};
+    }
+    if (vec + 1 < nvec) fetch(vec + 1);
+    for (int q = 0; q < r; ++q) {
+      __syncthreads();  // the previous phase is done with work (first pass: tables loaded)
+      // fold: work[j][n] = x[j][n] w^(q n) for n < Ky, zero up to Pn
+      for (int e = t; e < nzp * (Pn - Ky); e += NT) {
+        const int j = e / (Pn - Ky), np = Ky + e % (Pn - Ky);
+        work[j * PP + np + (np >> 3)] = C{0, 0};
+      }
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        if (jn[k] < 0) continue;
+        const int j = jn[k] >> 16, n = jn[k] & 0xffff;
+        work[j * PP + n + (n >> 3)] = q ? cmul(xc[k], tyl[(q * n) % Ly]) : xc[k];
+      }
+      __syncthreads();
+      stages_c<P, 0, C, -1, true, false, true>(1, G, w, j0, nodst, nodst, work, PP, tpl);
+      // z sum of bin ky = r m + q: y[i] = sum_j g(slot(i, j)) x[j]
+      C yr[RS];
+#pragma unroll
+      for (int s = 0; s < RS; ++s) yr[s] = C{0, 0};
+      const float* gq = gs + (size_t)q * Pn + m;
+      const int rPn = r * Pn;
+      // planes in groups of four: the rows' code words of the group (scalar
+      // loads), then the group's plane values and kernel values (LDS)
+#pragma unroll 1
+      for (int j4 = 0; j4 < NW; ++j4) {
+        uint32_t cw[RS];
+#pragma unroll
+        for (int s = 0; s < RS; ++s) cw[s] = qtab[(i0 + TPB * s) * 8 + j4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int j = 4 * j4 + b;
+          C xj = work[(j < nzp ? j : 0) * PP + mo];
+          if (j >= nzp) xj = C{0, 0};
+#pragma unroll
+          for (int s = 0; s < RS; ++s) {
+            const uint32_t code = (cw[s] >> (8 * b)) & 0x7fu;
+            const float gv = gq[code * rPn];
+            yr[s].x += gv * xj.x;
+            yr[s].y += gv * xj.y;
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < RS; ++s) {
+        const int i = i0 + TPB * s;
+        if (i < nzp) work[i * PP + mo] = yr[s];
+      }
+      __syncthreads();
+      stages_c<P, 0, C, +1, true, false, true>(1, G, w, j0, nodst, nodst, work, PP, tpl);
+      // unfold: this phase's share w^(-q n) x (length-Pn inverse transform at n)
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        if (jn[k] < 0) continue;
+        const int j = jn[k] >> 16, n = jn[k] & 0xffff;
+        C v = work[j * PP + n + (n >> 3)];
+        if (q) {
+          C tq = tyl[(q * n) % Ly];
+          tq.y = -tq.y;
+          v = cmul(v, tq);
+        }
+        acc[k] = cadd(acc[k], v);
+      }
+    }
+    C* oc = out + (size_t)vec * nzp * gt.pq + (size_t)kx * gt.cp;
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+      if (jn[k] >= 0) oc[(size_t)(jn[k] >> 16) * gt.pq + (jn[k] & 0xffff)] = acc[k];
+  }
+}
+
 // ------------------------------------------------------------ launcher ----
 static int rows_per_block_xt(int tp, int Lx, size_t cs) {
   // contiguous runs of 128 bytes when the block (1024 threads FP32, 512 FP64)
@@ -464,7 +630,37 @@ hipError_t launch_matvec_chunk_fused(const svh_problem* p, int nvec, const EpiPa
                        ep.ldx, p->d_xrow, x, At, tw[0]);
   });
   if (ev) hipEventRecord(ev[1], s);
-  {
+  if constexpr (sizeof(T) == 4) {
+    if (p->fused2_r > 0) {
+      const int r2 = p->fused2_r, P2 = Ly / r2;
+      const size_t sh = yzy2_lds_bytes(p, r2);
+      const uint32_t* qt = reinterpret_cast<const uint32_t*>(p->d_qtab);
+      const float* gg = static_cast<const float*>(gk);
+      const int NZ = nzp <= 8 ? 8 : nzp <= 16 ? 16 : nzp <= 24 ? 24 : 32;
+      with_plan(P2, [&](auto tag) {
+        using P = decltype(tag);
+        if constexpr (!P::rt) {
+          if constexpr (P::L == 128 || P::L == 256) {
+            auto go = [&](auto nzt) {
+              constexpr int NZc = decltype(nzt)::value;
+              auto kern = k_yzy2<P, NZc>;
+              hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+              hipLaunchKernelGGL(kern, dim3(Lx), dim3(kYzy2Threads), sh, s, gt, Lx, Ky, Ly, r2, nzp, nd, nvec, qt, gg,
+                                 reinterpret_cast<const float2*>(At), reinterpret_cast<float2*>(Ot),
+                                 reinterpret_cast<const float2*>(tw[1]));
+            };
+            switch (NZ) {
+              case 8: go(std::integral_constant<int, 8>{}); break;
+              case 16: go(std::integral_constant<int, 16>{}); break;
+              case 24: go(std::integral_constant<int, 24>{}); break;
+              default: go(std::integral_constant<int, 32>{}); break;
+            }
+          }
+        }
+      });
+    }
+  }
+  if (sizeof(T) == 8 || p->fused2_r <= 0) {
     FftPlan pp;
     make_plan(Pn, pp);
     with_plan(Pn, [&](auto tag) {

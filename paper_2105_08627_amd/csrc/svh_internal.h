@@ -139,6 +139,7 @@ struct svh_problem {
   double* d_gt64 = nullptr;
   float* d_gt32 = nullptr;
   int fused_r[2] = {0, 0};
+  int fused2_r = 0;  // phases of the resident-kernel fused step (FP32), 0: not applicable
   bool auto_fused[2] = {false, false};  // AUTO mode: the autotuner timed FUSED faster
   double2* d_twp64 = nullptr;
   float2* d_twp32 = nullptr;
@@ -207,6 +208,7 @@ hipError_t launch_tucker_box(int n1, int n2, int n3, const DevTucker& t, const d
 hipError_t launch_gather_transposed(const svh_problem* p, const double* d_in, double* d_out, hipStream_t s);
 GeoT make_geo_t(const svh_problem* p, size_t csize);
 int fused_phases(const svh_problem* p, size_t cs, size_t ts);
+int yzy2_phases(const svh_problem* p);
 bool fused_eligible(const svh_problem* p);
 bool use_fused(const svh_problem* p, svh_prec prec);
 // The first nfam (1 or 7) family tables [f][Kz][Ky][Kx] on the device by
