@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_NAMES_FP32 = {
     "pass_x": "svh::k_pass_x<float, svh::PlanC<8, 8, 8, 1> >",
     "pass_y": "svh::k_pass_y<float, -1, svh::PlanC<8, 8, 8, 1> >",
-    "pass_z_mul": "svh::k_zdirect<float, 24, 8, 4>",
+    "pass_z_mul": "svh::k_zdirect<float, 24, 8, 4, 512>",
     "pass_yi": "svh::k_pass_y<float, 1, svh::PlanC<8, 8, 8, 1> >",
     "pass_xi": "svh::k_pass_xi<float, svh::PlanC<8, 8, 8, 1> >",
 }

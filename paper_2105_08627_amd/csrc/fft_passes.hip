@@ -277,17 +277,17 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_z(FftPlan pl, FftPlan
 // circulant spectrum (real and even in the offset because the spectrum is
 // real and even).  Exact for any plane set; used when few planes are occupied
 // (the padded z FFT then spends almost all of its work on zeros).
-// Block: W adjacent kx of one ky, RG row groups (W * RG = 256 threads).
+// Block: W adjacent kx of one ky, RG row groups (W * RG = NT threads).
 // Thread (w, rg) keeps rows rg, rg + RG, ... of its pencil's nzp x nzp matrix
 // in registers for all vectors; each chunk of V vectors is staged through
 // LDS with 128/256-byte coalesced loads and updated in place.
-template <typename T, int NZ, int RG, int V>
-__global__ void __launch_bounds__(256) k_zdirect(Geo geo, int Lx, int Ly, int nzp, int nvec, int vpb,
+template <typename T, int NZ, int RG, int V, int NT>
+__global__ void __launch_bounds__(NT) k_zdirect(Geo geo, int Lx, int Ly, int nzp, int nvec, int vpb,
                                                  const int32_t* __restrict__ zlist,
                                                  const T* __restrict__ g,
                                                  typename CT<T>::t* __restrict__ B) {
   typedef typename CT<T>::t C;
-  constexpr int W = 256 / RG;
+  constexpr int W = NT / RG;
   constexpr int R = (NZ + RG - 1) / RG;
   extern __shared__ unsigned char smem_raw[];
   C* xs = reinterpret_cast<C*>(smem_raw);                    // [V][NZ][W]
@@ -297,7 +297,7 @@ __global__ void __launch_bounds__(256) k_zdirect(Geo geo, int Lx, int Ly, int nz
   const int bid = first_item();  // XCD-aware order of the (tile, ky) blocks
   const int tile = bid % ntile, ky = bid / ntile;
   const int kx0 = tile * W;
-  for (int i = t; i < NZ; i += 256) zl[i] = i < nzp ? zlist[i] : 0;
+  for (int i = t; i < NZ; i += NT) zl[i] = i < nzp ? zlist[i] : 0;
   __syncthreads();
   const int w = t % W, rg = t / W;
   const int kx = kx0 + w;
@@ -319,14 +319,14 @@ __global__ void __launch_bounds__(256) k_zdirect(Geo geo, int Lx, int Ly, int nz
   const int vbeg = blockIdx.y * vpb;
   const int vend = min(nvec, vbeg + vpb);
   // staged element e of a chunk: ww = e % W, j = (e / W) % NZ, v = e / (W NZ);
-  // thread t stages e = t + 256 q, q < EPT
-  constexpr int EPT = (V * NZ * W + 255) / 256;
+  // thread t stages e = t + NT q, q < EPT
+  constexpr int EPT = (V * NZ * W + NT - 1) / NT;
   C pre[EPT];
   auto fetch = [&](int v0) {
     const int nv = min(V, vend - v0);
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
-      const int e = t + 256 * q;
+      const int e = t + NT * q;
       const int ww = e % W, j = (e / W) % NZ, v = e / (W * NZ);
       pre[q] = (v < nv && j < nzp && kx0 + ww < Lx) ? base[((size_t)(v0 + v) * nzp + j) * plane + ww] : C{0, 0};
     }
@@ -337,7 +337,7 @@ __global__ void __launch_bounds__(256) k_zdirect(Geo geo, int Lx, int Ly, int nz
     __syncthreads();  // previous chunk's readers are done with xs
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
-      const int e = t + 256 * q;
+      const int e = t + NT * q;
       if (e < V * NZ * W) xs[e] = pre[q];
     }
     __syncthreads();
@@ -679,9 +679,11 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
       default: go(I32{}, RGmax{}); break;
     }
   } else if (zdirect) {
-    // double: 16 pencils x 16 row groups; float: 32 pencils x 8 row groups
+    // 512 threads: double 32 pencils x 16 row groups, float 64 pencils x 8
+    // row groups (512-byte runs of each plane row)
+    constexpr int NT = 512;
     constexpr int RG = sizeof(T) == 8 ? 16 : 8;
-    constexpr int W = 256 / RG;
+    constexpr int W = NT / RG;
     constexpr int V = 4;
     const int ntile = (Lx + W - 1) / W;
     const int nblk = ntile * Ly;
@@ -692,13 +694,13 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const size_t sh = (size_t)V * NZ * W * sizeof(C) + (size_t)NZ * sizeof(int);
     const T* gk = static_cast<const T*>(zhat);
     switch (NZ) {
-      case 8: hipLaunchKernelGGL((k_zdirect<T, 8, RG, V>), grid, dim3(256), sh, s, geo, Lx, Ly, nzp, nvec, vpb,
+      case 8: hipLaunchKernelGGL((k_zdirect<T, 8, RG, V, NT>), grid, dim3(NT), sh, s, geo, Lx, Ly, nzp, nvec, vpb,
                                  p->d_zlist, gk, B); break;
-      case 16: hipLaunchKernelGGL((k_zdirect<T, 16, RG, V>), grid, dim3(256), sh, s, geo, Lx, Ly, nzp, nvec, vpb,
+      case 16: hipLaunchKernelGGL((k_zdirect<T, 16, RG, V, NT>), grid, dim3(NT), sh, s, geo, Lx, Ly, nzp, nvec, vpb,
                                   p->d_zlist, gk, B); break;
-      case 24: hipLaunchKernelGGL((k_zdirect<T, 24, RG, V>), grid, dim3(256), sh, s, geo, Lx, Ly, nzp, nvec, vpb,
+      case 24: hipLaunchKernelGGL((k_zdirect<T, 24, RG, V, NT>), grid, dim3(NT), sh, s, geo, Lx, Ly, nzp, nvec, vpb,
                                   p->d_zlist, gk, B); break;
-      default: hipLaunchKernelGGL((k_zdirect<T, 32, RG, V>), grid, dim3(256), sh, s, geo, Lx, Ly, nzp, nvec, vpb,
+      default: hipLaunchKernelGGL((k_zdirect<T, 32, RG, V, NT>), grid, dim3(NT), sh, s, geo, Lx, Ly, nzp, nvec, vpb,
                                   p->d_zlist, gk, B); break;
     }
   } else {
