@@ -174,12 +174,35 @@ __device__ __forceinline__ void stage_r(int L, int Ns, int j0, int TP, const Src
     }
   }
   C v[NB][R];
+  if constexpr (IsGather<Src>::value) {
+    // gather source (first stage of a transform): all row words, then all
+    // indices, then all value loads
+    int4 wg[NB][R];
 #pragma unroll
-  for (int it = 0; it < NB; ++it) {
-    const int j = j0 + it * TP;
-    if (j < LR) {
+    for (int it = 0; it < NB; ++it) {
+      const int j = j0 + it * TP;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[it][r] = src.ld(j + r * LR);
+      for (int r = 0; r < R; ++r) {
+        if constexpr (Src::kUniform)
+          wg[it][r] = src.row.word_u(__builtin_amdgcn_readfirstlane(j0 >> 6) + ((it * TP + r * LR) >> 6));
+        else
+          wg[it][r] = src.row.word(j < LR ? j + r * LR : 0);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < NB; ++it) {
+      const int j = j0 + it * TP;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[it][r] = src.at(j < LR ? src.row.index(j + r * LR, wg[it][r]) : -1);
+    }
+  } else {
+#pragma unroll
+    for (int it = 0; it < NB; ++it) {
+      const int j = j0 + it * TP;
+      if (j < LR) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[it][r] = src.ld(j + r * LR);
+      }
     }
   }
   if constexpr (SC) {

@@ -180,6 +180,8 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_xt(FftPlan pl, GeoT g
   const int ngy = (Ky + WX - 1) / WX;
   const int nitems = nvec * nzp * ngy;
   const int nw = (Kx + 63) >> 6;  // occupancy words per row
+  // one pencil (grid row) per wavefront: row words through the scalar cache
+  constexpr bool UNI = wave_pencils<P>() && uniform_rows<P>();
   // the word array ends with one zero word, the zero value of empty positions
   const typename CT<T>::t* zero = reinterpret_cast<const typename CT<T>::t*>(xrow + (size_t)nzp * Ky * nw);
   const C* twl = lds_twiddles(lds + (size_t)WX * PP, tw, Lx);
@@ -190,8 +192,8 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_xt(FftPlan pl, GeoT g
     auto mksrc = [&](int jj) {
       const int y = gy * WX + jj;
       const bool ok = y < Ky;
-      return XIn<C>{x + (size_t)(vec / ncomp) * ldx + (size_t)(vec % ncomp) * K,
-                    make_xrow<false>(xrow, zp * Ky + (ok ? y : 0), nw, Kx, ok), zero};
+      return XIn<C, UNI>{x + (size_t)(vec / ncomp) * ldx + (size_t)(vec % ncomp) * K,
+                         make_xrow<UNI>(xrow, zp * Ky + (ok ? y : 0), nw, Kx, ok), zero};
     };
     fft_batch<P, C, -1, false, false>(pl, 1, WX, w, j0, mksrc, [](int) { return NoDst<C>{}; }, lds, PP, twl);
     C* col = At + (size_t)vz * gt.pq + gy * WX;
@@ -223,6 +225,8 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_xit(FftPlan pl, GeoT 
   const int ngy = (Ky + WX - 1) / WX;
   const int nitems = nvec * nzp * ngy;
   const int nw = (Kx + 63) >> 6;  // occupancy words per row
+  // one pencil (grid row) per wavefront: row words through the scalar cache
+  constexpr bool UNI = wave_pencils<P>() && uniform_rows<P>();
   const C* twl = lds_twiddles(lds + (size_t)WX * PP, tw, Lx);
   for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
     const int gy = item % ngy;
@@ -242,8 +246,8 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_xit(FftPlan pl, GeoT 
     auto mkdst = [&](int jj) {
       const int yy = gy * WX + jj;
       const bool ok = yy < Ky;
-      return XOut<C, T>{y + (size_t)rhs * ep.ldy + (size_t)comp * K, x + (size_t)rhs * ep.ldx + (size_t)comp * K, cd,
-                        make_xrow<false>(xrow, zp * Ky + (ok ? yy : 0), nw, Kx, ok), scale, mass};
+      return XOut<C, T, UNI>{y + (size_t)rhs * ep.ldy + (size_t)comp * K, x + (size_t)rhs * ep.ldx + (size_t)comp * K,
+                             cd, make_xrow<UNI>(xrow, zp * Ky + (ok ? yy : 0), nw, Kx, ok), scale, mass};
     };
     fft_batch<P, C, +1, true, true>(pl, 1, WX, w, j0, [](int) { return NoDst<C>{}; }, mkdst, lds, PP, twl);
   }
