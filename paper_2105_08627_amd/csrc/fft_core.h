@@ -18,6 +18,31 @@ template <typename T> struct CT;
 template <> struct CT<double> { typedef double2 t; };
 template <> struct CT<float> { typedef float2 t; };
 
+// Store of an intermediate that the next pass streams back in: nontemporal
+// (no reuse expected in the caches before then).
+__device__ __forceinline__ void st_stream(float2* p, float2 v) {
+  typedef float __attribute__((ext_vector_type(2))) f2;
+  const f2 t = {v.x, v.y};
+  __builtin_nontemporal_store(t, reinterpret_cast<f2*>(p));
+}
+__device__ __forceinline__ void st_stream(double2* p, double2 v) {
+  typedef double __attribute__((ext_vector_type(2))) d2;
+  const d2 t = {v.x, v.y};
+  __builtin_nontemporal_store(t, reinterpret_cast<d2*>(p));
+}
+
+// Load of an intermediate that is read once (nontemporal).
+__device__ __forceinline__ float2 ld_stream(const float2* p) {
+  typedef float __attribute__((ext_vector_type(2))) f2;
+  const f2 t = __builtin_nontemporal_load(reinterpret_cast<const f2*>(p));
+  return float2{t.x, t.y};
+}
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+  typedef double __attribute__((ext_vector_type(2))) d2;
+  const d2 t = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p));
+  return double2{t.x, t.y};
+}
+
 template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
 template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
 template <typename C> __device__ __forceinline__ C cmul(C a, C b) {

@@ -24,7 +24,7 @@ template <typename C> struct RowOut {
   int lim;
   bool valid;
   __device__ __forceinline__ void st(int n, C v) const {
-    if (valid && n < lim) row[n] = v;
+    if (valid && n < lim) st_stream(row + n, v);
   }
 };
 
@@ -80,7 +80,7 @@ template <typename C> struct ColIn {
   int stride, lim;
   bool valid;
   __device__ __forceinline__ C ld(int n) const {
-    return (valid && n < lim) ? base[(size_t)n * stride] : C{0, 0};
+    return (valid && n < lim) ? ld_stream(base + (size_t)n * stride) : C{0, 0};
   }
 };
 template <typename C> struct ColOut {
@@ -88,7 +88,7 @@ template <typename C> struct ColOut {
   int stride, lim;
   bool valid;
   __device__ __forceinline__ void st(int n, C v) const {
-    if (valid && n < lim) base[(size_t)n * stride] = v;
+    if (valid && n < lim) st_stream(base + (size_t)n * stride, v);
   }
 };
 
@@ -328,7 +328,8 @@ __global__ void __launch_bounds__(NT) k_zdirect(Geo geo, int Lx, int Ly, int nzp
     for (int q = 0; q < EPT; ++q) {
       const int e = t + NT * q;
       const int ww = e % W, j = (e / W) % NZ, v = e / (W * NZ);
-      pre[q] = (v < nv && j < nzp && kx0 + ww < Lx) ? base[((size_t)(v0 + v) * nzp + j) * plane + ww] : C{0, 0};
+      pre[q] = (v < nv && j < nzp && kx0 + ww < Lx) ? ld_stream(base + ((size_t)(v0 + v) * nzp + j) * plane + ww)
+                                                   : C{0, 0};
     }
   };
   if (vbeg < vend) fetch(vbeg);
@@ -359,7 +360,7 @@ __global__ void __launch_bounds__(NT) k_zdirect(Geo geo, int Lx, int Ly, int nzp
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int i = rg + r * RG;
-        if (i < nzp && valid) base[((size_t)(v0 + v) * nzp + i) * plane + w] = C{ar[r], ai[r]};
+        if (i < nzp && valid) st_stream(base + ((size_t)(v0 + v) * nzp + i) * plane + w, C{ar[r], ai[r]});
       }
     }
   }
