@@ -434,7 +434,7 @@ __global__ void __launch_bounds__(256) k_zdirect5(Geo geo, int Lx, int Ly, int n
     for (int q = 0; q < EPT; ++q) {
       const int e = t + 256 * q;
       const int ww = e % W, j = (e / W) % NZ, c = e / (W * NZ);
-      pre[q] = (e < NE && j < nzp && kx0 + ww < Lx) ? base[((size_t)(rhs * 5 + c) * nzp + j) * plane + ww]
+      pre[q] = (e < NE && j < nzp && kx0 + ww < Lx) ? ld_stream(base + ((size_t)(rhs * 5 + c) * nzp + j) * plane + ww)
                                                    : C{0, 0};
     }
   };
@@ -502,11 +502,11 @@ __global__ void __launch_bounds__(256) k_zdirect5(Geo geo, int Lx, int Ly, int n
                      -(a[8] + a[12]) + 2 * a[17] + a[19] - a[21] + 4 * a[23]};
       C* o = base + ((size_t)(rhs * 5) * nzp + i) * plane + w;
       const size_t cs = (size_t)nzp * plane;
-      o[0] = yx;
-      o[cs] = yy;
-      o[2 * cs] = yz;
-      o[3 * cs] = y2;
-      o[4 * cs] = y3;
+      st_stream(o, yx);
+      st_stream(o + cs, yy);
+      st_stream(o + 2 * cs, yz);
+      st_stream(o + 3 * cs, y2);
+      st_stream(o + 4 * cs, y3);
     }
   }
 }
