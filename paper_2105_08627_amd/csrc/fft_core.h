@@ -234,7 +234,12 @@ __device__ __forceinline__ void stage_r(int L, int Ns, int j0, int TP, const Src
 #pragma unroll
     for (int it = 0; it < NB; ++it)
 #pragma unroll
-      for (int r = 0; r < R; ++r) dg[it][r] = dst.diag(kk[it][r]);
+      for (int r = 0; r < R; ++r) {
+        // last stage (n = j + r Ns): outputs r Ns + (it TP ..) wholly past Kx
+        // (a uniform branch) are not stored, so they need no operands
+        if (Ns * R == L && r * Ns + it * TP >= dst.row.Kx) dg[it][r] = DiagPair<C>{C{0, 0}, C{0, 0}};
+        else dg[it][r] = dst.diag(kk[it][r]);
+      }
   }
   if constexpr (SYNC_MID == 1) __syncthreads();
   if constexpr (SYNC_MID == 2) wave_sync();
@@ -313,7 +318,9 @@ __device__ __forceinline__ void load0_r(int L, int j0, int TP, const Src& src, C
 #pragma unroll
       for (int it = 0; it < NB; ++it)
 #pragma unroll
-        for (int r = 0; r < R; ++r) wd[it * R + r] = src.row.word_u(wq + ((it * TP + r * LR) >> 6));
+        for (int r = 0; r < R; ++r)
+          wd[it * R + r] = r * LR + it * TP >= src.row.Kx ? int4{0, 0, 0, 0}
+                                                          : src.row.word_u(wq + ((it * TP + r * LR) >> 6));
     } else {
 #pragma unroll
       for (int it = 0; it < NB; ++it) {
@@ -330,7 +337,14 @@ __device__ __forceinline__ void load0_r(int L, int j0, int TP, const Src& src, C
       for (int r = 0; r < R; ++r) k[it * R + r] = j < LR ? src.row.index(j + r * LR, wd[it * R + r]) : -1;
     }
 #pragma unroll
-    for (int q = 0; q < NB * R; ++q) v[q] = src.at(k[q]);
+    for (int it = 0; it < NB; ++it)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        // rows r LR + (it TP ..) wholly in the zero padding (past Kx on every
+        // lane: a uniform branch) load nothing
+        if (r * LR + it * TP >= src.row.Kx) v[it * R + r] = C{0, 0};
+        else v[it * R + r] = src.at(k[it * R + r]);
+      }
   } else {
 #pragma unroll
     for (int it = 0; it < NB; ++it) {
