@@ -218,6 +218,21 @@ def test_fused_step_multi_chunk_and_single_plane(dev):
     assert np.all(_relerr(_run(q, xf, [0, -1], dev, torch.complex64), reff) <= 1e-5)
 
 
+@pytest.mark.parametrize("kx", [256, 250])
+def test_x_transform_512(dev, kx):
+    """Grids whose x transform has 512 points (Kx = 256, and Kx = 250 with a
+    row word that straddles Kx): one wavefront per x pencil, row words through
+    the scalar cache, padding rows skipped; against the oracle in FP64 and FP32."""
+    mask = wl.random_mask(81 + kx, kx, 5, 3, fill=0.5)
+    dx = 0.25e-6
+    p = _problem(mask, dx)
+    x = wl.random_currents(82, (3, 3, p.K))
+    fidx = [0, 1, -1]
+    ref = _oracle(mask, dx, x, fidx)
+    assert np.all(_relerr(_run(p, x, fidx, dev, torch.complex128), ref) <= 1e-12)
+    assert np.all(_relerr(_run(p, x, fidx, dev, torch.complex64), ref) <= 1e-5)
+
+
 def test_fused_two_phase_fp32(dev):
     """FP32 fused step on a grid whose y transform has 512 points (Ky = 256):
     two frequency phases of 256 bins each in the resident-kernel variant, with

@@ -100,6 +100,7 @@ MV_CASES = [
     ((1, 6, 5), None, 1.0, 25),        # one voxel wide in x: M1x vanishes
     ((5, 4, 30), 24, 0.5, 26),         # 24 irregular planes, 24 x 24 block per pencil
     ((4, 4, 40), 32, 0.5, 27),         # 32 planes (largest direct z step)
+    ((250, 3, 2), None, 0.3, 28),      # L = (512, 6, 4): one wavefront per x pencil
 ]
 
 
