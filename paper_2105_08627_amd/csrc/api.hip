@@ -704,7 +704,10 @@ svh_status matvec_impl(svh_problem* p, svh_prec prec, int nrhs, const int32_t* f
     double* Wt = V + (size_t)p->L[0] * p->tk.d[1] * p->tk.d[2];
     if (reinterpret_cast<char*>(Wt + (size_t)p->L[0] * p->L[1] * p->tk.d[2]) > w + ws_bytes)
       return fail(p, SVH_EINVAL, "matvec: workspace too small");
-    HIPCHK(launch_tucker_rebuild(p, !dbl, zdirect, zb, V, Wt, s));
+    if (zdirect && p->d_qtab)  // only the distinct plane offsets, indexed by slot
+      HIPCHK(launch_tucker_rebuild_rows(p, p->tk, p->tk.Fzd, (int)p->dzset.size(), !dbl, zb, V, Wt, s));
+    else
+      HIPCHK(launch_tucker_rebuild(p, !dbl, zdirect, zb, V, Wt, s));
     zhat = zb;
   } else if (!zhat) {
     return fail(p, SVH_ESTATE, "matvec: no spectrum");
@@ -726,6 +729,7 @@ svh_status matvec_impl(svh_problem* p, svh_prec prec, int nrhs, const int32_t* f
     ep.vec0 = 0;
     ep.ldx = ldx;
     ep.ldy = ldy;
+    ep.zslot = p->C == 3 && p->tucker && zdirect && p->d_qtab != nullptr;
     for (int i = 0; i < kMaxVecsPerChunk; ++i) ep.fidx[i] = -1;
     for (int i = 0; i < nr; ++i) ep.fidx[i] = freq_idx[r0 + i];
     const char* xc = xb + (size_t)r0 * ldx * cs;

@@ -278,12 +278,14 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_z(FftPlan pl, FftPlan
 // real and even).  Exact for any plane set; used when few planes are occupied
 // (the padded z FFT then spends almost all of its work on zeros).
 // Block: W adjacent kx of one ky, RG row groups (W * RG = NT threads).
+// g rows: plane offsets dz < Kz, or (qslot given) the distinct offsets only.
 // Thread (w, rg) keeps rows rg, rg + RG, ... of its pencil's nzp x nzp matrix
 // in registers for all vectors; each chunk of V vectors is staged through
 // LDS with 128/256-byte coalesced loads and updated in place.
 template <typename T, int NZ, int RG, int V, int NT>
 __global__ void __launch_bounds__(NT) k_zdirect(Geo geo, int Lx, int Ly, int nzp, int nvec, int vpb,
                                                  const int32_t* __restrict__ zlist,
+                                                 const uint8_t* __restrict__ qslot,
                                                  const T* __restrict__ g,
                                                  typename CT<T>::t* __restrict__ B) {
   typedef typename CT<T>::t C;
@@ -297,7 +299,10 @@ __global__ void __launch_bounds__(NT) k_zdirect(Geo geo, int Lx, int Ly, int nzp
   const int bid = first_item();  // XCD-aware order of the (tile, ky) blocks
   const int tile = bid % ntile, ky = bid / ntile;
   const int kx0 = tile * W;
+  uint8_t* qs = reinterpret_cast<uint8_t*>(zl + NZ);       // [NZ][NZ] slot codes (qslot given)
   for (int i = t; i < NZ; i += NT) zl[i] = i < nzp ? zlist[i] : 0;
+  if (qslot)
+    for (int e = t; e < NZ * NZ; e += NT) qs[e] = qslot[(e / NZ) * 32 + e % NZ];
   __syncthreads();
   const int w = t % W, rg = t / W;
   const int kx = kx0 + w;
@@ -309,8 +314,11 @@ __global__ void __launch_bounds__(NT) k_zdirect(Geo geo, int Lx, int Ly, int nzp
     const int i = rg + r * RG;
 #pragma unroll
     for (int j = 0; j < NZ; ++j) {
+      // row of g: the plane offset |z_i - z_j|, or its slot among the
+      // distinct offsets when g holds only those (qslot, 32 x 32 codes)
       int d = zl[i < NZ ? i : 0] - zl[j];
       d = d < 0 ? -d : d;
+      if (qslot && i < nzp && j < nzp) d = qs[i * NZ + j] & 0x7f;
       m[r][j] = (valid && i < nzp && j < nzp) ? g[((size_t)d * Ly + ky) * Lx + kx] : (T)0;
     }
   }
@@ -692,17 +700,17 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     while (vpb > V && (long long)nblk * ((nvec + vpb - 1) / vpb) < 4096) vpb = (vpb + 1) / 2;
     dim3 grid(nblk, (nvec + vpb - 1) / vpb);
     const int NZ = nzp <= 8 ? 8 : nzp <= 16 ? 16 : nzp <= 24 ? 24 : 32;
-    const size_t sh = (size_t)V * NZ * W * sizeof(C) + (size_t)NZ * sizeof(int);
+    const size_t sh = (size_t)V * NZ * W * sizeof(C) + (size_t)NZ * sizeof(int) + (size_t)NZ * NZ;
     const T* gk = static_cast<const T*>(zhat);
     switch (NZ) {
       case 8: hipLaunchKernelGGL((k_zdirect<T, 8, RG, V, NT>), grid, dim3(NT), sh, s, geo, Lx, Ly, nzp, nvec, vpb,
-                                 p->d_zlist, gk, B); break;
+                                 p->d_zlist, ep.zslot ? p->d_qtab : nullptr, gk, B); break;
       case 16: hipLaunchKernelGGL((k_zdirect<T, 16, RG, V, NT>), grid, dim3(NT), sh, s, geo, Lx, Ly, nzp, nvec, vpb,
-                                  p->d_zlist, gk, B); break;
+                                  p->d_zlist, ep.zslot ? p->d_qtab : nullptr, gk, B); break;
       case 24: hipLaunchKernelGGL((k_zdirect<T, 24, RG, V, NT>), grid, dim3(NT), sh, s, geo, Lx, Ly, nzp, nvec, vpb,
-                                  p->d_zlist, gk, B); break;
+                                  p->d_zlist, ep.zslot ? p->d_qtab : nullptr, gk, B); break;
       default: hipLaunchKernelGGL((k_zdirect<T, 32, RG, V, NT>), grid, dim3(NT), sh, s, geo, Lx, Ly, nzp, nvec, vpb,
-                                  p->d_zlist, gk, B); break;
+                                  p->d_zlist, ep.zslot ? p->d_qtab : nullptr, gk, B); break;
     }
   } else {
     const FftPlan& pl = p->plan[2];

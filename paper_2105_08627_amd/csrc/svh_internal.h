@@ -61,6 +61,7 @@ struct EpiParams {
   int vec0;           // first component-vector of this chunk
   long long ldx, ldy; // element stride between right-hand sides of x and y
   int fidx[kMaxVecsPerChunk];  // frequency slot per RHS of the chunk (-1 = bare)
+  bool zslot = false;          // direct z step: kernel rows indexed by offset slot (dzset), not by offset
 };
 
 // Strides (in complex elements) of the intermediate buffers
