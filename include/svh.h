@@ -224,10 +224,11 @@ svh_status svh_profile_read(svh_problem* p, double* ms_out, int* ncalls_out);
 
 /* Choice of the z-direction step of the product (all choices give the same
  * operator up to rounding):
- *  SVH_ZSTEP_AUTO   (default) FUSED when it applies (basis 3, at most 32
- *                   occupied z planes with at most 64 distinct plane
- *                   offsets), else DIRECT when at most 32 planes are
- *                   occupied, else FFT;
+ *  SVH_ZSTEP_AUTO   (default) DIRECT when at most 32 planes are occupied,
+ *                   else FFT; svh_autotune switches a precision to FUSED
+ *                   when that applies (basis 3, at most 32 occupied z planes
+ *                   with at most 64 distinct plane offsets) and it timed the
+ *                   fused step faster on the caller's batch;
  *  SVH_ZSTEP_FFT    zero-padded FFT along z, product with the circulant
  *                   spectrum, inverse FFT (eq. 9 literally);
  *  SVH_ZSTEP_DIRECT after the x and y transforms, the Toeplitz sum along z
