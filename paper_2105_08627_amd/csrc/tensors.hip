@@ -57,44 +57,56 @@ struct GemmArgs {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
-// One wavefront per 16-column tile; it walks all 16-row tiles of its column.
-// Operand layout of v_mfma_f64_16x16x4f64 (wave64): lane l supplies
-// A[l % 16][l / 16] and B[l / 16][l % 16]; the result register r of lane l
-// is D[l / 16 + 4 r][l % 16] (checked on the device against a host product).
+// One wavefront per 16 x 16 output tile, row tiles fastest (the waves of one
+// column strip share its B values in the caches); the operands of eight
+// K-steps are loaded before their MFMAs.  Operand layout of
+// v_mfma_f64_16x16x4f64 (wave64): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; the result register r of lane l is D[l / 16 + 4 r][l % 16]
+// (checked on the device against a host product).
 template <typename TOut>
 __global__ void __launch_bounds__(256) k_gemm_f64_mfma(GemmArgs g) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int tiles_n = (g.N + 15) / 16;
-  const int tn = blockIdx.x * 4 + wave;
-  if (tn >= tiles_n) return;
+  const int tiles_n = (g.N + 15) / 16, tiles_m = (g.M + 15) / 16;
+  const long long tile = (long long)blockIdx.x * 4 + wave;
+  if (tile >= (long long)tiles_m * tiles_n) return;
+  const int tm = (int)(tile % tiles_m), tn = (int)(tile / tiles_m);
   const long long b = blockIdx.y;
   const double* A = g.A + b * g.sab;
   const double* Bm = g.B + b * g.sbb;
   TOut* C = static_cast<TOut*>(g.C) + b * g.scb;
-  const int col = tn * 16 + (lane & 15);
+  const int col = tn * 16 + (lane & 15), row = tm * 16 + (lane & 15);
   const int kq = lane >> 4;
-  const int tiles_m = (g.M + 15) / 16;
-  for (int tm = 0; tm < tiles_m; ++tm) {
-    const int row = tm * 16 + (lane & 15);
-    double4_t acc = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < g.Kd; k0 += 4) {
-      const int kk = k0 + kq;
-      const double a = (row < g.M && kk < g.Kd) ? A[row * g.sam + kk * g.sak] : 0.0;
-      const double bv = (col < g.N && kk < g.Kd) ? Bm[kk * g.sbk + col * g.sbn] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+  // clamped addresses (always valid), zeros selected after the loads
+  const int rowc = row < g.M ? row : g.M - 1, colc = col < g.N ? col : g.N - 1;
+  double4_t acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < g.Kd; k0 += 32) {
+    double a[8], bv[8];
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+      const int kk = k0 + 4 * st + kq;
+      const int kc = kk < g.Kd ? kk : g.Kd - 1;
+      a[st] = A[rowc * g.sam + kc * g.sak];
+      bv[st] = Bm[kc * g.sbk + colc * g.sbn];
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int orow = tm * 16 + kq + 4 * r;
-      if (orow < g.M && col < g.N) C[orow * g.scm + col * g.scn] = (TOut)acc[r];
+    for (int st = 0; st < 8; ++st) {
+      const int kk = k0 + 4 * st + kq;
+      const bool ok = kk < g.Kd;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64((ok && row < g.M) ? a[st] : 0.0, (ok && col < g.N) ? bv[st] : 0.0,
+                                                 acc, 0, 0, 0);
     }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int orow = tm * 16 + kq + 4 * r;
+    if (orow < g.M && col < g.N) C[orow * g.scm + col * g.scn] = (TOut)acc[r];
   }
 }
 
 static hipError_t gemm(const GemmArgs& g, int batch, bool f32out, hipStream_t s) {
-  const int tiles_n = (g.N + 15) / 16;
-  dim3 grid((tiles_n + 3) / 4, batch);
+  const long long tiles = (long long)((g.M + 15) / 16) * ((g.N + 15) / 16);
+  dim3 grid((unsigned)((tiles + 3) / 4), batch);
   if (f32out) hipLaunchKernelGGL(k_gemm_f64_mfma<float>, grid, dim3(256), 0, s, g);
   else hipLaunchKernelGGL(k_gemm_f64_mfma<double>, grid, dim3(256), 0, s, g);
   return hipGetLastError();
