@@ -10,6 +10,8 @@
 //    restoration Z = core x1 F1 x2 F2 x3 F3 (eqs. 10-11).  The last product
 //    writes the restored spectrum in the precision of the matvec (FP64
 //    accumulation in both cases).
+#include <type_traits>
+
 #include "svh_internal.h"
 
 namespace svh {
@@ -58,12 +60,12 @@ struct GemmArgs {
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
 // One wavefront per 16 x 16 output tile, row tiles fastest (the waves of one
-// column strip share its B values in the caches); the operands of eight
-// K-steps are loaded before their MFMAs.  Operand layout of
+// column strip share its B values in the caches); the operands of KS
+// K-steps (KS = ceil(K / 4), at most 8) are loaded before their MFMAs.  Operand layout of
 // v_mfma_f64_16x16x4f64 (wave64): lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; the result register r of lane l is D[l / 16 + 4 r][l % 16]
 // (checked on the device against a host product).
-template <typename TOut>
+template <typename TOut, int KS>
 __global__ void __launch_bounds__(256) k_gemm_f64_mfma(GemmArgs g) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -80,17 +82,17 @@ __global__ void __launch_bounds__(256) k_gemm_f64_mfma(GemmArgs g) {
   // clamped addresses (always valid), zeros selected after the loads
   const int rowc = row < g.M ? row : g.M - 1, colc = col < g.N ? col : g.N - 1;
   double4_t acc = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < g.Kd; k0 += 32) {
-    double a[8], bv[8];
+  for (int k0 = 0; k0 < g.Kd; k0 += 4 * KS) {
+    double a[KS], bv[KS];
 #pragma unroll
-    for (int st = 0; st < 8; ++st) {
+    for (int st = 0; st < KS; ++st) {
       const int kk = k0 + 4 * st + kq;
       const int kc = kk < g.Kd ? kk : g.Kd - 1;
       a[st] = A[rowc * g.sam + kc * g.sak];
       bv[st] = Bm[kc * g.sbk + colc * g.sbn];
     }
 #pragma unroll
-    for (int st = 0; st < 8; ++st) {
+    for (int st = 0; st < KS; ++st) {
       const int kk = k0 + 4 * st + kq;
       const bool ok = kk < g.Kd;
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64((ok && row < g.M) ? a[st] : 0.0, (ok && col < g.N) ? bv[st] : 0.0,
@@ -107,8 +109,22 @@ __global__ void __launch_bounds__(256) k_gemm_f64_mfma(GemmArgs g) {
 static hipError_t gemm(const GemmArgs& g, int batch, bool f32out, hipStream_t s) {
   const long long tiles = (long long)((g.M + 15) / 16) * ((g.N + 15) / 16);
   dim3 grid((unsigned)((tiles + 3) / 4), batch);
-  if (f32out) hipLaunchKernelGGL(k_gemm_f64_mfma<float>, grid, dim3(256), 0, s, g);
-  else hipLaunchKernelGGL(k_gemm_f64_mfma<double>, grid, dim3(256), 0, s, g);
+  const int steps = (g.Kd + 3) / 4;
+  auto go = [&](auto kst) {
+    constexpr int KS = decltype(kst)::value;
+    if (f32out) hipLaunchKernelGGL((k_gemm_f64_mfma<float, KS>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_gemm_f64_mfma<double, KS>), grid, dim3(256), 0, s, g);
+  };
+  switch (steps < 8 ? steps : 8) {
+    case 1: go(std::integral_constant<int, 1>{}); break;
+    case 2: go(std::integral_constant<int, 2>{}); break;
+    case 3: go(std::integral_constant<int, 3>{}); break;
+    case 4: go(std::integral_constant<int, 4>{}); break;
+    case 5: go(std::integral_constant<int, 5>{}); break;
+    case 6: go(std::integral_constant<int, 6>{}); break;
+    case 7: go(std::integral_constant<int, 7>{}); break;
+    default: go(std::integral_constant<int, 8>{}); break;
+  }
   return hipGetLastError();
 }
 
