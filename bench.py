@@ -173,6 +173,14 @@ def bench_basis5(args, cfg, mask, fidx, dev):
             + " ".join(f"{k}={v:.3f}" for k, v in per.items()))
     rel = (torch.linalg.vector_norm((y32.to(torch.complex128) - y64).flatten())
            / torch.linalg.vector_norm(y64.flatten())).item()
+
+    # adjoint product (same kernels through the transposed block table)
+    ya32, adj32 = bench_adjoint(p, x32, fidx, max(args.steps // 2, 1))
+    ya64, adj64 = bench_adjoint(p, x64, fidx, args.fp64_steps)
+    adj_sym = (torch.linalg.vector_norm((ya64 - y64).flatten()) / torch.linalg.vector_norm(y64.flatten())).item()
+    del ya32, ya64
+    log(f"[bench] adjoint fp32 {adj32['ms_per_step']:.3f} ms/step fp64 {adj64['ms_per_step']:.3f} ms/step "
+        f"|Z^T x - Z x|/|Z x| {adj_sym:.1e}")
     Lx, Ly, _ = p.L
     # coupled z step: 12 z convolutions of complex data with real kernels per
     # pencil, i.e. 48 flops per (pencil, RHS, observer plane, source plane)
@@ -331,9 +339,56 @@ def bench_solve(args):
         log(f"[bench] solve {name}: {dt:.3f}s {info['iterations']} its, inner {info['inner_iterations']}, "
             f"relres {info['relres']:.2e}")
     Y64, Yir = res["fp64"].pop("Y"), res["fp32_refined"].pop("Y")
+    res["gradient"] = bench_gradient(p, f)
     return {"workload": f"16 coupled strips {mask.shape[2]}x{mask.shape[1]}x{mask.shape[0]}, K={p.K}, "
                         f"N={p.N} per port, 16 ports, rre 1e-8", **res,
             "admittance_rel_diff_fp32_refined_vs_fp64": float(np.abs(Yir - Y64).max() / np.abs(Y64).max())}
+
+
+def bench_gradient(p, f):
+    """Gradient of the full port-inductance matrix with respect to every
+    voxel's lambda^-2 (addition 3): forward solve, adjoint solve (transpose),
+    per-voxel admittance derivative, contraction with W = Z G Z for G = all
+    ones.  Timed after one untimed pass."""
+    import torch
+    w = 2 * np.pi * f
+    for timed in (False, True):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, Y, _ = p.solve(0, rre=1e-8, restart=50)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        Xa, _, info = p.solve(0, rre=1e-8, restart=50, transpose=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        dY = p.port_gradient(0, X, Xa)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        Z = np.linalg.inv(Y)
+        g = p.gradient_contract(dY, Z @ np.ones_like(Z) @ Z, -1.0 / w)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+    log(f"[bench] gradient: forward {t1 - t0:.3f}s adjoint {t2 - t1:.3f}s ({info['iterations']} its) "
+        f"dY {1e3 * (t3 - t2):.2f} ms contract {1e3 * (t4 - t3):.2f} ms")
+    return {"what": "d(sum of all port inductances)/d(lambda_k^-2) for every voxel k, FP64, rre 1e-8",
+            "forward_solve_s": t1 - t0, "adjoint_solve_s": t2 - t1, "adjoint_iterations": info["iterations"],
+            "port_gradient_ms": 1e3 * (t3 - t2), "contract_ms": 1e3 * (t4 - t3), "total_s": t4 - t0,
+            "dY_entries": int(dY.numel()), "grad_finite": bool(torch.isfinite(g).all().item())}
+
+
+def bench_adjoint(p, x, fidx, steps):
+    """Adjoint product y = Z^T x (addition 3) on the same batch as the
+    forward product, timed like it."""
+    import torch
+    y = torch.empty_like(x)
+    p.matvec_adjoint(x, fidx, out=y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        p.matvec_adjoint(x, fidx, out=y)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return y, {"ms_per_step": dt * 1e3 / steps, "matvecs_per_s": x.shape[0] * steps / dt}
 
 
 def main():
@@ -437,6 +492,14 @@ def main():
     rel = (torch.linalg.vector_norm((y32.to(torch.complex128) - y64).flatten())
            / torch.linalg.vector_norm(y64.flatten())).item()
 
+    # adjoint product (same kernels through the transposed block table)
+    ya32, adj32 = bench_adjoint(p, x32, fidx, max(args.steps // 2, 1))
+    ya64, adj64 = bench_adjoint(p, x64, fidx, args.fp64_steps)
+    adj_sym = (torch.linalg.vector_norm((ya64 - y64).flatten()) / torch.linalg.vector_norm(y64.flatten())).item()
+    del ya32, ya64
+    log(f"[bench] adjoint fp32 {adj32['ms_per_step']:.3f} ms/step fp64 {adj64['ms_per_step']:.3f} ms/step "
+        f"|Z^T x - Z x|/|Z x| {adj_sym:.1e}")
+
     mv32 = nrhs * args.steps / dt32
     mv64 = nrhs * args.fp64_steps / dt64
     nvec = 3 * nrhs
@@ -480,6 +543,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(KERNEL_NAMES_FP32.get(dom)),
                      "all_passes_frac": total_bytes / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "adjoint": {"fp32": adj32, "fp64": adj64, "rel_diff_vs_forward_fp64": adj_sym},
         "tucker_restore": {"ms": tk_ms, "tflops": tflops / (tk_ms * 1e-3) / 1e12 if tk_ms > 0 else None,
                            "mfma_frac": (tflops / (tk_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS) if tk_ms > 0 else None},
     }

@@ -122,6 +122,8 @@ def toeplitz_store_build(K, nfam, tol, path, stream=None):
 def toeplitz_store_restore(path, K, nfam, out, stream=None):
     """Algorithm 2, execution: the first nfam tables for a K grid restored from
     the store into the device tensor `out` (float64, nfam * Kx * Ky * Kz)."""
+    import torch
+    _device_tensor(out, "out", torch.float64, min_numel=int(nfam) * int(K[0]) * int(K[1]) * int(K[2]))
     st = lib().svh_toeplitz_store_restore(os.fsencode(path), int(K[0]), int(K[1]), int(K[2]), int(nfam),
                                           ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
     if st != 0:
@@ -131,11 +133,30 @@ def toeplitz_store_restore(path, K, nfam, out, stream=None):
 
 def green_tables(K, nfam, out, stream=None):
     """The first nfam unit-voxel tables computed on the device into `out`."""
+    import torch
+    _device_tensor(out, "out", torch.float64, min_numel=int(nfam) * int(K[0]) * int(K[1]) * int(K[2]))
     st = lib().svh_green_tables(int(K[0]), int(K[1]), int(K[2]), int(nfam), ctypes.c_void_p(out.data_ptr()),
                                 _stream_handle(stream))
     if st != 0:
         raise SvhError(f"svh_green_tables: {_STATUS.get(st, st)}")
     return out
+
+
+def _device_tensor(t, what, dtype, shape=None, min_numel=None):
+    """Check a tensor handed to the library by pointer: the C calls take no
+    shapes, so a wrong one would be read or written out of bounds."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError(f"{what} holds {t.numel()} elements, {min_numel} needed")
+    return t
 
 
 def _stream_handle(stream=None):
@@ -225,11 +246,11 @@ class Problem:
             self._ws[key] = ws
         return ws
 
-    def matvec(self, x, freq_idx, out=None, stream=None):
-        """y = Z x for x of shape (nrhs, C, K), complex128 (FP64) or complex64
-        (FP32), on a CUDA device.  freq_idx: one slot per RHS (-1: bare)."""
+    def _batch(self, x, freq_idx, out):
+        """Checks of a (nrhs, C, K) batch and its output; returns (prec, nrhs,
+        freq_idx as int32, output tensor)."""
         import torch
-        if not x.is_cuda:
+        if not isinstance(x, torch.Tensor) or not x.is_cuda:
             raise ValueError("x must be a device tensor")
         if x.dtype == torch.complex128:
             prec = SVH_FP64
@@ -237,11 +258,23 @@ class Problem:
             prec = SVH_FP32
         else:
             raise TypeError("x must be complex128 or complex64")
-        if x.dim() != 3 or x.shape[1] != self.C or x.shape[2] != self.K or not x.is_contiguous():
-            raise ValueError(f"x must be contiguous (nrhs, {self.C}, {self.K})")
+        if x.dim() != 3 or x.shape[0] < 1 or x.shape[1] != self.C or x.shape[2] != self.K:
+            raise ValueError(f"x must have shape (nrhs, {self.C}, {self.K}), got {tuple(x.shape)}")
+        _device_tensor(x, "x", x.dtype)
         nrhs = x.shape[0]
         fi = np.ascontiguousarray(np.broadcast_to(np.asarray(freq_idx, dtype=np.int32), (nrhs,)))
-        y = out if out is not None else torch.empty_like(x)
+        if out is None:
+            y = torch.empty_like(x)
+        else:
+            y = _device_tensor(out, "out", x.dtype, shape=x.shape)
+            if y.device != x.device:
+                raise ValueError("out must be on the device of x")
+        return prec, nrhs, fi, y
+
+    def matvec(self, x, freq_idx, out=None, stream=None):
+        """y = Z x for x of shape (nrhs, C, K), complex128 (FP64) or complex64
+        (FP32), on a CUDA device.  freq_idx: one slot per RHS (-1: bare)."""
+        prec, nrhs, fi, y = self._batch(x, freq_idx, out)
         ws = self.workspace(prec, nrhs, x.device)
         st = lib().svh_matvec(self._h, prec, nrhs, _ptr(fi), ctypes.c_void_p(x.data_ptr()),
                               ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
@@ -257,11 +290,7 @@ class Problem:
 
     def autotune(self, x, freq_idx, stream=None):
         """Pick the fastest launch shapes for this batch; returns tuned ms/matvec."""
-        import torch
-        prec = SVH_FP64 if x.dtype == torch.complex128 else SVH_FP32
-        nrhs = x.shape[0]
-        fi = np.ascontiguousarray(np.broadcast_to(np.asarray(freq_idx, dtype=np.int32), (nrhs,)))
-        y = torch.empty_like(x)
+        prec, nrhs, fi, y = self._batch(x, freq_idx, None)
         ws = self.workspace(prec, nrhs, x.device)
         ms = np.zeros(1)
         self._check(lib().svh_autotune(self._h, prec, nrhs, _ptr(fi), ctypes.c_void_p(x.data_ptr()),
@@ -289,11 +318,7 @@ class Problem:
 
     def matvec_adjoint(self, x, freq_idx, out=None, stream=None):
         """y = Z^T x (same conventions as matvec)."""
-        import torch
-        prec = SVH_FP64 if x.dtype == torch.complex128 else SVH_FP32
-        nrhs = x.shape[0]
-        fi = np.ascontiguousarray(np.broadcast_to(np.asarray(freq_idx, dtype=np.int32), (nrhs,)))
-        y = out if out is not None else torch.empty_like(x)
+        prec, nrhs, fi, y = self._batch(x, freq_idx, out)
         ws = self.workspace(prec, nrhs, x.device)
         self._check(lib().svh_matvec_adjoint(self._h, prec, nrhs, _ptr(fi), ctypes.c_void_p(x.data_ptr()),
                                              ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
@@ -303,6 +328,10 @@ class Problem:
     def port_gradient(self, freq_idx, xfwd, xadj, stream=None):
         """dY[q, p, k] = d Y_qp / d (lambda_k^-2) from forward and adjoint solutions."""
         import torch
+        if not hasattr(self, "nports"):
+            raise SvhError("port_gradient: set_ports first")
+        _device_tensor(xfwd, "xfwd", torch.complex128, shape=(self.nports, self.N))
+        _device_tensor(xadj, "xadj", torch.complex128, shape=(self.nports, self.N))
         dY = torch.empty((self.nports, self.nports, self.K), dtype=torch.complex128, device=xfwd.device)
         self._check(lib().svh_port_gradient(self._h, int(freq_idx), ctypes.c_void_p(xfwd.data_ptr()),
                                             ctypes.c_void_p(xadj.data_ptr()), ctypes.c_void_p(dY.data_ptr()),
@@ -312,7 +341,12 @@ class Problem:
     def gradient_contract(self, dY, W, scale, stream=None):
         """grad[k] = scale * Im(sum_qp W[q,p] dY[q,p,k]) (device float64 tensor)."""
         import torch
+        if not hasattr(self, "nports"):
+            raise SvhError("gradient_contract: set_ports first")
+        _device_tensor(dY, "dY", torch.complex128, shape=(self.nports, self.nports, self.K))
         Wc = np.ascontiguousarray(np.asarray(W, dtype=np.complex128))
+        if Wc.shape != (self.nports, self.nports):
+            raise ValueError(f"W must be ({self.nports}, {self.nports})")
         g = torch.empty(self.K, dtype=torch.float64, device=dY.device)
         self._check(lib().svh_gradient_contract(self._h, ctypes.c_void_p(dY.data_ptr()), _ptr(Wc), float(scale),
                                                 ctypes.c_void_p(g.data_ptr()), _stream_handle(stream)),

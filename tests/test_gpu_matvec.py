@@ -269,3 +269,29 @@ def test_green_methods_agree(dev):
     yq = _run(pq, x, [0, -1], dev, torch.complex128)
     yc = _run(pc, x, [0, -1], dev, torch.complex128)
     assert np.all(_relerr(yq, yc) <= 1e-14)
+
+
+def test_binding_rejects_mismatched_tensors(dev):
+    """The C calls take bare pointers, so the binding refuses tensors whose
+    shape, dtype, layout or device would not match what the kernels index."""
+    mask = wl.random_mask(71, 9, 7, 5, fill=0.6)
+    p = _problem(mask, 0.25e-6)
+    x = torch.zeros((2, 3, p.K), dtype=torch.complex64, device=dev)
+    bad = [
+        (lambda: p.matvec(x[:, :2].contiguous(), [0, 0]), ValueError),          # wrong component count
+        (lambda: p.matvec(x.real.contiguous(), [0, 0]), TypeError),              # not complex
+        (lambda: p.matvec(x.cpu(), [0, 0]), ValueError),                        # host tensor
+        (lambda: p.matvec(x.transpose(1, 2).contiguous().transpose(1, 2), [0, 0]), ValueError),  # strided
+        (lambda: p.matvec(x, [0, 0], out=torch.empty_like(x[:1])), ValueError),  # short output
+        (lambda: p.matvec(x, [0, 0], out=torch.empty_like(x, dtype=torch.complex128)), TypeError),
+        (lambda: p.matvec_adjoint(x[:, :, :-1].contiguous(), [0, 0]), ValueError),
+        (lambda: p.matvec_adjoint(x, [0, 0], out=torch.empty_like(x)[:, :, :-1]), ValueError),
+        (lambda: p.autotune(x.real.double().contiguous(), [0, 0]), TypeError),
+    ]
+    for call, exc in bad:
+        with pytest.raises(exc):
+            call()
+    # a well-formed call still runs after the rejected ones
+    y = p.matvec(x, [0, 0])
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(y).item() == 0
