@@ -345,6 +345,38 @@ def bench_solve(args):
             "admittance_rel_diff_fp32_refined_vs_fp64": float(np.abs(Yir - Y64).max() / np.abs(Y64).max())}
 
 
+def bench_solve_strips_over_ground(args):
+    """Port solve of the 128 x 128 x 64 strips-over-ground workload: 16 ports
+    in one batch, piecewise-linear basis (five components, so current turns
+    the vias' corners), Tucker tol 1e-6, FP32 products in FP64 refinement and
+    plain FP64, both to relative residual 1e-8."""
+    import torch
+    import paper_2105_08627_amd as svh
+    import workloads as wl
+    mask, ports = wl.strips_over_ground_with_ports(1002)
+    f = 10e9
+    p = svh.Problem(mask, 0.25e-6, basis=5)
+    p.set_material([f], 1e7, 90e-9)
+    p.setup_tensors()
+    p.tucker_compress(1e-6)
+    p.set_ports(ports)
+    res = {}
+    for name, refine in (("fp32_refined", True), ("fp64", False)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, Y, info = p.solve(0, rre=1e-8, restart=50, refine=refine)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[name] = {"seconds": dt, "Y": Y, **{k: info[k] for k in ("iterations", "inner_iterations",
+                                                                     "refinement_steps", "relres")}}
+        log(f"[bench] strips-over-ground solve {name}: {dt:.2f}s {info['iterations']} its, "
+            f"inner {info['inner_iterations']}, relres {info['relres']:.2e}")
+    Y64, Yir = res["fp64"].pop("Y"), res["fp32_refined"].pop("Y")
+    return {"workload": f"strips over a ground slab with 16 holes, {mask.shape[2]}x{mask.shape[1]}x{mask.shape[0]}, "
+                        f"K={p.K}, five components, N={p.N} per port, 16 ports, rre 1e-8, Tucker tol 1e-6",
+            **res, "admittance_rel_diff_fp32_refined_vs_fp64": float(np.abs(Yir - Y64).max() / np.abs(Y64).max())}
+
+
 def bench_gradient(p, f):
     """Gradient of the full port-inductance matrix with respect to every
     voxel's lambda^-2 (addition 3): forward solve, adjoint solve (transpose),
@@ -551,6 +583,7 @@ def main():
         out["basis5"] = bench_basis5(args, cfg, mask, fidx, dev)
     if not args.no_solve:
         out["solve"] = bench_solve(args)
+        out["solve_strips_over_ground"] = bench_solve_strips_over_ground(args)
     if args.table2:
         out["table2"] = bench_table2(args)
     if args.tucker_sweep:

@@ -309,7 +309,10 @@ size_t svh_solve_workspace_bytes(const svh_problem* p, svh_prec prec, int restar
  * residual target (the paper uses 1e-8).  maxit: cap on GMRES steps.
  * transpose != 0 solves K^T x = [b; 0] instead (adjoint system).
  * x_dev: nports columns of N complex doubles (currents, component-major as in
- * svh_matvec, then node potentials; port and grounded nodes hold 0).
+ * svh_matvec, then node potentials; port and grounded nodes hold 0).  Nodes
+ * are numbered in face-grid order: faces normal to x, then y, then z, each
+ * set with x fastest, then y, then z, counting only faces of non-empty
+ * voxels.
  * Y_host (may be NULL): nports*nports complex doubles, Y[q*nports + p].
  * info (may be NULL): iteration counts and true residuals.
  * Returns SVH_ENOTCONV (with x, Y and info filled) if the target is missed.

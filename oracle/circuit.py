@@ -56,24 +56,30 @@ def voxel_face_node(node_of, p, face):
     return node_of[(a, q[0], q[1], q[2])]
 
 
+def basis_face_flux(beta):
+    """(face code, A entry) pairs of basis function beta of a voxel: the
+    current it draws from each face node into the voxel (readings in the
+    module docstring).  beta 0-2: f^x, f^y, f^z, +1 at the -a face and -1 at
+    the +a face; 3: f^2D (eq. 5), -1/2 at both x faces and +1/2 at both y
+    faces; 4: f^3D (eq. 6), -1/2 at the four x and y faces and +1 at both z
+    faces (/dx^2 normalisation, so every function has zero net flux)."""
+    if beta < 3:
+        return [(2 * beta, 1.0), (2 * beta + 1, -1.0)]
+    if beta == 3:
+        return [(0, -0.5), (1, -0.5), (2, 0.5), (3, 0.5)]
+    return [(0, -0.5), (1, -0.5), (2, -0.5), (3, -0.5), (4, 1.0), (5, 1.0)]
+
+
 def incidence(mask, basis=3):
-    """Dense incidence matrix A (M x basis*K), readings in the module docstring.
-    Piecewise-linear columns follow the flux of eqs. 5-6 (/dx^2 normalisation):
-    f^2D draws -1/2 at both x faces and +1/2 at both y faces, f^3D draws -1/2
-    at the four x and y faces and +1 at both z faces."""
+    """Dense incidence matrix A (M x basis*K), entries from basis_face_flux."""
     node_of, nodes = face_nodes(mask)
     P = op.voxel_coords(mask)
     K = P.shape[0]
     A = np.zeros((len(nodes), basis * K))
     for k, p in enumerate(P):
-        for a in range(3):
-            A[voxel_face_node(node_of, p, 2 * a), a * K + k] += 1.0
-            A[voxel_face_node(node_of, p, 2 * a + 1), a * K + k] -= 1.0
-        if basis == 5:
-            for f in range(6):
-                m = voxel_face_node(node_of, p, f)
-                A[m, 3 * K + k] += -0.5 if _AX[f] == 0 else 0.5 if _AX[f] == 1 else 0.0
-                A[m, 4 * K + k] += -0.5 if _AX[f] < 2 else 1.0
+        for beta in range(basis):
+            for f, a in basis_face_flux(beta):
+                A[voxel_face_node(node_of, p, f), beta * K + k] += a
     return A, node_of, nodes
 
 

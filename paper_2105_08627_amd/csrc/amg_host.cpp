@@ -1,11 +1,18 @@
 // Aggregation multigrid for the Schur complement S = A_F Y^-1 A_F^T of the
 // preconditioner (eqs. 12-15), host setup.  The paper inverts S with an
 // aggregation-based algebraic multigrid (AGMG); this is an own implementation
-// of plain pairwise aggregation as published by Notay: each level pairs every
-// node with its strongest negatively coupled unpaired neighbour, twice, so
-// that aggregates hold up to four nodes; the coarse matrix is the Galerkin
-// product P^T S P with the piecewise-constant prolongation P.  Coarsening
-// stops at kAmgCoarse nodes or when a level no longer shrinks.
+// of pairwise aggregation as published by Notay: each level pairs every node
+// with its strongest negatively coupled unpaired neighbour, twice; the coarse
+// matrix is the Galerkin product P^T S P with the piecewise-constant
+// prolongation P.  Coarsening stops at kAmgCoarse nodes or when a level no
+// longer shrinks.
+//
+// With the linear basis functions the coarse graphs turn star-shaped (many
+// nodes whose only coupling is to one hub), and strict pairing stalls: a hub
+// takes one partner per pass and the rest stay single.  So a node left
+// single by a pass joins the pair of its dominant neighbour (at least half of
+// its total negative coupling).  Its smooth-mode value follows that
+// neighbour's, so the merge keeps the coarse space's quality.
 //
 // Rows without couplings (Dirichlet nodes, which keep identity rows, and the
 // one-node remainders of isolated lines) are solved exactly by their diagonal
@@ -31,12 +38,12 @@ bool decoupled_row(const AmgLevel& L, int i) {
 // or -1 for a decoupled row when drop is set (its diagonal solves it exactly,
 // so it is left out of the coarser levels).  Candidates of i: unmatched j with
 // -a_ij >= beta * max_k(-a_ik); i is paired with the candidate of the most
-// negative coupling, else left single.
+// negative coupling, else left single (and may then join a neighbour's pair).
 int pair_once(const AmgLevel& L, std::vector<int>& agg, bool drop) {
   const int n = L.n;
   agg.assign(n, -2);  // -2 unvisited
   int nc = 0;
-  const double beta = 0.25;
+  const double beta = 0.25, kJoinDominance = 0.5;
   for (int i = 0; i < n; ++i) {
     if (agg[i] != -2) continue;
     if (drop && decoupled_row(L, i)) {
@@ -62,7 +69,32 @@ int pair_once(const AmgLevel& L, std::vector<int>& agg, bool drop) {
     if (best >= 0) agg[best] = nc;
     ++nc;
   }
-  return nc;
+  // single nodes join the pair of their dominant neighbour (pairs formed in
+  // this pass only, so no chains), then aggregates are renumbered densely
+  std::vector<int> size(nc, 0), into(nc, -1);
+  for (int i = 0; i < n; ++i)
+    if (agg[i] >= 0) size[agg[i]]++;
+  for (int i = 0; i < n; ++i) {
+    if (agg[i] < 0 || size[agg[i]] != 1) continue;
+    double total = 0, bv = 0;
+    int bj = -1;
+    for (int q = L.rptr[i]; q < L.rptr[i + 1]; ++q)
+      if (L.col[q] != i && L.val[q] < 0) {
+        total -= L.val[q];
+        if (-L.val[q] > bv) {
+          bv = -L.val[q];
+          bj = L.col[q];
+        }
+      }
+    if (bj >= 0 && agg[bj] >= 0 && size[agg[bj]] >= 2 && bv >= kJoinDominance * total) into[agg[i]] = agg[bj];
+  }
+  std::vector<int> label(nc, -1);
+  int m = 0;
+  for (int a = 0; a < nc; ++a)
+    if (into[a] < 0) label[a] = m++;
+  for (int i = 0; i < n; ++i)
+    if (agg[i] >= 0) agg[i] = label[into[agg[i]] >= 0 ? into[agg[i]] : agg[i]];
+  return m;
 }
 
 // Galerkin product of a piecewise-constant prolongation: C = P^T A P (rows

@@ -240,15 +240,35 @@ __global__ void k_amg_smooth0(int nrhs, int n, const double* __restrict__ wdinv,
                               double2* __restrict__ x) {
   GRID_STRIDE(i, (long long)n * nrhs) x[i] = zscale(b[i], wdinv[i % n]);
 }
+// r = b - A x.  One thread takes a row for up to kResidRhs right-hand sides:
+// the row's entries are read once and the gathers of the right-hand sides
+// are independent (the index of a missing one is clamped to the last, so
+// every load is unconditional; only the stores are masked).
+constexpr int kResidRhs = 8;
 __global__ void k_amg_resid(int nrhs, int n, const int* __restrict__ rptr, const int* __restrict__ col,
                             const double* __restrict__ val, const double2* __restrict__ b,
                             const double2* __restrict__ x, double2* __restrict__ r) {
-  GRID_STRIDE(i, (long long)n * nrhs) {
-    const long long base = (i / n) * n;
+  const int nchunk = (nrhs + kResidRhs - 1) / kResidRhs;
+  GRID_STRIDE(i, (long long)n * nchunk) {
     const int row = (int)(i % n);
-    double2 acc = b[i];
-    for (int q = rptr[row]; q < rptr[row + 1]; ++q) acc = zsub(acc, zscale(x[base + col[q]], val[q]));
-    r[i] = acc;
+    const int r0 = (int)(i / n) * kResidRhs;
+    const int last = nrhs - 1 - r0;  // >= 0
+    long long off[kResidRhs];
+    double2 acc[kResidRhs];
+#pragma unroll
+    for (int j = 0; j < kResidRhs; ++j) {
+      off[j] = (long long)(r0 + min(j, last)) * n;
+      acc[j] = b[off[j] + row];
+    }
+    for (int q = rptr[row]; q < rptr[row + 1]; ++q) {
+      const int c = col[q];
+      const double v = val[q];
+#pragma unroll
+      for (int j = 0; j < kResidRhs; ++j) acc[j] = zsub(acc[j], zscale(x[off[j] + c], v));
+    }
+#pragma unroll
+    for (int j = 0; j < kResidRhs; ++j)
+      if (j <= last) r[off[j] + row] = acc[j];
   }
 }
 __global__ void k_amg_jacobi(int nrhs, int n, const double* __restrict__ wdinv, const double2* __restrict__ r,
@@ -449,6 +469,8 @@ int nblocks(long long n) {
   long long b = (n + 255) / 256;
   return (int)std::max(1LL, std::min(b, 8192LL));
 }
+// grid of k_amg_resid: one thread per row and group of kResidRhs right-hand sides
+int resid_blocks(int n, int nrhs) { return nblocks((long long)n * ((nrhs + kResidRhs - 1) / kResidRhs)); }
 
 constexpr int kDotBlocks = 256;
 
@@ -738,7 +760,7 @@ void vcycle(Ctx& c, const double2* b0, double2* x0, hipStream_t s) {
       } else {  // diagonal matrix (exact), or damped Jacobi sweeps
         hipLaunchKernelGGL(k_amg_smooth0, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, b, x);
         for (int k = 1; k < (p->amg_coarse == kAmgCoarseJacobi ? kAmgCoarseSweeps : 1); ++k) {
-          hipLaunchKernelGGL(k_amg_resid, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.rptr, L.col, L.val, b, x,
+          hipLaunchKernelGGL(k_amg_resid, dim3(resid_blocks(L.n, nr)), dim3(256), 0, s, nr, L.n, L.rptr, L.col, L.val, b, x,
                              L.r);
           hipLaunchKernelGGL(k_amg_jacobi, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, L.r, x);
         }
@@ -746,7 +768,7 @@ void vcycle(Ctx& c, const double2* b0, double2* x0, hipStream_t s) {
       break;
     }
     hipLaunchKernelGGL(k_amg_smooth0, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, b, x);
-    hipLaunchKernelGGL(k_amg_resid, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.rptr, L.col, L.val, b, x, L.r);
+    hipLaunchKernelGGL(k_amg_resid, dim3(resid_blocks(L.n, nr)), dim3(256), 0, s, nr, L.n, L.rptr, L.col, L.val, b, x, L.r);
     auto& Cl = p->amg[l + 1];
     hipLaunchKernelGGL(k_amg_restrict, dim3(nblocks((long long)Cl.n * nr)), dim3(256), 0, s, nr, L.n, Cl.n, L.mptr,
                        L.mem, L.r, Cl.b);
@@ -758,7 +780,7 @@ void vcycle(Ctx& c, const double2* b0, double2* x0, hipStream_t s) {
     double2* x = l ? L.x : x0;
     const long long n = (long long)L.n * nr;
     hipLaunchKernelGGL(k_amg_prolong, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, Cl.n, L.agg, Cl.x, x);
-    hipLaunchKernelGGL(k_amg_resid, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.rptr, L.col, L.val, b, x, L.r);
+    hipLaunchKernelGGL(k_amg_resid, dim3(resid_blocks(L.n, nr)), dim3(256), 0, s, nr, L.n, L.rptr, L.col, L.val, b, x, L.r);
     hipLaunchKernelGGL(k_amg_jacobi, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, L.r, x);
   }
 }

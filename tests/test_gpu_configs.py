@@ -1,0 +1,203 @@
+"""Port solves at the sizes of the paper-style workloads, checked against the
+oracle's equations.
+
+  * meander  64x64x16, one port, FP64 to 1e-8, Tucker tol 1e-8;
+  * strips   128x128x64 over a ground slab with 16 holes, 16 ports in one
+             batch, FP32 products inside FP64 refinement to 1e-8, tol 1e-6;
+  * bend     96x96x32 over a ground plane, per-voxel London depth drawn in
+             80-120 nm, adjoint gradient of the port inductance with respect
+             to every voxel's lambda^-2 against central differences (step
+             1e-4 p_k, solves to 1e-12) on 32 voxels: within 1e-3 of the
+             gradient plus the difference quotient's own noise, 1e-12 L / h.
+
+A dense LU solve is out of reach at these sizes, so each solution is checked
+against what the oracle fixes at any size:
+  * the saddle system of eq. 7 with the oracle's face-flux entries of A
+    (Z I - A^T Phi over every current row, A I at every free node), Z I
+    being the library's product; relative to ||b|| it must be the solver's
+    residual target;
+  * that product at sampled observer voxels against the oracle's row sums
+    from its own Green integrals (the Tucker-truncated spectrum sets the
+    bound: 10 tol of the row scale);
+  * the admittance as the current entering each + terminal, from the same
+    face fluxes.
+Voxel materials: sigma0 = 1e7 S/m, f = 10 GHz, lambda = 90 nm unless drawn.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import circuit as cc
+from oracle import green
+from oracle import operator as op
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+F, S0, LAM, DX = 10e9, 1e7, 90e-9, 0.25e-6
+
+
+def _node_index(mask):
+    """(K, 6) node index of every voxel face in the library's node order
+    (face grid: x faces, then y faces, then z faces, each with x fastest,
+    then y, then z; only faces of non-empty voxels are nodes)."""
+    Kz, Ky, Kx = mask.shape
+    P = op.voxel_coords(mask)
+    dims = [(Kx + 1, Ky, Kz), (Kx, Ky + 1, Kz), (Kx, Ky, Kz + 1)]
+    off = np.cumsum([0] + [a * b * c for a, b, c in dims])
+    ids = np.zeros((P.shape[0], 6), dtype=np.int64)
+    for f in range(6):
+        a, s = divmod(f, 2)
+        q = P.copy()
+        q[:, a] += s
+        X, Y, _ = dims[a]
+        ids[:, f] = off[a] + (q[:, 2] * Y + q[:, 1]) * X + q[:, 0]
+    used = np.unique(ids)
+    return np.searchsorted(used, ids), used.size
+
+
+def _problem(mask, ports, basis, tol, lam=LAM):
+    import paper_2105_08627_amd as svh
+    p = svh.Problem(mask, DX, basis=basis)
+    per_voxel = np.ndim(lam) > 0
+    s0 = np.full(np.size(lam), S0) if per_voxel else S0
+    p.set_material([F], s0, lam, per_voxel=per_voxel)
+    p.setup_tensors()
+    p.tucker_compress(tol)
+    p.set_ports(ports)
+    return p
+
+
+def _check_solution(p, mask, basis, ports, X, Y, rre, cols):
+    """Residual of eq. 7 from the oracle's face fluxes (all rows) and the
+    admittance as terminal currents, for the port columns `cols`."""
+    K = p.K
+    CK = basis * K
+    node, M = _node_index(mask)
+    assert M == p.M
+    plus = [np.unique([node[k, f] for k, f in pl]) for pl, _ in ports]
+    Xh = X.cpu().numpy()
+    I = Xh[:, :CK].reshape(-1, basis, K)
+    ZI = p.matvec(torch.from_numpy(np.ascontiguousarray(I[cols])).to(X.device), [0] * len(cols)).cpu().numpy()
+    terminals = np.unique(np.concatenate([node[k, f][None] for pl, mi in ports for k, f in pl + mi]))
+    free = np.ones(M, dtype=bool)
+    free[terminals] = False
+    for ci, q in enumerate(cols):
+        phi = Xh[q, CK:].copy()
+        phi[plus[q]] = 1.0
+        inj = np.zeros(M, dtype=np.complex128)
+        top = ZI[ci].copy()
+        bvec = np.zeros((basis, K))
+        hot = np.zeros(M)
+        hot[plus[q]] = 1.0
+        for beta in range(basis):
+            for f, a in cc.basis_face_flux(beta):
+                np.add.at(inj, node[:, f], a * I[q, beta])
+                top[beta] -= a * phi[node[:, f]]
+                bvec[beta] += a * hot[node[:, f]]
+        res = np.sqrt(np.sum(np.abs(top) ** 2) + np.sum(np.abs(inj[free]) ** 2)) / np.linalg.norm(bvec)
+        print(f"[configs] port {q}: residual of eq. 7 with the oracle's fluxes {res:.2e}", flush=True)
+        assert res <= 1.5 * rre, (q, res)
+        Yq = np.array([inj[pl].sum() for pl in plus])
+        assert np.abs(Yq - Y[:, q]).max() <= 1e-10 * np.abs(Y).max(), q
+
+
+def _check_rows(p, mask, basis, I, tol, lam, nobs=2, seed=0):
+    """Z I at sampled observer voxels against the oracle's row sums."""
+    P = op.voxel_coords(mask)
+    names = op.BASIS_SETS[basis]
+    w = 2 * np.pi * F
+    s = 1j * w * op.MU0 * DX
+    lamv = np.broadcast_to(np.asarray(lam, dtype=np.float64), (p.K,))
+    ZI = p.matvec(torch.from_numpy(np.ascontiguousarray(I[None])).to("cuda"), [0]).cpu().numpy()[0]
+    fams = green.FAMILIES if basis == 5 else ["M0"]
+    for l in np.random.default_rng(seed).choice(p.K, size=nobs, replace=False):
+        off = P - P[l]
+        fam = {n: green.family_values(n, off) for n in fams}
+        c = op.material_c(F, S0, lamv[l])
+        for b in range(basis):
+            conv, mag = 0, 0
+            for a in range(basis):
+                terms = op.block_terms(names[b], names[a])
+                if not terms:
+                    continue
+                row = sum(coef * fam[n] for coef, n in terms)
+                conv = conv + row @ I[a]
+                mag += np.sum(row ** 2) * np.mean(np.abs(I[a]) ** 2)
+            diag = sum(op.mass_coefficient(names[b], names[a]) * I[a, l] for a in range(basis)) * c / DX
+            ref = s * conv + diag
+            scale = abs(s) * np.sqrt(mag) + abs(ref)
+            e = abs(ZI[b, l] - ref) / scale
+            assert e <= 10 * tol, (l, b, e)
+
+
+def test_meander_port_solve():
+    mask, ports = wl.meander_with_port(1001)
+    p = _problem(mask, ports, 5, 1e-8)
+    X, Y, info = p.solve(0, rre=1e-8, restart=50)
+    print(f"[configs] meander K={p.K} N={p.N}: {info['iterations']} its, inner {info['inner_iterations']}, "
+          f"relres {info['relres']:.2e}", flush=True)
+    assert info["converged"] and info["relres"] <= 1e-8
+    _check_solution(p, mask, 5, ports, X, Y, 1e-8, [0])
+    I = X[0, :5 * p.K].cpu().numpy().reshape(5, p.K)
+    _check_rows(p, mask, 5, I, 1e-8, LAM)
+    Zp = 1 / Y[0, 0]
+    w = 2 * np.pi * F
+    assert Zp.real > 0 and Zp.imag > 0          # resistive and inductive
+    # without the linear functions no current turns the meander's corners
+    p3 = _problem(mask, ports, 3, 1e-8)
+    _, Y3, _ = p3.solve(0, rre=1e-8, check=False)
+    assert abs(Y3[0, 0]) <= 1e-6 * abs(Y[0, 0])
+    print(f"[configs] meander L = {Zp.imag / w * 1e12:.3f} pH", flush=True)
+
+
+def test_strips_over_ground_sixteen_ports_fp32_refined():
+    mask, ports = wl.strips_over_ground_with_ports(1002)
+    p = _problem(mask, ports, 5, 1e-6)
+    X, Y, info = p.solve(0, rre=1e-8, restart=50, refine=True)
+    print(f"[configs] strips K={p.K} N={p.N}: {info['iterations']} its, inner {info['inner_iterations']}, "
+          f"refinement {info['refinement_steps']}, relres {info['relres']:.2e}", flush=True)
+    assert info["converged"] and info["relres"] <= 1e-8
+    assert np.abs(Y - Y.T).max() <= 1e-7 * np.abs(Y).max()      # reciprocity
+    _check_solution(p, mask, 5, ports, X, Y, 1e-8, [0, 7, 15])
+    I = X[3, :5 * p.K].cpu().numpy().reshape(5, p.K)
+    _check_rows(p, mask, 5, I, 1e-6, LAM, nobs=1, seed=3)
+    L = np.linalg.inv(Y).imag / (2 * np.pi * F)
+    assert np.all(np.diag(L) > 0)
+    assert np.all(np.linalg.eigvalsh(0.5 * (L + L.T)) > 0)      # passive: inductance matrix SPD
+
+
+@pytest.mark.slow
+def test_bend_gradient_vs_central_differences():
+    mask, ports = wl.sharp_bend_with_port(1003)
+    K = int(mask.sum())
+    lam = wl.rng(1004).uniform(80e-9, 120e-9, K)
+    pvec = lam ** -2.0
+    p = _problem(mask, ports, 5, 1e-8, lam)
+    from paper_2105_08627_amd.autograd import port_inductance
+    pt = torch.tensor(pvec, dtype=torch.float64, device="cuda", requires_grad=True)
+    L = port_inductance(p, pt, S0, F, rre=1e-12)
+    L[0, 0].backward()
+    g = pt.grad.cpu().numpy()
+    print(f"[configs] bend K={K}: L = {L[0, 0].item() * 1e12:.4f} pH, max |dL/dp| {np.abs(g).max():.3e}", flush=True)
+
+    def L_of(pv):
+        p.set_material([F], np.full(K, S0), pv ** -0.5, per_voxel=True)
+        _, Yv, info = p.solve(0, rre=1e-12, maxit=2000)
+        assert info["converged"]
+        return (1 / Yv[0, 0]).imag / (2 * np.pi * F)
+
+    # 24 voxels drawn uniformly (mostly ground plane, small gradients) and 8
+    # from the 5 % of largest |dL/dp| (the current-carrying ones)
+    rng = np.random.default_rng(1005)
+    top = np.argsort(-np.abs(g))[:K // 20]
+    ks = np.concatenate([rng.choice(K, size=24, replace=False), rng.choice(top, size=8, replace=False)])
+    L0 = L[0, 0].item()
+    for k in ks:
+        h = 1e-4 * pvec[k]
+        up, dn = pvec.copy(), pvec.copy()
+        up[k] += h
+        dn[k] -= h
+        fd = (L_of(up) - L_of(dn)) / (2 * h)
+        # each L is accurate to about rre * L, so the difference quotient to rre * L / h
+        assert abs(g[k] - fd) <= 1e-3 * abs(g[k]) + 1e-12 * L0 / h, (k, g[k], fd)

@@ -39,9 +39,23 @@ def random_mask(seed, Kx, Ky, Kz, fill=0.5):
     return m
 
 
-def meander(seed, Kx=64, Ky=64, Kz=16, width=4, thick=2, gap=4, z0=7):
-    """Meander thin-film inductor: ``n`` horizontal lanes joined alternately at
-    the left and right ends (5-7 lanes, seeded)."""
+def compact_index(mask):
+    """Compact voxel numbering of a [Kz, Ky, Kx] mask (x fastest, then y, then
+    z): array of the same shape, -1 at empty voxels."""
+    idx = np.full(mask.shape, -1, dtype=np.int64)
+    nz = mask.reshape(-1) != 0
+    idx.reshape(-1)[nz] = np.arange(int(nz.sum()))
+    return idx
+
+
+def _face_list(mask, region, face):
+    """(compact voxel index, face code) for the non-empty voxels of the
+    [z, y, x] slice `region`."""
+    idx = compact_index(mask)[region]
+    return [(int(k), face) for k in idx.reshape(-1) if k >= 0]
+
+
+def _meander(seed, Kx, Ky, Kz, width, thick, gap, z0):
     g = rng(seed)
     m = np.zeros((Kz, Ky, Kx), dtype=np.uint8)
     nl = int(g.integers(5, 8))
@@ -56,7 +70,34 @@ def meander(seed, Kx=64, Ky=64, Kz=16, width=4, thick=2, gap=4, z0=7):
                 m[z0:z0 + thick, ys:ys + pitch + width, x1 - width:x1] = 1
             else:
                 m[z0:z0 + thick, ys:ys + pitch + width, x0:x0 + width] = 1
-    return m
+    # terminals: the free ends of the first and the last lane
+    zs, first = slice(z0, z0 + thick), slice(y0, y0 + width)
+    last = slice(y0 + (nl - 1) * pitch, y0 + (nl - 1) * pitch + width)
+    plus = _face_list(m, (zs, first, slice(x0, x0 + 1)), 0)
+    if (nl - 2) % 2 == 0:   # last lane joined on the right: free end on the left
+        minus = _face_list(m, (zs, last, slice(x0, x0 + 1)), 0)
+    else:
+        minus = _face_list(m, (zs, last, slice(x1 - 1, x1)), 1)
+    return m, [(plus, minus)]
+
+
+def meander(seed, Kx=64, Ky=64, Kz=16, width=4, thick=2, gap=4, z0=7):
+    """Meander thin-film inductor: ``n`` horizontal lanes joined alternately at
+    the left and right ends (5-7 lanes, seeded)."""
+    return _meander(seed, Kx, Ky, Kz, width, thick, gap, z0)[0]
+
+
+def meander_with_port(seed, Kx=64, Ky=64, Kz=16, width=4, thick=2, gap=4, z0=7):
+    """The meander and its one port: + terminal on the outer end face of the
+    first lane, - terminal on the free end face of the last lane."""
+    return _meander(seed, Kx, Ky, Kz, width, thick, gap, z0)
+
+
+def _gap_port(m, ys, xs, zvia, zgnd):
+    """Port across a one-voxel gap: + on the -z faces of the via voxels at
+    z = zvia, - on the +z faces of the ground voxels at z = zgnd below."""
+    return (_face_list(m, (slice(zvia, zvia + 1), ys, xs), 4),
+            _face_list(m, (slice(zgnd, zgnd + 1), ys, xs), 5))
 
 
 def ground_with_holes(g, m, z0, z1, nholes, hmin, hmax):
@@ -68,14 +109,11 @@ def ground_with_holes(g, m, z0, z1, nholes, hmin, hmax):
         m[z0:z1, y:y + hy, x:x + hx] = 0
 
 
-def strips_over_ground(seed, Kx=128, Ky=128, Kz=64):
-    """Multi-strip inductor over a ground slab with 16 random rectangular holes;
-    16 strips (width 4, thickness 2) at z in [12,14), each shorted to ground
-    by a via at one end and ending in a via with a one-voxel port gap above
-    the ground at the other."""
+def _strips_over_ground(seed, Kx, Ky, Kz):
     g = rng(seed)
     m = np.zeros((Kz, Ky, Kx), dtype=np.uint8)
     ground_with_holes(g, m, 2, 6, 16, 4, 16)
+    feet = []
     for i in range(16):
         y = 4 + i * (Ky - 8) // 16
         length = int(g.integers(40, 101))
@@ -85,11 +123,25 @@ def strips_over_ground(seed, Kx=128, Ky=128, Kz=64):
         m[7:12, y:y + 4, x + length - 4:x + length] = 1  # port via, gap at z=6
         m[2:6, y:y + 4, x:x + 4] = 1              # keep ground under the vias
         m[2:6, y:y + 4, x + length - 4:x + length] = 1
-    return m
+        feet.append((slice(y, y + 4), slice(x + length - 4, x + length)))
+    return m, [_gap_port(m, ys, xs, 7, 5) for ys, xs in feet]
 
 
-def sharp_bend(seed, Kx=96, Ky=96, Kz=32, width=6, thick=2):
-    """90-degree sharp bend strip over a ground plane (Sec. III.C stand-in)."""
+def strips_over_ground(seed, Kx=128, Ky=128, Kz=64):
+    """Multi-strip inductor over a ground slab with 16 random rectangular holes;
+    16 strips (width 4, thickness 2) at z in [12,14), each shorted to ground
+    by a via at one end and ending in a via with a one-voxel port gap above
+    the ground at the other."""
+    return _strips_over_ground(seed, Kx, Ky, Kz)[0]
+
+
+def strips_over_ground_with_ports(seed, Kx=128, Ky=128, Kz=64):
+    """The strips and their 16 ports, one across each via gap (+ on the via's
+    bottom faces, - on the ground's top faces below it)."""
+    return _strips_over_ground(seed, Kx, Ky, Kz)
+
+
+def _sharp_bend(seed, Kx, Ky, Kz, width, thick):
     g = rng(seed)
     m = np.zeros((Kz, Ky, Kx), dtype=np.uint8)
     m[2:6, :, :] = 1
@@ -99,7 +151,17 @@ def sharp_bend(seed, Kx=96, Ky=96, Kz=32, width=6, thick=2):
     m[zs:zs + thick, 8:c + width, c:c + width] = 1
     m[6:zs, c:c + width, 8:8 + width] = 1          # shorted via
     m[7:zs, 8:8 + width, c:c + width] = 1          # port via, gap at z=6
-    return m
+    return m, [_gap_port(m, slice(8, 8 + width), slice(c, c + width), 7, 5)]
+
+
+def sharp_bend(seed, Kx=96, Ky=96, Kz=32, width=6, thick=2):
+    """90-degree sharp bend strip over a ground plane (Sec. III.C stand-in)."""
+    return _sharp_bend(seed, Kx, Ky, Kz, width, thick)[0]
+
+
+def sharp_bend_with_port(seed, Kx=96, Ky=96, Kz=32, width=6, thick=2):
+    """The bend and its port across the via gap at the end of the y arm."""
+    return _sharp_bend(seed, Kx, Ky, Kz, width, thick)
 
 
 def manhattan_layer(g, m, z0, z1, fill, w=4):
