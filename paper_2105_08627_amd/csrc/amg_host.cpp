@@ -7,12 +7,14 @@
 // prolongation P.  Coarsening stops at kAmgCoarse nodes or when a level no
 // longer shrinks.
 //
-// With the linear basis functions the coarse graphs turn star-shaped (many
-// nodes whose only coupling is to one hub), and strict pairing stalls: a hub
-// takes one partner per pass and the rest stay single.  So a node left
+// With the linear basis functions S has positive couplings (between opposite
+// faces of a voxel) and its coarse graphs turn star-shaped (many nodes whose
+// only coupling is to one hub): strict pairing stalls, since a hub takes one
+// partner per pass and the rest stay single.  For such an S a node left
 // single by a pass joins the pair of its dominant neighbour (at least half of
-// its total negative coupling).  Its smooth-mode value follows that
-// neighbour's, so the merge keeps the coarse space's quality.
+// its total negative coupling); its smooth-mode value follows that
+// neighbour's, so the merge keeps the coarse space's quality.  An S without
+// positive couplings (piecewise-constant functions only) is paired strictly.
 //
 // Rows without couplings (Dirichlet nodes, which keep identity rows, and the
 // one-node remainders of isolated lines) are solved exactly by their diagonal
@@ -39,7 +41,7 @@ bool decoupled_row(const AmgLevel& L, int i) {
 // so it is left out of the coarser levels).  Candidates of i: unmatched j with
 // -a_ij >= beta * max_k(-a_ik); i is paired with the candidate of the most
 // negative coupling, else left single (and may then join a neighbour's pair).
-int pair_once(const AmgLevel& L, std::vector<int>& agg, bool drop) {
+int pair_once(const AmgLevel& L, std::vector<int>& agg, bool drop, bool join) {
   const int n = L.n;
   agg.assign(n, -2);  // -2 unvisited
   int nc = 0;
@@ -69,6 +71,7 @@ int pair_once(const AmgLevel& L, std::vector<int>& agg, bool drop) {
     if (best >= 0) agg[best] = nc;
     ++nc;
   }
+  if (!join) return nc;
   // single nodes join the pair of their dominant neighbour (pairs formed in
   // this pass only, so no chains), then aggregates are renumbered densely
   std::vector<int> size(nc, 0), into(nc, -1);
@@ -182,15 +185,25 @@ int amg_setup(AmgLevel fine, std::vector<AmgLevel>& levels, std::vector<std::vec
   levels.clear();
   aggs.clear();
   levels.push_back(std::move(fine));
+  bool join = false;
+  {
+    const AmgLevel& F = levels[0];
+    for (int i = 0; i < F.n && !join; ++i)
+      for (int q = F.rptr[i]; q < F.rptr[i + 1]; ++q)
+        if (F.col[q] != i && F.val[q] > 0) {
+          join = true;
+          break;
+        }
+  }
   while (levels.back().n > kAmgCoarse && (int)levels.size() < kAmgMaxLevels) {
     const AmgLevel& A = levels.back();
     int coupled = 0;
     for (int i = 0; i < A.n; ++i) coupled += decoupled_row(A, i) ? 0 : 1;
     // two pairing passes: aggregates of up to four nodes; decoupled rows drop out
     std::vector<int> a1, a2;
-    const int n1 = pair_once(A, a1, true);
+    const int n1 = pair_once(A, a1, true, join);
     AmgLevel A1 = galerkin(A, a1, n1);
-    const int n2 = pair_once(A1, a2, false);
+    const int n2 = pair_once(A1, a2, false, join);
     std::vector<int> agg(A.n);
     for (int i = 0; i < A.n; ++i) agg[i] = a1[i] >= 0 ? a2[a1[i]] : -1;
     if (n2 == 0 || n2 > 0.9 * coupled) break;  // nothing left, or no longer coarsening

@@ -89,17 +89,39 @@ __global__ void k_pre_rhs(int nrhs, long long N, int CK, int M, const int* __res
   }
 }
 
+// The sparse products of the Schur solve take one row for up to kRowRhs
+// right-hand sides per thread: the row's entries are read once and the
+// gathers of the right-hand sides are independent (a missing right-hand
+// side's index is clamped to the last one, so every load is unconditional;
+// only the stores are masked).  Each element sums in the row's order.
+constexpr int kRowRhs = 8;
+
 // u = Y^-1 A^T v (basis-sized), v a node vector with zero Dirichlet entries
 __global__ void k_s_half(int nrhs, int CK, int M, const int* __restrict__ cptr, const int* __restrict__ crow,
                          const double* __restrict__ cval, const double* __restrict__ ydiag,
                          const double2* __restrict__ v, double2* __restrict__ u) {
-  GRID_STRIDE(i, (long long)CK * nrhs) {
-    const long long r = i / CK;
+  const int nchunk = (nrhs + kRowRhs - 1) / kRowRhs;
+  GRID_STRIDE(i, (long long)CK * nchunk) {
     const int b = (int)(i % CK);
-    const double2* vr = v + r * M;
-    double2 acc = make_double2(0, 0);
-    for (int q = cptr[b]; q < cptr[b + 1]; ++q) acc = zadd(acc, zscale(vr[crow[q]], cval[q]));
-    u[r * CK + b] = zscale(acc, 1.0 / ydiag[b]);
+    const int r0 = (int)(i / CK) * kRowRhs;
+    const int last = nrhs - 1 - r0;  // >= 0
+    long long off[kRowRhs];
+    double2 acc[kRowRhs];
+#pragma unroll
+    for (int j = 0; j < kRowRhs; ++j) {
+      off[j] = (long long)(r0 + min(j, last)) * M;
+      acc[j] = make_double2(0, 0);
+    }
+    for (int q = cptr[b]; q < cptr[b + 1]; ++q) {
+      const int row = crow[q];
+      const double a = cval[q];
+#pragma unroll
+      for (int j = 0; j < kRowRhs; ++j) acc[j] = zadd(acc[j], zscale(v[off[j] + row], a));
+    }
+    const double yi = 1.0 / ydiag[b];
+#pragma unroll
+    for (int j = 0; j < kRowRhs; ++j)
+      if (j <= last) u[(long long)(r0 + j) * CK + b] = zscale(acc[j], yi);
   }
 }
 
@@ -107,13 +129,28 @@ __global__ void k_s_half(int nrhs, int CK, int M, const int* __restrict__ cptr, 
 __global__ void k_s_full(int nrhs, int CK, int M, const int* __restrict__ rptr, const int* __restrict__ rcol,
                          const double* __restrict__ rval, const uint8_t* __restrict__ freem,
                          const double2* __restrict__ u, double2* __restrict__ q) {
-  GRID_STRIDE(i, (long long)M * nrhs) {
-    const long long r = i / M;
+  const int nchunk = (nrhs + kRowRhs - 1) / kRowRhs;
+  GRID_STRIDE(i, (long long)M * nchunk) {
     const int m = (int)(i % M);
-    double2 acc = make_double2(0, 0);
+    const int r0 = (int)(i / M) * kRowRhs;
+    const int last = nrhs - 1 - r0;  // >= 0
+    long long off[kRowRhs];
+    double2 acc[kRowRhs];
+#pragma unroll
+    for (int j = 0; j < kRowRhs; ++j) {
+      off[j] = (long long)(r0 + min(j, last)) * CK;
+      acc[j] = make_double2(0, 0);
+    }
     if (freem[m])
-      for (int k = rptr[m]; k < rptr[m + 1]; ++k) acc = zadd(acc, zscale(u[r * CK + rcol[k]], rval[k]));
-    q[r * M + m] = acc;
+      for (int k = rptr[m]; k < rptr[m + 1]; ++k) {
+        const int col = rcol[k];
+        const double a = rval[k];
+#pragma unroll
+        for (int j = 0; j < kRowRhs; ++j) acc[j] = zadd(acc[j], zscale(u[off[j] + col], a));
+      }
+#pragma unroll
+    for (int j = 0; j < kRowRhs; ++j)
+      if (j <= last) q[(long long)(r0 + j) * M + m] = acc[j];
   }
 }
 
@@ -240,23 +277,19 @@ __global__ void k_amg_smooth0(int nrhs, int n, const double* __restrict__ wdinv,
                               double2* __restrict__ x) {
   GRID_STRIDE(i, (long long)n * nrhs) x[i] = zscale(b[i], wdinv[i % n]);
 }
-// r = b - A x.  One thread takes a row for up to kResidRhs right-hand sides:
-// the row's entries are read once and the gathers of the right-hand sides
-// are independent (the index of a missing one is clamped to the last, so
-// every load is unconditional; only the stores are masked).
-constexpr int kResidRhs = 8;
+// r = b - A x, one row for up to kRowRhs right-hand sides per thread.
 __global__ void k_amg_resid(int nrhs, int n, const int* __restrict__ rptr, const int* __restrict__ col,
                             const double* __restrict__ val, const double2* __restrict__ b,
                             const double2* __restrict__ x, double2* __restrict__ r) {
-  const int nchunk = (nrhs + kResidRhs - 1) / kResidRhs;
+  const int nchunk = (nrhs + kRowRhs - 1) / kRowRhs;
   GRID_STRIDE(i, (long long)n * nchunk) {
     const int row = (int)(i % n);
-    const int r0 = (int)(i / n) * kResidRhs;
+    const int r0 = (int)(i / n) * kRowRhs;
     const int last = nrhs - 1 - r0;  // >= 0
-    long long off[kResidRhs];
-    double2 acc[kResidRhs];
+    long long off[kRowRhs];
+    double2 acc[kRowRhs];
 #pragma unroll
-    for (int j = 0; j < kResidRhs; ++j) {
+    for (int j = 0; j < kRowRhs; ++j) {
       off[j] = (long long)(r0 + min(j, last)) * n;
       acc[j] = b[off[j] + row];
     }
@@ -264,10 +297,10 @@ __global__ void k_amg_resid(int nrhs, int n, const int* __restrict__ rptr, const
       const int c = col[q];
       const double v = val[q];
 #pragma unroll
-      for (int j = 0; j < kResidRhs; ++j) acc[j] = zsub(acc[j], zscale(x[off[j] + c], v));
+      for (int j = 0; j < kRowRhs; ++j) acc[j] = zsub(acc[j], zscale(x[off[j] + c], v));
     }
 #pragma unroll
-    for (int j = 0; j < kResidRhs; ++j)
+    for (int j = 0; j < kRowRhs; ++j)
       if (j <= last) r[off[j] + row] = acc[j];
   }
 }
@@ -469,8 +502,8 @@ int nblocks(long long n) {
   long long b = (n + 255) / 256;
   return (int)std::max(1LL, std::min(b, 8192LL));
 }
-// grid of k_amg_resid: one thread per row and group of kResidRhs right-hand sides
-int resid_blocks(int n, int nrhs) { return nblocks((long long)n * ((nrhs + kResidRhs - 1) / kResidRhs)); }
+// grid of the row kernels: one thread per row and group of kRowRhs right-hand sides
+int resid_blocks(int n, int nrhs) { return nblocks((long long)n * ((nrhs + kRowRhs - 1) / kRowRhs)); }
 
 constexpr int kDotBlocks = 256;
 
@@ -603,9 +636,9 @@ void pcg_block(Ctx& c, hipStream_t s) {
   svh_problem* p = c.p;
   const long long nM = (long long)c.M * c.nr;
   for (int k = 0; k < kPcgBlock; ++k) {
-    hipLaunchKernelGGL(k_s_half, dim3(nblocks((long long)c.CK * c.nr)), dim3(256), 0, s, c.nr, c.CK, c.M,
+    hipLaunchKernelGGL(k_s_half, dim3(resid_blocks(c.CK, c.nr)), dim3(256), 0, s, c.nr, c.CK, c.M,
                        p->d_cptr, p->d_crow, p->d_cval, p->d_ydiag, c.w.P, c.w.U);
-    hipLaunchKernelGGL(k_s_full, dim3(nblocks(nM)), dim3(256), 0, s, c.nr, c.CK, c.M, p->d_rptr, p->d_rcol,
+    hipLaunchKernelGGL(k_s_full, dim3(resid_blocks(c.M, c.nr)), dim3(256), 0, s, c.nr, c.CK, c.M, p->d_rptr, p->d_rcol,
                        p->d_rval, p->d_free, c.w.U, c.w.Q);
     mdot(c, c.M, 1, c.w.P, 0, c.M, c.w.Q, c.M, c.w.pq, s);
     hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(256), 0, s, c.nr, c.w.rho, c.w.pq, c.w.alpha);
