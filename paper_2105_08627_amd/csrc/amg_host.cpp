@@ -180,21 +180,19 @@ AmgLevel schur_matrix(const Topology& t, const std::vector<char>& dirichlet, con
   return S;
 }
 
+bool has_positive_coupling(const AmgLevel& A) {
+  for (int i = 0; i < A.n; ++i)
+    for (int q = A.rptr[i]; q < A.rptr[i + 1]; ++q)
+      if (A.col[q] != i && A.val[q] > 0) return true;
+  return false;
+}
+
 int amg_setup(AmgLevel fine, std::vector<AmgLevel>& levels, std::vector<std::vector<int>>& aggs,
               std::vector<double>& coarse_inv) {
   levels.clear();
   aggs.clear();
   levels.push_back(std::move(fine));
-  bool join = false;
-  {
-    const AmgLevel& F = levels[0];
-    for (int i = 0; i < F.n && !join; ++i)
-      for (int q = F.rptr[i]; q < F.rptr[i + 1]; ++q)
-        if (F.col[q] != i && F.val[q] > 0) {
-          join = true;
-          break;
-        }
-  }
+  const bool join = has_positive_coupling(levels[0]);
   while (levels.back().n > kAmgCoarse && (int)levels.size() < kAmgMaxLevels) {
     const AmgLevel& A = levels.back();
     int coupled = 0;

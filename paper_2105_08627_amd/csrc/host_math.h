@@ -40,6 +40,9 @@ constexpr int kAmgCoarse = 256;      // stop coarsening at this many nodes
 constexpr int kAmgCoarseMax = 1024;  // largest coarsest level inverted densely
 constexpr int kAmgMaxLevels = 24;
 AmgLevel schur_matrix(const Topology& t, const std::vector<char>& dirichlet, const std::vector<double>& ydiag);
+// true if some off-diagonal entry is positive (S is then not an M-matrix: the
+// linear basis functions couple opposite faces of a voxel positively)
+bool has_positive_coupling(const AmgLevel& A);
 // levels[0] = fine; aggs[l][i] = aggregate (node of level l + 1) of node i of
 // level l, or -1 for a row without couplings (left out of level l + 1).  Returns how the coarsest level is solved: kAmgCoarseDense
 // (coarse_inv = its dense inverse), kAmgCoarseDiagonal (it is diagonal),

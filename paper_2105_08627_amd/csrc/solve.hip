@@ -96,6 +96,33 @@ __global__ void k_pre_rhs(int nrhs, long long N, int CK, int M, const int* __res
 // only the stores are masked).  Each element sums in the row's order.
 constexpr int kRowRhs = 8;
 
+// acc[j] += sgn * sum_q a[q] * x[off[j] + c[q]] over q in [q0, q1), four
+// entries at a time so that their index loads and gathers are in flight
+// together (the additions keep the entry order)
+template <int SGN>
+__device__ __forceinline__ void row_gather(int q0, int q1, const int* __restrict__ c, const double* __restrict__ a,
+                                           const double2* __restrict__ x, const long long* off, double2* acc) {
+  int q = q0;
+  for (; q + 4 <= q1; q += 4) {
+    const int c0 = c[q], c1 = c[q + 1], c2 = c[q + 2], c3 = c[q + 3];
+    const double a0 = SGN * a[q], a1 = SGN * a[q + 1], a2 = SGN * a[q + 2], a3 = SGN * a[q + 3];
+#pragma unroll
+    for (int j = 0; j < kRowRhs; ++j) {
+      const double2 x0 = x[off[j] + c0], x1 = x[off[j] + c1], x2 = x[off[j] + c2], x3 = x[off[j] + c3];
+      acc[j] = zadd(acc[j], zscale(x0, a0));
+      acc[j] = zadd(acc[j], zscale(x1, a1));
+      acc[j] = zadd(acc[j], zscale(x2, a2));
+      acc[j] = zadd(acc[j], zscale(x3, a3));
+    }
+  }
+  for (; q < q1; ++q) {
+    const int cq = c[q];
+    const double aq = SGN * a[q];
+#pragma unroll
+    for (int j = 0; j < kRowRhs; ++j) acc[j] = zadd(acc[j], zscale(x[off[j] + cq], aq));
+  }
+}
+
 // u = Y^-1 A^T v (basis-sized), v a node vector with zero Dirichlet entries
 __global__ void k_s_half(int nrhs, int CK, int M, const int* __restrict__ cptr, const int* __restrict__ crow,
                          const double* __restrict__ cval, const double* __restrict__ ydiag,
@@ -112,12 +139,7 @@ __global__ void k_s_half(int nrhs, int CK, int M, const int* __restrict__ cptr, 
       off[j] = (long long)(r0 + min(j, last)) * M;
       acc[j] = make_double2(0, 0);
     }
-    for (int q = cptr[b]; q < cptr[b + 1]; ++q) {
-      const int row = crow[q];
-      const double a = cval[q];
-#pragma unroll
-      for (int j = 0; j < kRowRhs; ++j) acc[j] = zadd(acc[j], zscale(v[off[j] + row], a));
-    }
+    row_gather<1>(cptr[b], cptr[b + 1], crow, cval, v, off, acc);
     const double yi = 1.0 / ydiag[b];
 #pragma unroll
     for (int j = 0; j < kRowRhs; ++j)
@@ -141,13 +163,7 @@ __global__ void k_s_full(int nrhs, int CK, int M, const int* __restrict__ rptr, 
       off[j] = (long long)(r0 + min(j, last)) * CK;
       acc[j] = make_double2(0, 0);
     }
-    if (freem[m])
-      for (int k = rptr[m]; k < rptr[m + 1]; ++k) {
-        const int col = rcol[k];
-        const double a = rval[k];
-#pragma unroll
-        for (int j = 0; j < kRowRhs; ++j) acc[j] = zadd(acc[j], zscale(u[off[j] + col], a));
-      }
+    if (freem[m]) row_gather<1>(rptr[m], rptr[m + 1], rcol, rval, u, off, acc);
 #pragma unroll
     for (int j = 0; j < kRowRhs; ++j)
       if (j <= last) q[(long long)(r0 + j) * M + m] = acc[j];
@@ -293,12 +309,7 @@ __global__ void k_amg_resid(int nrhs, int n, const int* __restrict__ rptr, const
       off[j] = (long long)(r0 + min(j, last)) * n;
       acc[j] = b[off[j] + row];
     }
-    for (int q = rptr[row]; q < rptr[row + 1]; ++q) {
-      const int c = col[q];
-      const double v = val[q];
-#pragma unroll
-      for (int j = 0; j < kRowRhs; ++j) acc[j] = zsub(acc[j], zscale(x[off[j] + c], v));
-    }
+    row_gather<-1>(rptr[row], rptr[row + 1], col, val, x, off, acc);
 #pragma unroll
     for (int j = 0; j < kRowRhs; ++j)
       if (j <= last) r[off[j] + row] = acc[j];

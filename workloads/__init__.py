@@ -100,30 +100,62 @@ def _gap_port(m, ys, xs, zvia, zgnd):
             _face_list(m, (slice(zgnd, zgnd + 1), ys, xs), 5))
 
 
-def ground_with_holes(g, m, z0, z1, nholes, hmin, hmax):
+def ground_with_holes(g, m, z0, z1, nholes, hmin, hmax, keep=()):
+    """Ground slab z in [z0, z1) with nholes random rectangular holes; a hole
+    that would touch one of the `keep` rectangles (y0, y1, x0, x1) grown by
+    one voxel is drawn again."""
     Kz, Ky, Kx = m.shape
     m[z0:z1, :, :] = 1
-    for _ in range(nholes):
+    made = 0
+    while made < nholes:
         hx, hy = int(g.integers(hmin, hmax + 1)), int(g.integers(hmin, hmax + 1))
         x, y = int(g.integers(0, Kx - hx)), int(g.integers(0, Ky - hy))
+        if any(y < y1 + 1 and y0 - 1 < y + hy and x < x1 + 1 and x0 - 1 < x + hx for y0, y1, x0, x1 in keep):
+            continue
         m[z0:z1, y:y + hy, x:x + hx] = 0
+        made += 1
+
+
+def _connected(m):
+    """True if the non-empty voxels form one face-connected piece."""
+    idx = np.argwhere(m)
+    if idx.size == 0:
+        return True
+    seen = np.zeros(m.shape, dtype=bool)
+    stack = [tuple(idx[0])]
+    seen[stack[0]] = True
+    count = 0
+    while stack:
+        z, y, x = stack.pop()
+        count += 1
+        for dz, dy, dx in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+            q = (z + dz, y + dy, x + dx)
+            if all(0 <= q[i] < m.shape[i] for i in range(3)) and m[q] and not seen[q]:
+                seen[q] = True
+                stack.append(q)
+    return count == len(idx)
 
 
 def _strips_over_ground(seed, Kx, Ky, Kz):
     g = rng(seed)
     m = np.zeros((Kz, Ky, Kx), dtype=np.uint8)
-    ground_with_holes(g, m, 2, 6, 16, 4, 16)
-    feet = []
+    strips = []
     for i in range(16):
         y = 4 + i * (Ky - 8) // 16
         length = int(g.integers(40, 101))
         x = int(g.integers(2, Kx - length - 2))
+        strips.append((y, x, length))
+    # the holes keep clear of the vias' footprints, so every strip returns
+    # through one connected ground
+    keep = [r for y, x, n in strips for r in ((y, y + 4, x, x + 4), (y, y + 4, x + n - 4, x + n))]
+    ground_with_holes(g, m, 2, 6, 16, 4, 16, keep)
+    feet = []
+    for y, x, length in strips:
         m[12:14, y:y + 4, x:x + length] = 1
         m[6:12, y:y + 4, x:x + 4] = 1             # shorted via
         m[7:12, y:y + 4, x + length - 4:x + length] = 1  # port via, gap at z=6
-        m[2:6, y:y + 4, x:x + 4] = 1              # keep ground under the vias
-        m[2:6, y:y + 4, x + length - 4:x + length] = 1
         feet.append((slice(y, y + 4), slice(x + length - 4, x + length)))
+    assert _connected(m)
     return m, [_gap_port(m, ys, xs, 7, 5) for ys, xs in feet]
 
 
