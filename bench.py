@@ -179,7 +179,7 @@ def bench_basis5(args, cfg, mask, fidx, dev):
     ya64, adj64 = bench_adjoint(p, x64, fidx, args.fp64_steps)
     adj_sym = (torch.linalg.vector_norm((ya64 - y64).flatten()) / torch.linalg.vector_norm(y64.flatten())).item()
     del ya32, ya64
-    log(f"[bench] adjoint fp32 {adj32['ms_per_step']:.3f} ms/step fp64 {adj64['ms_per_step']:.3f} ms/step "
+    log(f"[bench] basis5 adjoint fp32 {adj32['ms_per_step']:.3f} ms/step fp64 {adj64['ms_per_step']:.3f} ms/step "
         f"|Z^T x - Z x|/|Z x| {adj_sym:.1e}")
     Lx, Ly, _ = p.L
     # coupled z step: 12 z convolutions of complex data with real kernels per
@@ -194,6 +194,7 @@ def bench_basis5(args, cfg, mask, fidx, dev):
                         f"7 integral families, Tucker tol {args.tol:g}",
             "setup_s": t_setup, "tucker_s": t_tucker, "tucker_ranks": ranks.tolist(),
             **res, "rel_err_fp32_vs_fp64": rel,
+            "adjoint": {"fp32": adj32, "fp64": adj64, "rel_diff_vs_forward_fp64": adj_sym},
             "z_step_fp32": {"ms": zms, "tflops": zflops / (zms * 1e-3) / 1e12,
                             "alu_frac": zflops / (zms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
                             "hbm_gbs": by["pass_z_mul"] / (zms * 1e-3) / 1e9}}
