@@ -315,6 +315,31 @@ __global__ void k_amg_resid(int nrhs, int n, const int* __restrict__ rptr, const
       if (j <= last) r[off[j] + row] = acc[j];
   }
 }
+// r = b - A x on a small level, whose few rows leave most of the chip idle
+// with one thread per row: one wavefront per row instead.  Lane t takes
+// right-hand side t % 16 of the current group of 16 and the row's entries
+// t / 16, t / 16 + 4, ...; the four partial sums meet through lane exchanges.
+__global__ void k_amg_resid_w(int nrhs, int n, const int* __restrict__ rptr, const int* __restrict__ col,
+                              const double* __restrict__ val, const double2* __restrict__ b,
+                              const double2* __restrict__ x, double2* __restrict__ r) {
+  const int lane = threadIdx.x & 63, rl = lane & 15, g = lane >> 4;
+  const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+  for (long long row = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; row < n; row += nwaves) {
+    const int q0 = rptr[row], q1 = rptr[row + 1];
+    for (int r0 = 0; r0 < nrhs; r0 += 16) {
+      const long long off = (long long)min(r0 + rl, nrhs - 1) * n;
+      double2 acc = make_double2(0, 0);
+      for (int q = q0 + g; q < q1; q += 4) acc = zadd(acc, zscale(x[off + col[q]], val[q]));
+      acc.x += __shfl_xor(acc.x, 16);
+      acc.y += __shfl_xor(acc.y, 16);
+      acc.x += __shfl_xor(acc.x, 32);
+      acc.y += __shfl_xor(acc.y, 32);
+      if (g == 0 && r0 + rl < nrhs) r[off + row] = zsub(b[off + row], acc);
+    }
+  }
+}
+constexpr int kWaveRowLevel = 32768;  // levels with fewer rows take a wavefront per row
+
 __global__ void k_amg_jacobi(int nrhs, int n, const double* __restrict__ wdinv, const double2* __restrict__ r,
                              double2* __restrict__ x) {
   GRID_STRIDE(i, (long long)n * nrhs) x[i] = zadd(x[i], zscale(r[i], wdinv[i % n]));
@@ -515,6 +540,16 @@ int nblocks(long long n) {
 }
 // grid of the row kernels: one thread per row and group of kRowRhs right-hand sides
 int resid_blocks(int n, int nrhs) { return nblocks((long long)n * ((nrhs + kRowRhs - 1) / kRowRhs)); }
+
+// r = b - A x on one multigrid level (wavefront per row on small levels)
+void amg_resid(const svh_problem::AmgDev& L, int nr, const double2* b, const double2* x, double2* r, hipStream_t s) {
+  if (L.n < kWaveRowLevel)
+    hipLaunchKernelGGL(k_amg_resid_w, dim3(nblocks(64LL * L.n)), dim3(256), 0, s, nr, L.n, L.rptr, L.col, L.val, b, x,
+                       r);
+  else
+    hipLaunchKernelGGL(k_amg_resid, dim3(resid_blocks(L.n, nr)), dim3(256), 0, s, nr, L.n, L.rptr, L.col, L.val, b, x,
+                       r);
+}
 
 constexpr int kDotBlocks = 256;
 
@@ -804,15 +839,14 @@ void vcycle(Ctx& c, const double2* b0, double2* x0, hipStream_t s) {
       } else {  // diagonal matrix (exact), or damped Jacobi sweeps
         hipLaunchKernelGGL(k_amg_smooth0, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, b, x);
         for (int k = 1; k < (p->amg_coarse == kAmgCoarseJacobi ? kAmgCoarseSweeps : 1); ++k) {
-          hipLaunchKernelGGL(k_amg_resid, dim3(resid_blocks(L.n, nr)), dim3(256), 0, s, nr, L.n, L.rptr, L.col, L.val, b, x,
-                             L.r);
+          amg_resid(L, nr, b, x, L.r, s);
           hipLaunchKernelGGL(k_amg_jacobi, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, L.r, x);
         }
       }
       break;
     }
     hipLaunchKernelGGL(k_amg_smooth0, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, b, x);
-    hipLaunchKernelGGL(k_amg_resid, dim3(resid_blocks(L.n, nr)), dim3(256), 0, s, nr, L.n, L.rptr, L.col, L.val, b, x, L.r);
+    amg_resid(L, nr, b, x, L.r, s);
     auto& Cl = p->amg[l + 1];
     hipLaunchKernelGGL(k_amg_restrict, dim3(nblocks((long long)Cl.n * nr)), dim3(256), 0, s, nr, L.n, Cl.n, L.mptr,
                        L.mem, L.r, Cl.b);
@@ -824,7 +858,7 @@ void vcycle(Ctx& c, const double2* b0, double2* x0, hipStream_t s) {
     double2* x = l ? L.x : x0;
     const long long n = (long long)L.n * nr;
     hipLaunchKernelGGL(k_amg_prolong, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, Cl.n, L.agg, Cl.x, x);
-    hipLaunchKernelGGL(k_amg_resid, dim3(resid_blocks(L.n, nr)), dim3(256), 0, s, nr, L.n, L.rptr, L.col, L.val, b, x, L.r);
+    amg_resid(L, nr, b, x, L.r, s);
     hipLaunchKernelGGL(k_amg_jacobi, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, L.r, x);
   }
 }
