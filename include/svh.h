@@ -100,7 +100,10 @@ svh_status svh_setup_tensors(svh_problem* p, void* stream);
  *                        Gauss-Legendre on the 8 polynomial boxes of the
  *                        overlap-weighted 3D form, point counts by distance
  *                        to the singular point; the 8 offsets whose boxes
- *                        touch it by Duffy pyramids on the host;
+ *                        touch it on the host, each box's monomial integrals
+ *                        reduced exactly to regular face integrals (Euler's
+ *                        relation for homogeneous functions and the
+ *                        divergence theorem);
  *  SVH_GREEN_CLOSED_FORM M0 from the closed-form Coulomb box-box potential in
  *                        binary128 on the host (svh_green_toeplitz); the M1/M2
  *                        families still by quadrature.
@@ -162,8 +165,8 @@ svh_status svh_get_toeplitz(const svh_problem* p, double* T_host);
  *   family 4-6  M2_a = int int u_a u'_a g
  * Family 0 is the closed form of svh_green_toeplitz; families 1-6 (basis 5
  * only, EINVAL otherwise) are computed by Gauss-Legendre quadrature of the
- * overlap-weighted 3D form on the device (Duffy pyramids on the host for the
- * offsets whose boxes touch the singular point). */
+ * overlap-weighted 3D form on the device (the offsets whose boxes touch the
+ * singular point on the host, reduced to regular face integrals). */
 svh_status svh_get_family(const svh_problem* p, int family, double* T_host);
 
 /* Tucker-compress the circulant spectrum (Algorithm 1, Sec. II.B.2) with

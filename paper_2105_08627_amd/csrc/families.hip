@@ -14,9 +14,8 @@
 // integral splits into 8 boxes.  Offsets with max |d_i| >= 2 keep the
 // singular point outside every box: tensor Gauss-Legendre per box with a
 // point count from the box's distance to it (this kernel).  The 8 offsets
-// with all d_i in {0, 1} are computed on the host: boxes with the singular
-// point at a corner use the Duffy pyramid map, which removes the 1/r
-// singularity.
+// with all d_i in {0, 1} are computed on the host by an exact reduction of
+// each box's monomial integrals to regular face integrals (below).
 #include <cmath>
 #include <vector>
 
@@ -149,64 +148,140 @@ __global__ void k_family_quad(int Kx, int Ky, int Kz, int nfam, double* __restri
   }
 }
 
+// ------------------------------------------------------------ near offsets --
+// The 8 offsets with all d_i in {0, 1} have boxes that touch the singular
+// point, so they are evaluated on the host by a reduction that needs no
+// singular quadrature.  On one box (s = d + v in [a_0, a_0+1] x [a_1, a_1+1] x
+// [a_2, a_2+1], integer a_i) the weight product is a polynomial in s, so the
+// integral is a sum of monomial integrals J(alpha) = int_box s^alpha / |s| ds.
+// s^alpha / |s| is homogeneous of degree k = |alpha| - 1, so div(s f) =
+// (3 + k) f (Euler), and the divergence theorem gives
+//   J(alpha) = 1 / (|alpha| + 2) * sum over faces of (s . n) int_face s^alpha / |s| dS.
+// Faces through s = 0 have s . n = 0 and drop out; every other face lies at
+// |s_k| >= 1 from the singular point, where the integrand is analytic, so a
+// tensor Gauss-Legendre rule on the face converges geometrically (24 x 24
+// points: below 1e-25 relative).  All of it runs in extended precision.
+
+// Gauss-Legendre nodes and weights on [0, 1] in extended precision.
+static void gauss_legendre01_ld(int n, long double* x, long double* w) {
+  for (int i = 0; i < n; ++i) {
+    long double z = cosl(3.141592653589793238462643383279502884L * (i + 0.75L) / (n + 0.5L));
+    long double dp = 0;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const long double pk = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1);
+      const long double dz = p1 / dp;
+      z -= dz;
+      if (fabsl(dz) < 1e-19L) break;
+    }
+    x[i] = (1 - z) / 2;
+    w[i] = 1 / ((1 - z * z) * dp * dp);
+  }
+}
+
+// Overlap weight of one axis as a cubic in s (ascending coefficients), on
+// the half of the box where sign(v) = sg, for v = s - d:
+//   kind 0 (powers (0,0)): t;  kind 1 ((0,1)): v t / 2;
+//   kind 2 ((1,1)): -t/4 + t^2/2 - t^3/6;  t = 1 - |v| = (1 + sg d) - sg s.
+static void weight_cubic(int kind, int sg, int d, long double out[4]) {
+  const long double t0 = 1.0L + sg * d, t1 = -sg;
+  for (int k = 0; k < 4; ++k) out[k] = 0;
+  if (kind == 0) {
+    out[0] = t0;
+    out[1] = t1;
+  } else if (kind == 1) {  // (s - d)(t0 + t1 s) / 2
+    out[0] = -d * t0 / 2;
+    out[1] = (t0 - d * t1) / 2;
+    out[2] = t1 / 2;
+  } else {
+    const long double T1[4] = {t0, t1, 0, 0};
+    const long double T2[4] = {t0 * t0, 2 * t0 * t1, t1 * t1, 0};
+    const long double T3[4] = {t0 * t0 * t0, 3 * t0 * t0 * t1, 3 * t0 * t1 * t1, t1 * t1 * t1};
+    for (int k = 0; k < 4; ++k) out[k] = -T1[k] / 4 + T2[k] / 2 - T3[k] / 6;
+  }
+}
+
+// J[(ax * 4 + ay) * 4 + az] = int over the box [a, a+1]^3 of s^alpha / |s|.
+static void monomial_integrals(const int a[3], long double J[64]) {
+  constexpr int n = 24;
+  static long double gx[n], gw[n];
+  static bool init = false;
+  if (!init) {
+    gauss_legendre01_ld(n, gx, gw);
+    init = true;
+  }
+  for (int m = 0; m < 64; ++m) J[m] = 0;
+  for (int k = 0; k < 3; ++k) {
+    const int i = (k + 1) % 3, j = (k + 2) % 3;
+    for (int side = 0; side < 2; ++side) {
+      const long double c = a[k] + side;  // face s_k = c, outward normal sign: + at a+1, - at a
+      const long double sn = side ? c : -c;  // s . n on this face
+      if (c == 0) continue;
+      // F[pk][pi][pj] = c^pk * int int s_i^pi s_j^pj / |s| over the face
+      long double F[4][4] = {};
+      for (int p = 0; p < n; ++p) {
+        const long double si = a[i] + gx[p];
+        for (int q = 0; q < n; ++q) {
+          const long double sj = a[j] + gx[q];
+          const long double g = gw[p] * gw[q] / sqrtl(c * c + si * si + sj * sj);
+          long double pi = 1;
+          for (int ei = 0; ei < 4; ++ei) {
+            long double pj = 1;
+            for (int ej = 0; ej < 4; ++ej) {
+              F[ei][ej] += g * pi * pj;
+              pj *= sj;
+            }
+            pi *= si;
+          }
+        }
+      }
+      long double ck = 1;
+      for (int ek = 0; ek < 4; ++ek) {
+        for (int ei = 0; ei < 4; ++ei)
+          for (int ej = 0; ej < 4; ++ej) {
+            int e[3];
+            e[k] = ek;
+            e[i] = ei;
+            e[j] = ej;
+            const int deg = ek + ei + ej;
+            J[(e[0] * 4 + e[1]) * 4 + e[2]] += sn * ck * F[ei][ej] / (deg + 2);
+          }
+        ck *= c;
+      }
+    }
+  }
+}
+
 // Host: all seven families at one offset with all d_i in {0, 1}.
 static void family_near(const int d[3], double out[kNFam]) {
-  static std::vector<double> xa, wa, xr, wr, xg, wg;
-  if (xa.empty()) {
-    xa.resize(24); wa.resize(24); xr.resize(16); wr.resize(16); xg.resize(20); wg.resize(20);
-    gauss_legendre01(24, xa.data(), wa.data());
-    gauss_legendre01(16, xr.data(), wr.data());
-    gauss_legendre01(20, xg.data(), wg.data());
-  }
-  long double acc[kNFam] = {0, 0, 0, 0, 0, 0, 0};  // extended precision: ~2e5 terms per family
-  auto add = [&](double vx, double vy, double vz, double wt) {
-    double ax[3], ay[3], az[3];
-    axis_weights(vx, ax[0], ax[1], ax[2]);
-    axis_weights(vy, ay[0], ay[1], ay[2]);
-    axis_weights(vz, az[0], az[1], az[2]);
-    acc[0] += wt * ax[0] * ay[0] * az[0];
-    acc[1] += wt * ax[1] * ay[0] * az[0];
-    acc[2] += wt * ax[0] * ay[1] * az[0];
-    acc[3] += wt * ax[0] * ay[0] * az[1];
-    acc[4] += wt * ax[2] * ay[0] * az[0];
-    acc[5] += wt * ax[0] * ay[2] * az[0];
-    acc[6] += wt * ax[0] * ay[0] * az[2];
-  };
+  // weight kind per family and axis: 0 (0,0), 1 (0,1), 2 (1,1)
+  static const int kind[kNFam][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1},
+                                     {2, 0, 0}, {0, 2, 0}, {0, 0, 2}};
+  long double acc[kNFam] = {0, 0, 0, 0, 0, 0, 0};
   for (int box = 0; box < 8; ++box) {
-    double lo[3], slo[3];
-    bool corner = true;
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = ((box >> a) & 1) ? 0.0 : -1.0;
-      slo[a] = d[a] + lo[a];
-      if (!(slo[a] == 0.0 || slo[a] == -1.0)) corner = false;  // 0 must be an endpoint
+    int a[3], sg[3];
+    for (int ax = 0; ax < 3; ++ax) {
+      const int lo = ((box >> ax) & 1) ? 0 : -1;  // v in [lo, lo + 1]
+      sg[ax] = lo == 0 ? 1 : -1;
+      a[ax] = d[ax] + lo;
     }
-    if (corner) {
-      // s-box is [0,1] or [-1,0] per axis; s = sign * t, t in [0,1]^3;
-      // pyramid `ax`: t = rho (.., 1 at ax, ..) scaled by (e1, e2) on the others
-      double sg[3];
-      for (int a = 0; a < 3; ++a) sg[a] = slo[a] == 0.0 ? 1.0 : -1.0;
-      for (int ax = 0; ax < 3; ++ax) {
-        const int o1 = (ax + 1) % 3, o2 = (ax + 2) % 3;
-        for (int ir = 0; ir < 16; ++ir)
-          for (int i1 = 0; i1 < 24; ++i1)
-            for (int i2 = 0; i2 < 24; ++i2) {
-              const double rho = xr[ir], e1 = xa[i1], e2 = xa[i2];
-              double t[3];
-              t[ax] = rho;
-              t[o1] = rho * e1;
-              t[o2] = rho * e2;
-              const double wt = wr[ir] * wa[i1] * wa[i2] * rho / std::sqrt(1.0 + e1 * e1 + e2 * e2);
-              add(sg[0] * t[0] - d[0], sg[1] * t[1] - d[1], sg[2] * t[2] - d[2], wt);
-            }
-      }
-    } else {
-      for (int i = 0; i < 20; ++i)
-        for (int j = 0; j < 20; ++j)
-          for (int k = 0; k < 20; ++k) {
-            const double vx = lo[0] + xg[i], vy = lo[1] + xg[j], vz = lo[2] + xg[k];
-            const double X = d[0] + vx, Y = d[1] + vy, Z = d[2] + vz;
-            add(vx, vy, vz, wg[i] * wg[j] * wg[k] / std::sqrt(X * X + Y * Y + Z * Z));
-          }
+    long double J[64];
+    monomial_integrals(a, J);
+    for (int f = 0; f < kNFam; ++f) {
+      long double wx[4], wy[4], wz[4];
+      weight_cubic(kind[f][0], sg[0], d[0], wx);
+      weight_cubic(kind[f][1], sg[1], d[1], wy);
+      weight_cubic(kind[f][2], sg[2], d[2], wz);
+      long double sum = 0;
+      for (int ex = 0; ex < 4; ++ex)
+        for (int ey = 0; ey < 4; ++ey)
+          for (int ez = 0; ez < 4; ++ez) sum += wx[ex] * wy[ey] * wz[ez] * J[(ex * 4 + ey) * 4 + ez];
+      acc[f] += sum;
     }
   }
   for (int f = 0; f < kNFam; ++f) out[f] = (double)(acc[f] / (4.0L * 3.141592653589793238462643383279502884L));

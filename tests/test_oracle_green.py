@@ -132,3 +132,97 @@ def test_quadrature_converged():
     for n in base:
         scale = np.abs(green.family_values("M0", offs))
         assert np.all(np.abs(base[n] - fine[n]) <= 2e-15 * scale), n
+
+
+# ---------------------------------------------------------------------------
+# Near-singular offsets (all |d_i| <= 1) of every family, against a reference
+# that shares no step with the oracle's Duffy rule: the overlap weights are
+# rebuilt here from their definition (integrals over the overlap of two unit
+# intervals, as polynomials), the innermost z integral of
+# w_z(z) / sqrt(rho^2 + (d_z + z)^2) is taken in closed form (antiderivatives
+# of t^k / sqrt(rho^2 + t^2), k <= 3), and the remaining 2D integral, which has
+# at most a logarithmic singularity at a corner, by adaptive QUADPACK.
+
+def _weight_poly_from_definition(pq, lo):
+    """w(v) = int s^q (s - v)^p ds over [max(-1/2, v - 1/2), min(1/2, v + 1/2)]
+    as a polynomial in v on the half [lo, lo + 1] (lo = -1 or 0)."""
+    P = np.polynomial.Polynomial
+    v = P([0.0, 1.0])
+    a, b = (v - 0.5, P([0.5])) if lo >= 0 else (P([-0.5]), v + 0.5)
+    p, q = pq
+    s_pow = {0: lambda x: x, 1: lambda x: x ** 2 / 2, 2: lambda x: x ** 3 / 3}
+    # int s^q (s - v)^p ds, p, q in {0, 1}: expand (s - v)^p
+    if p == 0:
+        return s_pow[q](b) - s_pow[q](a)
+    return (s_pow[q + 1](b) - s_pow[q + 1](a)) - v * (s_pow[q](b) - s_pow[q](a))
+
+
+def _inner_closed_form(c, rho2, t0, t1):
+    """int_{t0}^{t1} sum_k c_k t^k / sqrt(rho2 + t^2) dt (k <= 3), closed form."""
+    assert rho2 > 0.0
+    rho = np.sqrt(rho2)
+
+    def F(t):
+        s = np.sqrt(rho2 + t * t)
+        ash = np.arcsinh(t / rho)
+        return (c[0] * ash + c[1] * s + c[2] * (t * s - rho2 * ash) / 2
+                + c[3] * s * (t * t - 2 * rho2) / 3)
+    return F(t1) - F(t0)
+
+
+def _family_semi_analytic(name, d, epsabs=1e-15):
+    pqs = green.FAMILIES[name]
+    P = np.polynomial.Polynomial
+    tot = 0.0
+    for lx in (-1.0, 0.0):
+        wx = _weight_poly_from_definition(pqs[0], lx)
+        for ly in (-1.0, 0.0):
+            wy = _weight_poly_from_definition(pqs[1], ly)
+            for lz in (-1.0, 0.0):
+                wz = _weight_poly_from_definition(pqs[2], lz)(P([-float(d[2]), 1.0]))  # in t = d_z + z
+                c = list(wz.coef) + [0.0] * (4 - len(wz.coef))
+                t0, t1 = d[2] + lz, d[2] + lz + 1.0
+
+                def f(y, x):
+                    rho2 = (d[0] + x) ** 2 + (d[1] + y) ** 2
+                    return wx(x) * wy(y) * _inner_closed_form(c, rho2, t0, t1)
+                tot += integrate.dblquad(f, lx, lx + 1, ly, ly + 1, epsabs=epsabs, epsrel=1e-13)[0]
+    return tot / FOUR_PI
+
+
+NEAR_OFFSETS = [(a, b, c) for c in (0, 1) for b in (0, 1) for a in (0, 1)] + \
+    [(-1, 0, 0), (0, -1, 1), (1, 0, -1), (-1, -1, -1)]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", list(green.FAMILIES))
+def test_near_families_against_semi_analytic(name):
+    """App. A eqs. 19-21 at the offsets whose boxes touch the singular point:
+    the oracle's Duffy rule against the independent reference above, to
+    1e-14 of M0(0)."""
+    scale = green.family_values("M0", [(0, 0, 0)])[0]
+    v = green.family_values(name, NEAR_OFFSETS)
+    for d, got in zip(NEAR_OFFSETS, v):
+        ref = _family_semi_analytic(name, d)
+        assert abs(got - ref) <= 1e-14 * scale, (name, d, got, ref)
+
+
+def test_semi_analytic_reference_reduces_to_classical_constant():
+    """The reference itself: M0(0) is the mean inverse distance of the unit cube."""
+    v = _family_semi_analytic("M0", (0, 0, 0))
+    assert abs(v * FOUR_PI - MEAN_INV_DIST_UNIT_CUBE) < 1e-14
+
+
+def test_duffy_rule_converged():
+    """The corner-box rule (n_ang, n_rad) = (20, 14) against (40, 28)."""
+    offs = [(a, b, c) for c in (0, 1) for b in (0, 1) for a in (0, 1)] + [(-1, 1, 0)]
+    saved = green._corner_box_integral
+    try:
+        base = {n: green.family_values(n, offs) for n in green.FAMILIES}
+        green._corner_box_integral = lambda d, lo, hi, pqs: saved(d, lo, hi, pqs, n_ang=40, n_rad=28)
+        fine = {n: green.family_values(n, offs) for n in green.FAMILIES}
+    finally:
+        green._corner_box_integral = saved
+    scale = green.family_values("M0", [(0, 0, 0)])[0]
+    for n in base:
+        assert np.all(np.abs(base[n] - fine[n]) <= 1e-15 * scale), (n, np.abs(base[n] - fine[n]).max() / scale)
