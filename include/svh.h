@@ -343,13 +343,28 @@ svh_status svh_matvec_adjoint(svh_problem* p, svh_prec prec, int nrhs, const int
 svh_status svh_port_gradient(svh_problem* p, int freq_idx, const void* xfwd_dev, const void* xadj_dev,
                              void* dY_dev, void* stream);
 
-/* grad_dev[k] = scale * Im( sum_{q,p} W[q][p] dY[q][p][k] ) for K voxels, with
- * dY from svh_port_gradient and W_host nports*nports complex doubles (host).
- * For a scalar loss of the port inductances L = Im(Y^-1) / w with weights G
- * (dLoss/dL), W = Z G Z (Z = Y^-1 symmetric) and scale = -1/w: the gradient
- * with respect to lambda_k^-2.  Synchronises the stream. */
-svh_status svh_gradient_contract(svh_problem* p, const void* dY_dev, const double* W_host, double scale,
-                                 double* grad_dev, void* stream);
+/* Port impedance and inductance from the admittance of svh_solve (eq. 3 and
+ * the inductance extraction of Sec. III): Z = Y^-1 and L = Im(Z) / w, with w
+ * the angular frequency of slot freq_idx.  Y_host: nports*nports complex
+ * doubles, Y[q*nports + p] (as svh_solve writes it).  Z_host (may be NULL):
+ * nports*nports complex doubles; L_host (may be NULL): nports*nports doubles
+ * in henry.  Host arithmetic only (Gauss-Jordan elimination with partial
+ * pivoting); EINVAL if Y is singular.  Touches no GPU. */
+svh_status svh_port_inductance(svh_problem* p, int freq_idx, const double* Y_host, double* Z_host,
+                               double* L_host);
+
+/* Gradient of a scalar loss of the port inductances with respect to the
+ * per-voxel kinetic parameter p_k = lambda_k^-2 (eq. 3):
+ *   grad_dev[k] = sum_{q,p} G[q][p] dL[q][p] / dp_k,  L = Im(Y^-1) / w,
+ * computed as -(1/w) Im( sum_{a,b} W[a][b] dY[a][b][k] ) with W = Z^T G Z^T,
+ * Z = Y^-1 (dZ = -Z dY Z).  Y_host: the admittance of the forward solve
+ * (nports^2 complex doubles); G_host: dLoss/dL, nports^2 doubles, row-major
+ * [q][p]; dY_dev from svh_port_gradient at the same frequency slot; grad_dev:
+ * K doubles (device).  ws_dev: device workspace of at least 16*nports^2
+ * bytes (receives W).  EINVAL if Y is singular.  Synchronises the stream. */
+svh_status svh_gradient_contract(svh_problem* p, int freq_idx, const double* Y_host, const double* G_host,
+                                 const void* dY_dev, double* grad_dev, void* ws_dev, size_t ws_bytes,
+                                 void* stream);
 
 /* Text of the last error on this problem (never NULL). */
 const char* svh_last_error(const svh_problem* p);

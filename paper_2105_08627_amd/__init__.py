@@ -23,7 +23,7 @@ EXPORTED = [
     "svh_create", "svh_get_sizes", "svh_set_material", "svh_setup_tensors", "svh_green_toeplitz",
     "svh_get_toeplitz", "svh_get_family", "svh_set_green_method", "svh_toeplitz_store_build",
     "svh_set_toeplitz_store", "svh_toeplitz_store_restore", "svh_green_tables", "svh_tucker_compress", "svh_workspace_bytes", "svh_matvec",
-    "svh_set_zstep", "svh_autotune", "svh_set_ports", "svh_solve_sizes", "svh_solve_workspace_bytes", "svh_solve", "svh_set_graphs", "svh_set_schur_precond", "svh_matvec_adjoint", "svh_port_gradient", "svh_gradient_contract", "svh_profile_enable", "svh_profile_read", "svh_last_error", "svh_destroy",
+    "svh_set_zstep", "svh_autotune", "svh_set_ports", "svh_solve_sizes", "svh_solve_workspace_bytes", "svh_solve", "svh_set_graphs", "svh_set_schur_precond", "svh_matvec_adjoint", "svh_port_gradient", "svh_port_inductance", "svh_gradient_contract", "svh_profile_enable", "svh_profile_read", "svh_last_error", "svh_destroy",
 ]
 PROF_NAMES = ["tucker_restore", "pass_x", "pass_y", "pass_z_mul", "pass_yi", "pass_xi"]
 
@@ -75,7 +75,8 @@ def lib():
     L.svh_set_schur_precond.argtypes = [vp, i32]
     L.svh_matvec_adjoint.argtypes = [vp, i32, i32, vp, vp, vp, vp, sz, vp]
     L.svh_port_gradient.argtypes = [vp, i32, vp, vp, vp, vp]
-    L.svh_gradient_contract.argtypes = [vp, vp, vp, dbl, vp, vp]
+    L.svh_port_inductance.argtypes = [vp, i32, vp, vp, vp]
+    L.svh_gradient_contract.argtypes = [vp, i32, vp, vp, vp, vp, vp, sz, vp]
     L.svh_solve_sizes.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.svh_solve_workspace_bytes.argtypes = [vp, i32, i32]
     L.svh_solve_workspace_bytes.restype = sz
@@ -338,18 +339,40 @@ class Problem:
                                             _stream_handle(stream)), "svh_port_gradient")
         return dY
 
-    def gradient_contract(self, dY, W, scale, stream=None):
-        """grad[k] = scale * Im(sum_qp W[q,p] dY[q,p,k]) (device float64 tensor)."""
+    def _admittance(self, Y):
+        Yc = np.ascontiguousarray(np.asarray(Y, dtype=np.complex128))
+        if Yc.shape != (self.nports, self.nports):
+            raise ValueError(f"Y must be ({self.nports}, {self.nports})")
+        return Yc
+
+    def port_inductance(self, freq_idx, Y):
+        """(Z, L): port impedance Y^-1 and inductance Im(Z)/w (svh_port_inductance)."""
+        if not hasattr(self, "nports"):
+            raise SvhError("port_inductance: set_ports first")
+        Yc = self._admittance(Y)
+        Z = np.zeros_like(Yc)
+        L = np.zeros(Yc.shape)
+        self._check(lib().svh_port_inductance(self._h, int(freq_idx), _ptr(Yc), _ptr(Z), _ptr(L)),
+                    "svh_port_inductance")
+        return Z, L
+
+    def gradient_contract(self, freq_idx, Y, G, dY, stream=None):
+        """grad[k] = sum_qp G[q,p] dL[q,p]/d(lambda_k^-2) (device float64 tensor),
+        from the forward admittance Y, the loss weights G = dLoss/dL and dY of
+        port_gradient (svh_gradient_contract)."""
         import torch
         if not hasattr(self, "nports"):
             raise SvhError("gradient_contract: set_ports first")
         _device_tensor(dY, "dY", torch.complex128, shape=(self.nports, self.nports, self.K))
-        Wc = np.ascontiguousarray(np.asarray(W, dtype=np.complex128))
-        if Wc.shape != (self.nports, self.nports):
-            raise ValueError(f"W must be ({self.nports}, {self.nports})")
+        Yc = self._admittance(Y)
+        Gc = np.ascontiguousarray(np.asarray(G, dtype=np.float64))
+        if Gc.shape != (self.nports, self.nports):
+            raise ValueError(f"G must be ({self.nports}, {self.nports})")
         g = torch.empty(self.K, dtype=torch.float64, device=dY.device)
-        self._check(lib().svh_gradient_contract(self._h, ctypes.c_void_p(dY.data_ptr()), _ptr(Wc), float(scale),
-                                                ctypes.c_void_p(g.data_ptr()), _stream_handle(stream)),
+        ws = torch.empty(16 * self.nports * self.nports, dtype=torch.uint8, device=dY.device)
+        self._check(lib().svh_gradient_contract(self._h, int(freq_idx), _ptr(Yc), _ptr(Gc),
+                                                ctypes.c_void_p(dY.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)),
                     "svh_gradient_contract")
         return g
 

@@ -1038,6 +1038,45 @@ svh_status fgmres(Ctx& c, const double2* B, double2* X, const std::vector<double
   return SVH_ENOTCONV;
 }
 
+// Z = A^-1 for a small dense complex matrix (row-major n x n), Gauss-Jordan
+// elimination with partial pivoting; false if A is singular.
+bool invert_small(int n, std::vector<cd> A, std::vector<cd>& Z) {
+  Z.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+  double amax = 0;
+  for (const cd& v : A) amax = std::max(amax, std::abs(v));
+  if (!(amax > 0)) return false;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::abs(A[(size_t)r * n + c]) > std::abs(A[(size_t)piv * n + c])) piv = r;
+    if (!(std::abs(A[(size_t)piv * n + c]) > 1e-300 * amax)) return false;
+    if (piv != c)
+      for (int k = 0; k < n; ++k) {
+        std::swap(A[(size_t)piv * n + k], A[(size_t)c * n + k]);
+        std::swap(Z[(size_t)piv * n + k], Z[(size_t)c * n + k]);
+      }
+    const cd inv = 1.0 / A[(size_t)c * n + c];
+    for (int k = 0; k < n; ++k) {
+      A[(size_t)c * n + k] *= inv;
+      Z[(size_t)c * n + k] *= inv;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const cd f = A[(size_t)r * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) {
+        A[(size_t)r * n + k] -= f * A[(size_t)c * n + k];
+        Z[(size_t)r * n + k] -= f * Z[(size_t)c * n + k];
+      }
+    }
+  }
+  return true;
+}
+
+// w of frequency slot f (the coupling scalar is j w mu0 dx)
+double angular_frequency(const svh_problem* p, int f) { return p->sconv[f].imag() / (kMu0 * p->dx); }
+
 }  // namespace
 
 void free_solver(svh_problem* p) {
@@ -1245,7 +1284,7 @@ svh_status svh_port_gradient(svh_problem* p, int freq_idx, const void* xfwd_dev,
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int K = p->nvox, nr = p->nports;
   const long long N = (long long)p->C * K + p->topo.M;
-  const double w = p->sconv[freq_idx].imag() / (kMu0 * p->dx);  // sconv = j w mu0 dx
+  const double w = angular_frequency(p, freq_idx);
   const double inv_wmu = p->dx / (w * kMu0);
   hipLaunchKernelGGL(k_port_grad, dim3(nblocks((long long)K * nr * nr)), dim3(256), 0, s, nr, p->C, K, N,
                      p->d_cdiag64 + (size_t)freq_idx * K, inv_wmu, static_cast<const double2*>(xfwd_dev),
@@ -1254,21 +1293,60 @@ svh_status svh_port_gradient(svh_problem* p, int freq_idx, const void* xfwd_dev,
   return SVH_OK;
 }
 
-svh_status svh_gradient_contract(svh_problem* p, const void* dY_dev, const double* W_host, double scale,
-                                 double* grad_dev, void* stream) {
+svh_status svh_port_inductance(svh_problem* p, int freq_idx, const double* Y_host, double* Z_host, double* L_host) {
   if (!p) return SVH_EINVAL;
-  if (p->nports < 1 || !dY_dev || !W_host || !grad_dev) return sfail(p, SVH_EINVAL, "gradient_contract: bad arguments");
+  if (p->nports < 1 || !Y_host) return sfail(p, SVH_EINVAL, "port_inductance: bad arguments (set the ports first)");
+  if (freq_idx < 0 || freq_idx >= p->nfreq) return sfail(p, SVH_EINVAL, "port_inductance: bad frequency slot");
+  const int n = p->nports;
+  std::vector<cd> Y((size_t)n * n), Z;
+  for (size_t i = 0; i < Y.size(); ++i) Y[i] = cd(Y_host[2 * i], Y_host[2 * i + 1]);
+  if (!invert_small(n, Y, Z)) return sfail(p, SVH_EINVAL, "port_inductance: singular admittance matrix");
+  const double w = angular_frequency(p, freq_idx);
+  for (size_t i = 0; i < Z.size(); ++i) {
+    if (Z_host) {
+      Z_host[2 * i] = Z[i].real();
+      Z_host[2 * i + 1] = Z[i].imag();
+    }
+    if (L_host) L_host[i] = Z[i].imag() / w;
+  }
+  return SVH_OK;
+}
+
+svh_status svh_gradient_contract(svh_problem* p, int freq_idx, const double* Y_host, const double* G_host,
+                                 const void* dY_dev, double* grad_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+  if (!p) return SVH_EINVAL;
+  if (p->nports < 1 || !Y_host || !G_host || !dY_dev || !grad_dev || !ws_dev)
+    return sfail(p, SVH_EINVAL, "gradient_contract: bad arguments");
+  if (freq_idx < 0 || freq_idx >= p->nfreq) return sfail(p, SVH_EINVAL, "gradient_contract: bad frequency slot");
+  const int n = p->nports;
+  if (ws_bytes < sizeof(double2) * n * n) return sfail(p, SVH_EINVAL, "gradient_contract: workspace too small");
+  std::vector<cd> Y((size_t)n * n), Z;
+  for (size_t i = 0; i < Y.size(); ++i) Y[i] = cd(Y_host[2 * i], Y_host[2 * i + 1]);
+  if (!invert_small(n, Y, Z)) return sfail(p, SVH_EINVAL, "gradient_contract: singular admittance matrix");
+  // Loss = sum_qp G_qp L_qp with L = Im(Z) / w and dZ = -Z dY Z, so
+  // dLoss/dp_k = -(1/w) Im( sum_ab W_ab dY_ab ), W = Z^T G Z^T
+  std::vector<cd> T((size_t)n * n, 0.0);
+  std::vector<double2> W((size_t)n * n);
+  for (int a = 0; a < n; ++a)  // T = Z^T G
+    for (int pp = 0; pp < n; ++pp) {
+      cd acc = 0;
+      for (int q = 0; q < n; ++q) acc += Z[(size_t)q * n + a] * G_host[(size_t)q * n + pp];
+      T[(size_t)a * n + pp] = acc;
+    }
+  for (int a = 0; a < n; ++a)  // W = T Z^T
+    for (int b = 0; b < n; ++b) {
+      cd acc = 0;
+      for (int pp = 0; pp < n; ++pp) acc += T[(size_t)a * n + pp] * Z[(size_t)b * n + pp];
+      W[(size_t)a * n + b] = make_double2(acc.real(), acc.imag());
+    }
+  const double w = angular_frequency(p, freq_idx);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int np = p->nports;
-  double2* dW = nullptr;
-  SCHK(hipMallocAsync((void**)&dW, sizeof(double2) * np * np, s));
-  SCHK(hipMemcpyAsync(dW, W_host, sizeof(double2) * np * np, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_grad_contract, dim3(nblocks(p->nvox)), dim3(256), 0, s, np, p->nvox, dW,
-                     static_cast<const double2*>(dY_dev), scale, grad_dev);
-  hipError_t e = hipGetLastError();
-  (void)hipFreeAsync(dW, s);
-  SCHK(e);
-  SCHK(hipStreamSynchronize(s));
+  double2* dW = static_cast<double2*>(ws_dev);
+  SCHK(hipMemcpyAsync(dW, W.data(), sizeof(double2) * n * n, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_grad_contract, dim3(nblocks(p->nvox)), dim3(256), 0, s, n, p->nvox, dW,
+                     static_cast<const double2*>(dY_dev), -1.0 / w, grad_dev);
+  SCHK(hipGetLastError());
+  SCHK(hipStreamSynchronize(s));  // W lives on this frame
   return SVH_OK;
 }
 

@@ -112,3 +112,46 @@ def test_inductance_gradient_vs_finite_differences():
             vals.append((Lk[0, 0] + 0.5 * Lk[0, 1]).item())
         fd = (vals[0] - vals[1]) / (2 * h)
         assert abs(g[k] - fd) <= 1e-3 * abs(g[k]) + 1e-6 * np.abs(g).max(), (k, g[k], fd)
+
+
+def test_port_inductance_and_contraction_through_the_abi():
+    """svh_port_inductance (Z = Y^-1, L = Im Z / w) and svh_gradient_contract
+    (W = Z^T G Z^T formed in the library) against the same algebra written
+    out here with numpy on the library's own Y and dY."""
+    dx = 0.25e-6
+    mask, ports, lam = bend_like()
+    p = _problem(mask, ports, lam, dx)
+    X, Y, _ = p.solve(0, rre=1e-12)
+    Xa, _, _ = p.solve(0, rre=1e-12, transpose=True)
+    dY = p.port_gradient(0, X, Xa)
+    Z, L = p.port_inductance(0, Y)
+    w = 2 * np.pi * F
+    Zref = np.linalg.inv(Y)
+    assert np.abs(Z - Zref).max() <= 1e-13 * np.abs(Zref).max()
+    assert np.abs(L - Zref.imag / w).max() <= 1e-13 * np.abs(Zref.imag / w).max()
+    G = np.array([[1.0, 0.5], [-0.25, 2.0]])
+    g = p.gradient_contract(0, Y, G, dY).cpu().numpy()
+    W = Zref.T @ G @ Zref.T
+    ref = -np.imag(np.einsum("ab,abk->k", W, dY.cpu().numpy())) / w
+    assert np.abs(g - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_autograd_backward_uses_the_forward_material():
+    """Two forward calls with different materials before the first backward:
+    the first backward must still give the gradient of its own forward."""
+    from paper_2105_08627_amd.autograd import port_inductance
+    dx = 0.25e-6
+    mask, ports, lam = bend_like()
+    p = _problem(mask, ports, lam, dx)
+    dev = torch.device("cuda")
+    pv1 = torch.tensor(lam ** -2.0, dtype=torch.float64, device=dev, requires_grad=True)
+    L1 = port_inductance(p, pv1, S0, F, rre=1e-12)
+    pv2 = torch.tensor((1.3 * lam) ** -2.0, dtype=torch.float64, device=dev, requires_grad=True)
+    L2 = port_inductance(p, pv2, S0, F, rre=1e-12)
+    L1[0, 0].backward()
+    g_interleaved = pv1.grad.cpu().numpy()
+    pv3 = torch.tensor(lam ** -2.0, dtype=torch.float64, device=dev, requires_grad=True)
+    port_inductance(p, pv3, S0, F, rre=1e-12)[0, 0].backward()
+    g_fresh = pv3.grad.cpu().numpy()
+    assert np.abs(g_interleaved - g_fresh).max() <= 1e-9 * np.abs(g_fresh).max()
+    del L2
