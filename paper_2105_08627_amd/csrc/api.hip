@@ -152,6 +152,7 @@ svh_status svh_create(svh_problem** out, int Kx, int Ky, int Kz, double dx_m, in
   p->C = basis;
   HIPCHK(hipGetDevice(&p->device));
   HIPCHK(hipDeviceGetAttribute(&p->ncu, hipDeviceAttributeMultiprocessorCount, p->device));
+  HIPCHK(hipDeviceGetAttribute(&p->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
   const size_t Kt = (size_t)Kx * Ky * Kz;
   p->vidx.assign(Kt, -1);
   int n = 0;
@@ -277,22 +278,26 @@ svh_status svh_set_material(svh_problem* p, int nfreq, const double* f_hz, const
   if (!p) return SVH_EINVAL;
   if (nfreq < 1 || !f_hz || !sigma0 || !lambda) return fail(p, SVH_EINVAL, "set_material: bad arguments");
   const int K = p->nvox;
+  // validate everything before any state of p changes
+  for (int f = 0; f < nfreq; ++f)
+    if (!(f_hz[f] > 0) || !std::isfinite(f_hz[f])) return fail(p, SVH_EINVAL, "set_material: frequency must be > 0");
+  for (int k = 0; k < (per_voxel ? K : 1); ++k)
+    if (!(sigma0[k] >= 0) || !(lambda[k] > 0) || !std::isfinite(sigma0[k]) || !std::isfinite(lambda[k]))
+      return fail(p, SVH_EINVAL, "set_material: need sigma0 >= 0, lambda > 0");
   std::vector<double2> cd64((size_t)nfreq * K);
   std::vector<float2> cd32((size_t)nfreq * K);
   std::vector<double2> s64(nfreq);
   std::vector<float2> s32(nfreq);
-  p->sconv.assign(nfreq, 0);
+  std::vector<std::complex<double>> sconv(nfreq);
   for (int f = 0; f < nfreq; ++f) {
-    if (!(f_hz[f] > 0)) return fail(p, SVH_EINVAL, "set_material: frequency must be > 0");
     const double w = 2 * M_PI * f_hz[f];
     const std::complex<double> s(0.0, w * kMu0 * p->dx);
-    p->sconv[f] = s;
+    sconv[f] = s;
     s64[f] = make_double2(s.real(), s.imag());
     s32[f] = make_float2((float)s.real(), (float)s.imag());
     for (int k = 0; k < K; ++k) {
       const double s0 = sigma0[per_voxel ? k : 0];
       const double lam = lambda[per_voxel ? k : 0];
-      if (!(s0 >= 0) || !(lam > 0)) return fail(p, SVH_EINVAL, "set_material: need sigma0 >= 0, lambda > 0");
       // eq. 3: sigma = sigma0 - j / (w mu lam^2); c = 1 / sigma
       const std::complex<double> sigma(s0, -1.0 / (w * kMu0 * lam * lam));
       const std::complex<double> c = 1.0 / sigma / p->dx;
@@ -300,10 +305,16 @@ svh_status svh_set_material(svh_problem* p, int nfreq, const double* f_hz, const
       cd32[(size_t)f * K + k] = make_float2((float)c.real(), (float)c.imag());
     }
   }
+  // a failed upload leaves the material unset rather than half replaced
+  p->nfreq = 0;
+  p->sconv.clear();
+  p->cdiag_host.clear();
+  p->diag_freq = -2;
   HIPCHK(upload(&p->d_cdiag64, cd64.data(), cd64.size()));
   HIPCHK(upload(&p->d_cdiag32, cd32.data(), cd32.size()));
   HIPCHK(upload(&p->d_sconv64, s64.data(), s64.size()));
   HIPCHK(upload(&p->d_sconv32, s32.data(), s32.size()));
+  p->sconv = std::move(sconv);
   p->cdiag_host.resize(cd64.size());
   for (size_t i = 0; i < cd64.size(); ++i) p->cdiag_host[i] = std::complex<double>(cd64[i].x, cd64[i].y);
   p->nfreq = nfreq;
@@ -736,6 +747,8 @@ svh_status matvec_impl(svh_problem* p, svh_prec prec, int nrhs, const int32_t* f
     char* yc = static_cast<char*>(y) + (size_t)r0 * ldy * cs;
     hipError_t e = dbl ? launch_matvec_chunk<double>(p, nr * p->C, ep, xc, yc, A, B, zhat, s, ev)
                        : launch_matvec_chunk<float>(p, nr * p->C, ep, xc, yc, A, B, zhat, s, ev);
+    if (e == hipErrorInvalidConfiguration)
+      return fail(p, SVH_EINVAL, "matvec: the z step of this grid needs more LDS per block than the device has");
     HIPCHK(e);
   }
   for (size_t i = 0; i < evs.size(); i += 8)

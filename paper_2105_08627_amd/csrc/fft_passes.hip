@@ -664,7 +664,7 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const int nd = (int)p->dzset.size();
     const int nrhs = nvec / 5;
     const int NZ = nzp <= 8 ? 8 : nzp <= 16 ? 16 : nzp <= 24 ? 24 : 32;
-    auto go = [&](auto nzt, auto rgt) {
+    auto go = [&](auto nzt, auto rgt) -> hipError_t {
       constexpr int NZc = decltype(nzt)::value, RGc = decltype(rgt)::value;
       constexpr int W = 256 / RGc;
       const int ntile = (Lx + W - 1) / W;
@@ -673,20 +673,24 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
       while (rpb > 1 && (long long)nblk * ((nrhs + rpb - 1) / rpb) < 4096) rpb = (rpb + 1) / 2;
       dim3 grid(nblk, (nrhs + rpb - 1) / rpb);
       const size_t sh = (size_t)5 * NZc * W * sizeof(C) + (size_t)7 * nd * W * sizeof(T);
+      if (sh > (size_t)p->max_lds) return hipErrorInvalidConfiguration;
       hipLaunchKernelGGL((k_zdirect5<T, NZc, RGc>), grid, dim3(256), sh, s, geo, Lx, Ly, nzp, nd, nrhs, rpb,
                          p->d_qtab, static_cast<const T*>(zhat), B);
+      return hipSuccess;
     };
     using I8 = std::integral_constant<int, 8>;
     using I16 = std::integral_constant<int, 16>;
     using I24 = std::integral_constant<int, 24>;
     using I32 = std::integral_constant<int, 32>;
     using RGmax = std::integral_constant<int, sizeof(T) == 8 ? 32 : 16>;
+    hipError_t ez;
     switch (NZ) {
-      case 8: go(I8{}, I8{}); break;
-      case 16: go(I16{}, I16{}); break;
-      case 24: go(I24{}, RGmax{}); break;
-      default: go(I32{}, RGmax{}); break;
+      case 8: ez = go(I8{}, I8{}); break;
+      case 16: ez = go(I16{}, I16{}); break;
+      case 24: ez = go(I24{}, RGmax{}); break;
+      default: ez = go(I32{}, RGmax{}); break;
     }
+    if (ez != hipSuccess) return ez;
   } else if (zdirect) {
     // 512 threads: double 32 pencils x 16 row groups, float 64 pencils x 8
     // row groups (512-byte runs of each plane row)
@@ -701,6 +705,7 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     dim3 grid(nblk, (nvec + vpb - 1) / vpb);
     const int NZ = nzp <= 8 ? 8 : nzp <= 16 ? 16 : nzp <= 24 ? 24 : 32;
     const size_t sh = (size_t)V * NZ * W * sizeof(C) + (size_t)NZ * sizeof(int) + (size_t)NZ * NZ;
+    if (sh > (size_t)p->max_lds) return hipErrorInvalidConfiguration;
     const T* gk = static_cast<const T*>(zhat);
     switch (NZ) {
       case 8: hipLaunchKernelGGL((k_zdirect<T, 8, RG, V, NT>), grid, dim3(NT), sh, s, geo, Lx, Ly, nzp, nvec, vpb,

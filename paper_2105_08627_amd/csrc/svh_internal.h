@@ -101,6 +101,7 @@ struct svh_problem {
   int nvox = 0;
   int device = 0;
   int ncu = 256;  // compute units of the device
+  int max_lds = 65536;  // bytes of LDS one block may use on the device
   std::vector<int32_t> vidx;       // dense -> compact index or -1, [z][y][x]
   std::vector<int32_t> zlist;      // occupied z planes
   std::vector<int32_t> zslot;      // z -> plane slot or -1 (size L[2])

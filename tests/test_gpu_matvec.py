@@ -120,6 +120,31 @@ def test_empty_planes_pruned(dev, zstep):
     assert np.all(err <= 1e-12), err
 
 
+@pytest.mark.parametrize("nplanes", [25, 32])
+@pytest.mark.parametrize("zstep", ["direct", "fused"])
+def test_direct_z_step_at_the_plane_limit(dev, zstep, nplanes):
+    """25 and 32 occupied planes of a 40-plane grid: the largest direct z sum
+    (32-plane template, FP64 needs more than 64 KiB of LDS per block) and the
+    fused step, FP64 and FP32, against the dense oracle."""
+    g = np.random.default_rng(60 + nplanes)
+    mask = np.zeros((40, 5, 6), dtype=np.uint8)
+    planes = np.sort(g.choice(40, nplanes, replace=False))
+    for z in planes:
+        mask[z] = g.random((5, 6)) < 0.6
+        mask[z, 0, 0] = 1
+    dx = 0.25e-6
+    p = _problem(mask, dx)
+    p.set_zstep(zstep)
+    fidx = [0, -1]
+    x = wl.random_currents(70 + nplanes, (2, 3, p.K))
+    ref = _oracle(mask, dx, x, fidx)
+    e64 = _relerr(_run(p, x, fidx, dev, torch.complex128), ref)
+    e32 = _relerr(_run(p, x, fidx, dev, torch.complex64), ref)
+    print("plane limit", nplanes, zstep, e64, e32)
+    assert np.all(e64 <= 1e-12)
+    assert np.all(e32 <= 1e-5)
+
+
 @pytest.mark.parametrize("zstep", ["fft", "direct", "fused"])
 @pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)])
 def test_tucker_full_rank_matches_exact(dev, dtype, tol, zstep):
