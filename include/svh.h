@@ -200,6 +200,24 @@ svh_status svh_matvec(svh_problem* p, svh_prec prec, int nrhs,
                       const int32_t* freq_idx_host, const void* x_dev, void* y_dev,
                       void* ws_dev, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as svh_matvec, with the workspace taken from a fixed array of
+ * 64 MiB in device memory (one per device, reserved when the library's code
+ * is loaded on that device and held until the process ends) instead of a
+ * caller buffer.  Makes no allocation (no hipMalloc, no events).  The
+ * caller still passes x_dev and y_dev (as in svh_matvec).
+ * EINVAL if svh_workspace_bytes(p, prec, nrhs) exceeds 64 MiB (the text of
+ * svh_last_error gives the size needed; call svh_matvec with a workspace
+ * then), or if the current device is not the one p was created on;
+ * ESTATE while per-kernel profiling is enabled.  Every call on one device
+ * shares that array: calls that may overlap on one device (several streams
+ * or threads) race and give wrong results; serialise them.  Nothing in the
+ * array needs to start at zero (every byte the product reads it first
+ * writes in the same call).  Enqueued on stream; does not synchronise. */
+svh_status svh_matvec_noalloc(svh_problem* p, svh_prec prec, int nrhs, const int32_t* freq_idx_host,
+                              const void* x_dev, void* y_dev, void* stream);
+
 /* Autotuner: times the launch shapes of the FFT passes (persistent grids of
  * 1, 2 or 4 resident waves of blocks, or one block per pencil group; full or
  * half column tiles for the y passes) on this exact batch (same arguments as

@@ -22,7 +22,7 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTCONV", -5: 
 EXPORTED = [
     "svh_create", "svh_get_sizes", "svh_set_material", "svh_setup_tensors", "svh_green_toeplitz",
     "svh_get_toeplitz", "svh_get_family", "svh_set_green_method", "svh_toeplitz_store_build",
-    "svh_set_toeplitz_store", "svh_toeplitz_store_restore", "svh_green_tables", "svh_tucker_compress", "svh_workspace_bytes", "svh_matvec",
+    "svh_set_toeplitz_store", "svh_toeplitz_store_restore", "svh_green_tables", "svh_tucker_compress", "svh_workspace_bytes", "svh_matvec", "svh_matvec_noalloc",
     "svh_set_zstep", "svh_autotune", "svh_set_ports", "svh_solve_sizes", "svh_solve_workspace_bytes", "svh_solve", "svh_set_graphs", "svh_set_schur_precond", "svh_matvec_adjoint", "svh_port_gradient", "svh_port_inductance", "svh_gradient_contract", "svh_profile_enable", "svh_profile_read", "svh_last_error", "svh_destroy",
 ]
 PROF_NAMES = ["tucker_restore", "pass_x", "pass_y", "pass_z_mul", "pass_yi", "pass_xi"]
@@ -69,6 +69,7 @@ def lib():
     L.svh_workspace_bytes.argtypes = [vp, i32, i32]
     L.svh_workspace_bytes.restype = sz
     L.svh_matvec.argtypes = [vp, i32, i32, vp, vp, vp, vp, sz, vp]
+    L.svh_matvec_noalloc.argtypes = [vp, i32, i32, vp, vp, vp, vp]
     L.svh_set_zstep.argtypes = [vp, i32]
     L.svh_set_ports.argtypes = [vp, i32, vp, vp, vp, vp]
     L.svh_set_graphs.argtypes = [vp, i32]
@@ -281,6 +282,15 @@ class Problem:
                               ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                               _stream_handle(stream))
         self._check(st, "svh_matvec")
+        return y
+
+    def matvec_noalloc(self, x, freq_idx, out, stream=None):
+        """matvec with the library's static device workspace (svh_matvec_noalloc):
+        no workspace tensor; `out` must be given (no output is allocated)."""
+        prec, nrhs, fi, y = self._batch(x, freq_idx, out)
+        st = lib().svh_matvec_noalloc(self._h, prec, nrhs, _ptr(fi), ctypes.c_void_p(x.data_ptr()),
+                                      ctypes.c_void_p(y.data_ptr()), _stream_handle(stream))
+        self._check(st, "svh_matvec_noalloc")
         return y
 
     def set_zstep(self, mode):

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 
 #include "host_math.h"
 #include "svh_internal.h"
@@ -131,6 +132,32 @@ int chunk_rhs(const svh_problem* p, int nrhs) {
   return std::max(1, std::min(nrhs, maxr));
 }
 
+// Workspace of svh_matvec_noalloc: a fixed array in device memory, one copy
+// per device the library runs on, held until the process ends.  Host code
+// never passes `scratch` itself to a kernel (on the host the name is only a
+// stand-in for the symbol): it looks up each device's address once, with
+// that device current, and uses that address.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// Address of `scratch` on device dev, which must be the current device.
+hipError_t scratch_address(int dev, void** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -153,6 +180,10 @@ svh_status svh_create(svh_problem** out, int Kx, int Ky, int Kz, double dx_m, in
   HIPCHK(hipGetDevice(&p->device));
   HIPCHK(hipDeviceGetAttribute(&p->ncu, hipDeviceAttributeMultiprocessorCount, p->device));
   HIPCHK(hipDeviceGetAttribute(&p->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
+  {
+    void* sp = nullptr;  // set-up of this device's svh_matvec_noalloc workspace
+    HIPCHK(scratch_address(p->device, &sp));
+  }
   const size_t Kt = (size_t)Kx * Ky * Kz;
   p->vidx.assign(Kt, -1);
   int n = 0;
@@ -565,6 +596,26 @@ svh_status svh_matvec(svh_problem* p, svh_prec prec, int nrhs, const int32_t* fr
   if (!p) return SVH_EINVAL;
   const long long ld = (long long)p->C * p->nvox;
   return svh::matvec_impl(p, prec, nrhs, freq_idx, x, ld, y, ld, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+svh_status svh_matvec_noalloc(svh_problem* p, svh_prec prec, int nrhs, const int32_t* freq_idx, const void* x,
+                              void* y, void* stream) {
+  if (!p) return SVH_EINVAL;
+  if (nrhs < 1) return fail(p, SVH_EINVAL, "matvec_noalloc: bad arguments");
+  if (p->prof) return fail(p, SVH_ESTATE, "matvec_noalloc: per-kernel profiling is enabled (it creates events)");
+  const size_t need = svh_workspace_bytes(p, prec, nrhs);
+  if (need > kScratchBytes)
+    return fail(p, SVH_EINVAL, "matvec_noalloc: the batch needs " + std::to_string(need) +
+                                   " bytes of workspace, more than the " + std::to_string(kScratchBytes) +
+                                   " bytes of the static scratch array; use svh_matvec with a caller workspace");
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != p->device) return fail(p, SVH_EINVAL, "matvec_noalloc: the problem lives on another device");
+  void* ws = nullptr;
+  HIPCHK(scratch_address(dev, &ws));
+  const long long ld = (long long)p->C * p->nvox;
+  return svh::matvec_impl(p, prec, nrhs, freq_idx, x, ld, y, ld, ws, kScratchBytes,
+                          static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"
