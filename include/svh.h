@@ -62,8 +62,6 @@ typedef struct svh_problem svh_problem;
  * dx_m > 0: voxel edge length in metres.
  * basis: 3 (piecewise-constant basis f^x, f^y, f^z of eq. 4) or 5 (plus the
  *   piecewise-linear f^2D, f^3D of eqs. 5-6, which let current turn corners).
- *   Basis 5 runs the direct z step only: svh_setup_tensors then requires at
- *   most 32 occupied z planes with at most 64 distinct plane offsets.
  * mask_host: Kt bytes, x fastest; non-zero marks a non-empty voxel.  At least
  *   one voxel must be non-empty.
  * The FFT grid is L_i = 2 K_i when 2 K_i factors into 2s and 3s, else the
@@ -245,20 +243,22 @@ svh_status svh_profile_read(svh_problem* p, double* ms_out, int* ncalls_out);
 
 /* Choice of the z-direction step of the product (all choices give the same
  * operator up to rounding):
- *  SVH_ZSTEP_AUTO   (default) DIRECT when at most 32 planes are occupied,
- *                   else FFT; svh_autotune switches a precision to FUSED
+ *  SVH_ZSTEP_AUTO   (default) DIRECT when at most 32 planes are occupied
+ *                   (basis 5: and at most 64 distinct plane offsets), else
+ *                   FFT; svh_autotune switches a precision to FUSED
  *                   when that applies (basis 3, at most 32 occupied z planes
  *                   with at most 64 distinct plane offsets) and it timed the
  *                   fused step faster on the caller's batch;
  *  SVH_ZSTEP_FFT    zero-padded FFT along z, product with the circulant
- *                   spectrum, inverse FFT (eq. 9 literally);
+ *                   spectrum (basis 5: the 17 blocks of eq. 8 from the seven
+ *                   family spectra), inverse FFT (eq. 9 literally);
  *  SVH_ZSTEP_DIRECT after the x and y transforms, the Toeplitz sum along z
  *                   over the occupied planes with the inverse z transform of
  *                   the circulant spectrum (EINVAL if more than 32 planes);
  *  SVH_ZSTEP_FUSED  the same sum, with the y transform, the z sum and the
  *                   inverse y transform of one x frequency in one kernel
  *                   (EINVAL where it does not apply).
- * Basis 5 accepts AUTO and DIRECT only. */
+ * FUSED applies to basis 3 only. */
 #define SVH_ZSTEP_AUTO 0
 #define SVH_ZSTEP_FFT 1
 #define SVH_ZSTEP_DIRECT 2

@@ -358,19 +358,30 @@ namespace {
 // the occupied plane offsets.
 svh_status setup_tensors5(svh_problem* p, hipStream_t s) {
   const int nzp = (int)p->zlist.size();
-  if (nzp > kMaxDirectPlanes || !p->d_qtab)
-    return fail(p, SVH_EINVAL, "setup_tensors: the piecewise-linear basis needs at most 32 occupied z planes "
-                               "with at most 64 distinct plane offsets");
+  const bool direct = nzp <= kMaxDirectPlanes && p->d_qtab;  // the direct z step applies
   const size_t Kt = (size_t)p->K[0] * p->K[1] * p->K[2];
-  const int nd = (int)p->dzset.size();
+  const int nd = direct ? (int)p->dzset.size() : 0;
   const size_t rows = (size_t)nd * p->K[1] * p->K[0];
   const size_t gsz = (size_t)kNFam * nd * p->L[1] * p->L[0];
+  const size_t hsz = folded_size(p);
   double *dF = nullptr, *dR = nullptr, *dT = nullptr;
   HIPCHK(hipMalloc(&dF, kNFam * Kt * sizeof(double)));
   hipError_t e = p->store.empty() ? family_tables(p->K, kNFam, dF, s) : store_tables(p, kNFam, dF, s);
   p->Tf.assign(kNFam * Kt, 0.0);
   if (e == hipSuccess) e = hipMemcpy(p->Tf.data(), dF, kNFam * Kt * sizeof(double), hipMemcpyDeviceToHost);
+  // folded spectra of the seven families (z FFT step)
+  if (e == hipSuccess) e = hipMalloc(&p->d_zhat64, kNFam * hsz * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&p->d_zhat32, kNFam * hsz * sizeof(float));
+  if (e == hipSuccess) {
+    const size_t nt = (size_t)p->K[2] * (p->L[0] / 2 + 1) * (p->K[1] + p->L[1] / 2 + 1);
+    e = hipMalloc(&dT, nt * sizeof(double));
+  }
+  if (e == hipSuccess) e = launch_folded_spectra(p, dF, kNFam, p->d_zhat64, dT, s);
+  if (e == hipSuccess) e = launch_to_f32(p->d_zhat64, p->d_zhat32, kNFam * hsz, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
   hipFree(dF);
+  if (dT) hipFree(dT);
+  dT = nullptr;
   HIPCHK(e);
   // M0 from the closed form if chosen, else from the same quadrature; exact
   // zeros where an odd family vanishes
@@ -385,6 +396,7 @@ svh_status setup_tensors5(svh_problem* p, hipStream_t s) {
           if (d[a] == 0) p->Tf[f * Kt + ((size_t)z * p->K[1] + y) * p->K[0] + x] = 0.0;
         }
   }
+  if (!direct) return SVH_OK;
   std::vector<double> hr(kNFam * rows);
   for (int f = 0; f < kNFam; ++f)
     for (int q = 0; q < nd; ++q)
@@ -428,12 +440,13 @@ svh_status svh_setup_tensors(svh_problem* p, void* stream) {
     if (st != SVH_OK) p->T.clear();
     return st;
   }
-  const size_t Lt = (size_t)p->L[0] * p->L[1] * p->L[2];
+  const size_t Ht = folded_size(p);
   double *dT = nullptr, *t1 = nullptr;
-  const size_t n1 = (size_t)p->K[2] * p->K[1] * p->L[0];
+  const size_t n1 = std::max((size_t)p->K[2] * p->K[1] * p->L[0],
+                             (size_t)p->K[2] * (p->L[0] / 2 + 1) * (p->K[1] + p->L[1] / 2 + 1));
   const size_t n2 = (size_t)p->K[2] * p->L[1] * p->L[0];
-  HIPCHK(hipMalloc(&p->d_zhat64, Lt * sizeof(double)));
-  HIPCHK(hipMalloc(&p->d_zhat32, Lt * sizeof(float)));
+  HIPCHK(hipMalloc(&p->d_zhat64, Ht * sizeof(double)));
+  HIPCHK(hipMalloc(&p->d_zhat32, Ht * sizeof(float)));
   HIPCHK(hipMalloc(&p->d_g64, n2 * sizeof(double)));
   HIPCHK(hipMalloc(&p->d_g32, n2 * sizeof(float)));
   HIPCHK(hipMalloc(&dT, Kt * sizeof(double)));
@@ -446,10 +459,11 @@ svh_status svh_setup_tensors(svh_problem* p, void* stream) {
     if (e == hipSuccess) e = p->store.empty() ? family_tables(p->K, 1, dT, s) : store_tables(p, 1, dT, s);
     if (e == hipSuccess) e = hipMemcpy(p->T.data(), dT, Kt * sizeof(double), hipMemcpyDeviceToHost);
   }
-  // the x and y axes of the spectrum give the z-space kernel; the z axis
-  // then gives the full circulant spectrum
-  if (e == hipSuccess) e = launch_even_spectrum(p, dT, p->d_zhat64, t1, p->d_g64, s);
-  if (e == hipSuccess) e = launch_to_f32(p->d_zhat64, p->d_zhat32, Lt, s);
+  // the x and y axes of the spectrum give the z-space kernel (direct z
+  // step); the folded spectrum serves the z FFT step
+  if (e == hipSuccess) e = launch_even_spectrum(p, dT, nullptr, t1, p->d_g64, s);
+  if (e == hipSuccess) e = launch_folded_spectra(p, dT, 1, p->d_zhat64, t1, s);
+  if (e == hipSuccess) e = launch_to_f32(p->d_zhat64, p->d_zhat32, Ht, s);
   if (e == hipSuccess) e = launch_to_f32(p->d_g64, p->d_g32, n2, s);
   if (e == hipSuccess && p->fused_r[0] > 0) {
     const size_t ng = p->dzset.size() * (size_t)p->L[0] * p->L[1];
@@ -516,8 +530,10 @@ svh_status svh_tucker_compress(svh_problem* p, double tol, int32_t* ranks_out, d
       for (int a = 0; a < 3; ++a) t.d[a] = tf.d[a];
       HIPCHK(upload(&t.core, tf.core.data(), tf.core.size()));
       for (int a = 0; a < 3; ++a) HIPCHK(upload(&t.F[a], tf.F[a].data(), tf.F[a].size()));
-      const std::vector<double> Fz = zspace_factor(tf, p->L[2], p->dzset, kOdd[f][2] != 0);
-      HIPCHK(upload(&t.Fz, Fz.data(), Fz.size()));
+      if (p->d_qtab) {  // z-space factor at the distinct plane offsets (direct z step)
+        const std::vector<double> Fz = zspace_factor(tf, p->L[2], p->dzset, kOdd[f][2] != 0);
+        HIPCHK(upload(&t.Fz, Fz.data(), Fz.size()));
+      }
       if (ranks_out)
         for (int a = 0; a < 3; ++a) ranks_out[3 * f + a] = tf.d[a];
       worst = std::max(worst, tf.relerr);
@@ -525,6 +541,8 @@ svh_status svh_tucker_compress(svh_problem* p, double tol, int32_t* ranks_out, d
     p->tucker = true;
     dfree(p->d_g5_64);
     dfree(p->d_g5_32);
+    dfree(p->d_zhat64);
+    dfree(p->d_zhat32);
     if (relerr_out) *relerr_out = worst;
     return SVH_OK;
   }
@@ -580,12 +598,13 @@ size_t svh_workspace_bytes(const svh_problem* p, svh_prec prec, int nrhs) {
   }
   size_t b = (size_t)cr * p->C * vec_bytes_AB(p, cs);
   if (p->tucker && p->C == 5) {
-    const size_t gsz = (size_t)kNFam * p->dzset.size() * p->L[0] * p->L[1];
+    const size_t gsz = use_zdirect(p) ? (size_t)kNFam * p->dzset.size() * p->L[0] * p->L[1]
+                                      : (size_t)kNFam * folded_size(p);
     b += ((gsz * (prec == SVH_FP64 ? sizeof(double) : sizeof(float)) + 255) & ~(size_t)255) + 256;
     b += tucker_scratch_doubles5(p) * sizeof(double);
   } else if (p->tucker) {
-    const size_t Lt = (size_t)p->L[0] * p->L[1] * (use_zdirect(p) ? p->K[2] : p->L[2]);
-    b += Lt * (prec == SVH_FP64 ? sizeof(double) : sizeof(float));
+    const size_t Lt = use_zdirect(p) ? (size_t)p->L[0] * p->L[1] * p->K[2] : folded_size(p);
+    b += ((Lt * (prec == SVH_FP64 ? sizeof(double) : sizeof(float)) + 255) & ~(size_t)255);
     b += tucker_scratch_doubles(p) * sizeof(double);
   }
   return std::max(b + 1024, bf);
@@ -726,9 +745,9 @@ svh_status matvec_impl(svh_problem* p, svh_prec prec, int nrhs, const int32_t* f
   char* A = w;
   char* B = w + Abytes;
   const bool zdirect = use_zdirect(p);
-  const void* zhat = p->C == 5 ? (dbl ? (const void*)p->d_g5_64 : (const void*)p->d_g5_32)
-                     : zdirect ? (dbl ? (const void*)p->d_g64 : (const void*)p->d_g32)
-                               : (dbl ? (const void*)p->d_zhat64 : (const void*)p->d_zhat32);
+  const void* zhat = !zdirect ? (dbl ? (const void*)p->d_zhat64 : (const void*)p->d_zhat32)
+                     : p->C == 5 ? (dbl ? (const void*)p->d_g5_64 : (const void*)p->d_g5_32)
+                                 : (dbl ? (const void*)p->d_g64 : (const void*)p->d_g32);
   std::vector<hipEvent_t> evs;
   if (p->prof) {
     const int nchunk = (nrhs + cr - 1) / cr;
@@ -744,11 +763,13 @@ svh_status matvec_impl(svh_problem* p, svh_prec prec, int nrhs, const int32_t* f
     }
     HIPCHK(hipEventRecord(evs[0], s));
   }
+  const int hx = p->L[0] / 2 + 1, hy = p->L[1] / 2 + 1, hz = p->L[2] / 2 + 1;
   if (p->tucker && p->C == 5) {
-    // restore the seven families' z-space kernels one after another
+    // restore the seven families' z-space kernels (direct z step) or folded
+    // spectra (z FFT step) one after another
     char* zb = B + align(Bbytes);
     const int nd = (int)p->dzset.size();
-    const size_t rows = (size_t)nd * p->L[0] * p->L[1];
+    const size_t rows = zdirect ? (size_t)nd * p->L[0] * p->L[1] : folded_size(p);
     const size_t gbytes = align(kNFam * rows * (dbl ? 8 : 4));
     double* V = reinterpret_cast<double*>(zb + gbytes);
     for (int f = 0; f < kNFam; ++f) {
@@ -756,8 +777,18 @@ svh_status matvec_impl(svh_problem* p, svh_prec prec, int nrhs, const int32_t* f
       double* Wt = V + (size_t)p->L[0] * t.d[1] * t.d[2];
       if (reinterpret_cast<char*>(Wt + (size_t)p->L[0] * p->L[1] * t.d[2]) > w + ws_bytes)
         return fail(p, SVH_EINVAL, "matvec: workspace too small");
-      HIPCHK(launch_tucker_rebuild_rows(p, t, t.Fz, nd, !dbl, zb + f * rows * (dbl ? 8 : 4), V, Wt, s));
+      void* out = zb + f * rows * (dbl ? 8 : 4);
+      if (zdirect) HIPCHK(launch_tucker_rebuild_rows(p, t, t.Fz, nd, !dbl, out, V, Wt, s));
+      else HIPCHK(launch_tucker_box(hx, hy, hz, t, t.F[2], !dbl, out, V, Wt, s));
     }
+    zhat = zb;
+  } else if (p->tucker && !zdirect) {
+    char* zb = B + align(Bbytes);
+    double* V = reinterpret_cast<double*>(zb + align(folded_size(p) * (dbl ? 8 : 4)));
+    double* Wt = V + (size_t)p->L[0] * p->tk.d[1] * p->tk.d[2];
+    if (reinterpret_cast<char*>(Wt + (size_t)p->L[0] * p->L[1] * p->tk.d[2]) > w + ws_bytes)
+      return fail(p, SVH_EINVAL, "matvec: workspace too small");
+    HIPCHK(launch_tucker_box(hx, hy, hz, p->tk, p->tk.F[2], !dbl, zb, V, Wt, s));
     zhat = zb;
   } else if (p->tucker) {
     char* zb = B + align(Bbytes);
@@ -886,10 +917,11 @@ svh_status svh_set_zstep(svh_problem* p, int mode) {
                                   p->zlist.size() > (size_t)kMaxDirectPlanes))
     return fail(p, SVH_EINVAL, "set_zstep: the fused step needs basis 3 and at most 32 occupied planes with at "
                                "most 64 distinct plane offsets");
-  if (p->C == 5 && mode == SVH_ZSTEP_FFT)
-    return fail(p, SVH_EINVAL, "set_zstep: the piecewise-linear basis runs the direct z step only");
   if (mode == SVH_ZSTEP_DIRECT && (int)p->zlist.size() > kMaxDirectPlanes)
     return fail(p, SVH_EINVAL, "set_zstep: direct z sum supports at most 32 occupied planes");
+  if (mode == SVH_ZSTEP_DIRECT && p->C == 5 && !p->d_qtab)
+    return fail(p, SVH_EINVAL, "set_zstep: the five-component direct z sum supports at most 64 distinct plane "
+                               "offsets");
   p->zstep = mode;
   return SVH_OK;
 }

@@ -131,147 +131,8 @@ __global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_y(FftPlan pl, Geo geo
   run_items<P, C, DIR, true>(pl, j0, ntile * nzp * nvec, mk_in, mk_out, acc, twl);
 }
 
-// ---------------------------------------------------------------- Z pass --
-template <typename C> struct ZIn {
-  const C* __restrict__ base;  // B + ky*Lx + kx  (vector start)
-  const int32_t* __restrict__ zslot;
-  size_t plane;  // Ly * Lx
-  bool valid;
-  __device__ __forceinline__ C ld(int n) const {
-    const int s = zslot[n];
-    return (valid && s >= 0) ? base[(size_t)s * plane] : C{0, 0};
-  }
-};
-template <typename C> struct ZOut {
-  C* __restrict__ base;
-  const int32_t* __restrict__ zslot;
-  size_t plane;
-  bool valid;
-  __device__ __forceinline__ void st(int n, C v) const {
-    const int s = zslot[n];
-    if (valid && s >= 0) base[(size_t)s * plane] = v;
-  }
-};
-
-// Last forward stage (Ns = L/R), multiply by the real spectrum, first inverse
-// stage (Ns = 1, same radix): butterfly j keeps the elements j + r L/R.
-template <typename C, typename T, int R, class Src, class Dst>
-__device__ __forceinline__ void fused_mul_r(int L, int j0, int TP, const Src& src, const Dst& dst,
-                                            const C* __restrict__ tw, const T (&zv)[12], bool sync_mid) {
-  constexpr int NB = NbMax<R>::v;
-  const int LR = L / R;
-  const int Ns = LR;
-  C v[NB][R];
-#pragma unroll
-  for (int it = 0; it < NB; ++it) {
-    const int j = j0 + it * TP;
-    if (j < LR) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[it][r] = src.ld(j + r * LR);
-    }
-  }
-  if (sync_mid) __syncthreads();
-#pragma unroll
-  for (int it = 0; it < NB; ++it) {
-    const int j = j0 + it * TP;
-    if (j < LR) {
-      if (Ns > 1) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], tw[r * j]);  // step = 1, k = j
-      }
-      dft<R, -1>(v[it]);
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[it][r] = cscale(v[it][r], zv[it * R + r]);
-      dft<R, +1>(v[it]);
-#pragma unroll
-      for (int r = 0; r < R; ++r) dst.st(j * R + r, v[it][r]);
-    }
-  }
-}
-
-template <typename C, typename T, class Src, class Dst>
-__device__ __forceinline__ void fused_mul(int R, int L, int j0, int TP, const Src& src, const Dst& dst,
-                                          const C* tw, const T (&zv)[12], bool sync_mid) {
-  switch (R) {
-    case 8: fused_mul_r<C, T, 8>(L, j0, TP, src, dst, tw, zv, sync_mid); break;
-    case 4: fused_mul_r<C, T, 4>(L, j0, TP, src, dst, tw, zv, sync_mid); break;
-    case 3: fused_mul_r<C, T, 3>(L, j0, TP, src, dst, tw, zv, sync_mid); break;
-    default: fused_mul_r<C, T, 2>(L, j0, TP, src, dst, tw, zv, sync_mid); break;
-  }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(MaxThreads<T>::v) k_pass_z(FftPlan pl, FftPlan ipl, Geo geo, int W, int Lx, int Ly, int nzp,
-                                                 int nvec, int vpb, const int32_t* __restrict__ zslot,
-                                                 const T* __restrict__ zhat,
-                                                 typename CT<T>::t* __restrict__ B,
-                                                 const typename CT<T>::t* __restrict__ tw) {
-  typedef typename CT<T>::t C;
-  extern __shared__ unsigned char smem_raw[];
-  C* lds = reinterpret_cast<C*>(smem_raw);
-  const int t = threadIdx.x;
-  const int w = t % W, j0 = t / W;
-  const int ntile = (Lx + W - 1) / W;
-  const int bid = first_item();  // XCD-aware order of the (tile, ky) blocks
-  const int tile = bid % ntile, ky = bid / ntile;
-  const int kx = tile * W + w;
-  const bool valid = kx < Lx;
-  const int kxc = valid ? kx : 0;
-  const int L = pl.L, TP = pl.tp;
-  const int Rl = pl.r[pl.ns - 1];
-  const int LR = L / Rl;
-  // spectrum values for the elements this thread holds in the fused stage
-  T zv[12];
-  const size_t plane = (size_t)Ly * Lx;
-  {
-    const int nb = NbMax<8>::v;  // placeholder to keep the array size fixed
-    (void)nb;
-    int q = 0;
-    const int NB = Rl == 8 ? 1 : Rl == 4 ? 2 : Rl == 3 ? 3 : 4;
-    for (int it = 0; it < NB; ++it)
-      for (int r = 0; r < Rl; ++r, ++q) {
-        const int j = j0 + it * TP;
-        const int n = j + r * LR;
-        zv[q] = (valid && j < LR) ? zhat[(size_t)n * plane + (size_t)ky * Lx + kxc] : (T)0;
-      }
-    for (; q < 12; ++q) zv[q] = (T)0;
-  }
-  Lds<C, true> acc{lds, W, 0, w};
-  const C* twl = lds_twiddles(lds + (size_t)W * L, tw, L);
-  const int v0 = blockIdx.y * vpb;
-  const int v1 = min(nvec, v0 + vpb);
-  for (int vec = v0; vec < v1; ++vec) {
-    C* vb = B + (size_t)vec * nzp * geo.pb + (size_t)ky * geo.rp + kxc;
-    ZIn<C> gin{vb, zslot, (size_t)geo.pb, valid};
-    ZOut<C> gout{vb, zslot, (size_t)geo.pb, valid};
-    if (pl.ns == 1) {
-      fused_mul<C, T>(Rl, L, j0, TP, gin, gout, twl, zv, false);
-    } else {
-      int Ns = 1;
-      stage_any<C, -1, false>(pl.r[0], L, Ns, j0, TP, gin, acc, twl);
-      Ns *= pl.r[0];
-      __syncthreads();
-      for (int s = 1; s < pl.ns - 1; ++s) {
-        stage_any<C, -1, true>(pl.r[s], L, Ns, j0, TP, acc, acc, twl);
-        Ns *= pl.r[s];
-        __syncthreads();
-      }
-      fused_mul<C, T>(Rl, L, j0, TP, acc, acc, twl, zv, true);
-      __syncthreads();
-      Ns = Rl;
-      for (int s = 1; s < ipl.ns - 1; ++s) {
-        stage_any<C, +1, true>(ipl.r[s], L, Ns, j0, TP, acc, acc, twl);
-        Ns *= ipl.r[s];
-        __syncthreads();
-      }
-      stage_any<C, +1, false>(ipl.r[ipl.ns - 1], L, Ns, j0, TP, acc, gout, twl);
-      __syncthreads();
-    }
-  }
-}
-
 // ------------------------------------------------- Z step, direct sum ----
-// Same z-direction product as k_pass_z, written in z space: after the x and y
+// The z-direction product of eq. 9 written in z space: after the x and y
 // transforms, pencil (kx, ky) needs y[z_i] = sum_j g(kx, ky, |z_i - z_j|) x[z_j]
 // over the occupied planes only, where g is the inverse z transform of the
 // circulant spectrum (real and even in the offset because the spectrum is
@@ -588,10 +449,13 @@ Geo make_geo(const svh_problem* p, size_t csize) {
   return g;
 }
 
+// Direct z sum (occupied planes) or padded z FFT: the direct sum whenever it
+// applies (at most 32 occupied planes; with five components also at most 64
+// distinct plane offsets) unless the FFT is asked for.
 bool use_zdirect(const svh_problem* p) {
   const int nzp = (int)p->zlist.size();
   if (p->zstep == SVH_ZSTEP_FFT) return false;
-  if (p->zstep == SVH_ZSTEP_DIRECT) return nzp <= kMaxDirectPlanes;
+  if (p->C == 5) return nzp <= kMaxDirectPlanes && p->d_qtab != nullptr;
   return nzp <= kMaxDirectPlanes;
 }
 
@@ -658,7 +522,10 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
   if (ev) hipEventRecord(ev[2], s);
   // Z step: padded FFT along z with the spectrum product, or the direct sum
   const bool zdirect = use_zdirect(p);
-  if (p->C == 5) {
+  if (!zdirect) {
+    const hipError_t ez = launch_zfft<T>(p, nvec, B, zhat, s);
+    if (ez != hipSuccess) return ez;
+  } else if (p->C == 5) {
     // coupled five-component direct sum; double: 8 pencils x 32 row groups
     // (one row each), float: 16 pencils x 16 row groups
     const int nd = (int)p->dzset.size();
@@ -717,15 +584,6 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
       default: hipLaunchKernelGGL((k_zdirect<T, 32, RG, V, NT>), grid, dim3(NT), sh, s, geo, Lx, Ly, nzp, nvec, vpb,
                                   p->d_zlist, ep.zslot ? p->d_qtab : nullptr, gk, B); break;
     }
-  } else {
-    const FftPlan& pl = p->plan[2];
-    const int W = cols_per_block(pl.tp, pl.L, sizeof(C));
-    const FftPlan ipl = reversed(pl);
-    const int vpb = nvec < 4 ? nvec : 4;
-    dim3 grid(((Lx + W - 1) / W) * Ly, (nvec + vpb - 1) / vpb);
-    const size_t sh = (size_t)W * pl.L * sizeof(C) + twiddle_bytes(pl.L, sizeof(C));
-    hipLaunchKernelGGL(k_pass_z<T>, grid, dim3(W * pl.tp), sh, s, pl, ipl, geo, W, Lx, Ly, nzp, nvec, vpb,
-                       p->d_zslot, static_cast<const T*>(zhat), B, tw[2]);
   }
   if (ev) hipEventRecord(ev[3], s);
   // Y inverse
@@ -751,10 +609,9 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const int nitems = ((NP + WX - 1) / WX) * nvec;
     const size_t sh = (size_t)WX * pencil_pitch(Lx) * sizeof(C) + twiddle_bytes(Lx, sizeof(C));
     const int g = persistent_grid((const void*)k_pass_xi<T, P>, WX * tp, sh, nitems, p->ncu, tn.grid_mult[3]);
-    // the direct z sum uses the z-space kernel, so only the x and y
-    // transforms leave a factor to divide out
-    const T inv_n =
-        (T)(1.0 / ((double)p->L[0] * p->L[1] * (zdirect || p->C == 5 ? 1.0 : (double)p->L[2])));
+    // the z steps leave no factor (the direct sum uses the z-space kernel,
+    // the z FFT divides by Lz in its product): only the x and y transforms'
+    const T inv_n = (T)(1.0 / ((double)p->L[0] * p->L[1]));
     const C* sc = dbl ? reinterpret_cast<const C*>(p->d_sconv64) : reinterpret_cast<const C*>(p->d_sconv32);
     const C* cd = dbl ? reinterpret_cast<const C*>(p->d_cdiag64) : reinterpret_cast<const C*>(p->d_cdiag32);
     hipLaunchKernelGGL((k_pass_xi<T, P>), dim3(g), dim3(WX * tp), sh, s, pl, geo, WX, Kx, Ky, nzp, K, nvec, ep,

@@ -131,7 +131,9 @@ struct svh_problem {
   double* d_g5_64 = nullptr;
   float* d_g5_32 = nullptr;
   svh::DevTucker tk5[svh::kNFam];
-  double* d_zhat64 = nullptr;   // dense spectrum [Lz][Ly][Lx] (real)
+  // spectra of the circulants (real; j times this for M1x, M1y, M1z), folded
+  // to k_a <= L_a / 2 per axis: [f][kz][ky][kx], one family (basis 3) or seven
+  double* d_zhat64 = nullptr;
   float* d_zhat32 = nullptr;
   double* d_g64 = nullptr;      // dense z-space kernel [Kz][Ly][Lx] (real)
   float* d_g32 = nullptr;
@@ -223,6 +225,14 @@ hipError_t store_tables(const svh_problem* p, int nfam, double* d_out, hipStream
 hipError_t launch_zspace_families(const svh_problem* p, const double* d_rows, int nd, double* d_out,
                                   double* d_tmp, hipStream_t s);
 size_t tucker_scratch_doubles5(const svh_problem* p);
+// Folded spectra (k_a <= L_a / 2) of nfam family tables; see tensors.hip.
+hipError_t launch_folded_spectra(const svh_problem* p, const double* d_in, int nfam, double* d_out, double* d_tmp,
+                                 hipStream_t s);
+size_t folded_size(const svh_problem* p);
+// Z step by zero-padded z FFT with the folded spectra (zfft.hip).
+template <typename T>
+hipError_t launch_zfft(const svh_problem* p, int nvec, void* B, const void* spec, hipStream_t s);
+size_t zfft_lds_bytes(const svh_problem* p, size_t cs, int nc);
 bool use_zdirect(const svh_problem* p);
 Geo make_geo(const svh_problem* p, size_t csize);
 void free_solver(svh_problem* p);

@@ -16,15 +16,17 @@
 
 namespace svh {
 
+// out[o][k][i] for k < nk (nk = L: the whole axis; L / 2 + 1: the folded
+// half, the rest following by symmetry); tab has period L.
 __global__ void k_even_axis(const double* __restrict__ in, double* __restrict__ out, int nouter, int Kin,
-                            int L, int ninner, const double* __restrict__ tab, int odd) {
-  const size_t total = (size_t)nouter * L * ninner;
+                            int nk, int ninner, const double* __restrict__ tab, int odd, int L) {
+  const size_t total = (size_t)nouter * nk * ninner;
   for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < total;
        id += (size_t)gridDim.x * blockDim.x) {
     const int i = (int)(id % ninner);
     const size_t rest = id / ninner;
-    const int k = (int)(rest % L);
-    const size_t o = rest / L;
+    const int k = (int)(rest % nk);
+    const size_t o = rest / nk;
     const double* src = in + o * (size_t)Kin * ninner + i;
     double s = odd ? 0.0 : src[0];
     long long m = 0;
@@ -145,18 +147,63 @@ hipError_t launch_even_spectrum(const svh_problem* p, const double* d_T, double*
   e = hipMemcpyAsync(d_cos, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) {
     // x: [Kz][Ky][Kx] -> [Kz][Ky][Lx]
-    hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, d_T, d_tmp1, Kz * Ky, Kx, Lx, 1, d_cos, 0);
+    hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, d_T, d_tmp1, Kz * Ky, Kx, Lx, 1, d_cos, 0, Lx);
     // y: [Kz][Ky][Lx] -> [Kz][Ly][Lx]  (this is the z-space kernel)
     hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, d_tmp1, d_tmp2, Kz, Ky, Ly, Lx,
-                       d_cos + Lmax, 0);
+                       d_cos + Lmax, 0, Ly);
     // z: [Kz][Ly][Lx] -> [Lz][Ly][Lx]
-    hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, d_tmp2, d_out, 1, Kz, Lz, Ly * Lx,
-                       d_cos + 2 * Lmax, 0);
+    if (d_out)
+      hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, d_tmp2, d_out, 1, Kz, Lz, Ly * Lx,
+                         d_cos + 2 * Lmax, 0, Lz);
     e = hipGetLastError();
   }
   hipError_t e2 = hipStreamSynchronize(s);
   hipFree(d_cos);
   return e != hipSuccess ? e : e2;
+}
+
+// Folded spectra of nfam family tables d_in [f][Kz][Ky][Kx] (M0, M1x, M1y,
+// M1z, M2x, M2y, M2z in that order): d_out[f][kz][ky][kx] for k_a <= L_a / 2,
+// each axis a cosine sum (or, along the odd axis of an M1 family, the sine
+// sum: the spectrum divided by j).  d_tmp: Kz*Ky*(Lx/2+1) + Kz*(Ly/2+1)*(Lx/2+1)
+// doubles.  Synchronises the stream.
+hipError_t launch_folded_spectra(const svh_problem* p, const double* d_in, int nfam, double* d_out, double* d_tmp,
+                                 hipStream_t s) {
+  const int Kx = p->K[0], Ky = p->K[1], Kz = p->K[2];
+  const int Lx = p->L[0], Ly = p->L[1], Lz = p->L[2];
+  const int hx = Lx / 2 + 1, hy = Ly / 2 + 1, hz = Lz / 2 + 1;
+  const int Lmax = std::max(Lx, std::max(Ly, Lz));
+  std::vector<double> tab(6 * (size_t)Lmax, 0.0);  // cos, sin per axis
+  for (int a = 0; a < 3; ++a)
+    for (int m = 0; m < p->L[a]; ++m) {
+      const long double ang = 2.0L * 3.141592653589793238462643383279502884L * m / p->L[a];
+      tab[(size_t)(2 * a) * Lmax + m] = (double)cosl(ang);
+      tab[(size_t)(2 * a + 1) * Lmax + m] = (double)sinl(ang);
+    }
+  double* d_tab = nullptr;
+  hipError_t e = hipMalloc(&d_tab, sizeof(double) * tab.size());
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(d_tab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, s);
+  double* t1 = d_tmp;
+  double* t2 = d_tmp + (size_t)Kz * Ky * hx;
+  const size_t Kt = (size_t)Kx * Ky * Kz, Ht = (size_t)hx * hy * hz;
+  for (int f = 0; f < nfam && e == hipSuccess; ++f) {
+    const int ox = f == 1, oy = f == 2, oz = f == 3;
+    hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, d_in + f * Kt, t1, Kz * Ky, Kx, hx, 1,
+                       d_tab + (size_t)ox * Lmax, ox, Lx);
+    hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, t1, t2, Kz, Ky, hy, hx,
+                       d_tab + (size_t)(2 + oy) * Lmax, oy, Ly);
+    hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, t2, d_out + f * Ht, 1, Kz, hz, hy * hx,
+                       d_tab + (size_t)(4 + oz) * Lmax, oz, Lz);
+    e = hipGetLastError();
+  }
+  hipError_t e2 = hipStreamSynchronize(s);
+  hipFree(d_tab);
+  return e != hipSuccess ? e : e2;
+}
+
+size_t folded_size(const svh_problem* p) {
+  return (size_t)(p->L[0] / 2 + 1) * (p->L[1] / 2 + 1) * (p->L[2] / 2 + 1);
 }
 
 size_t tucker_scratch_doubles(const svh_problem* p) {
@@ -265,10 +312,10 @@ hipError_t launch_zspace_families(const svh_problem* p, const double* d_rows, in
     const int ox = kFamOdd[f][0], oy = kFamOdd[f][1];
     // x: [nd][Ky][Kx] -> [nd][Ky][Lx]
     hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, in, d_tmp, nd * Ky, Kx, Lx, 1,
-                       d_tab + (size_t)ox * Lmax, ox);
+                       d_tab + (size_t)ox * Lmax, ox, Lx);
     // y: [nd][Ky][Lx] -> [nd][Ly][Lx]
     hipLaunchKernelGGL(k_even_axis, dim3(2048), dim3(256), 0, s, d_tmp, out, nd, Ky, Ly, Lx,
-                       d_tab + (size_t)(2 + oy) * Lmax, oy);
+                       d_tab + (size_t)(2 + oy) * Lmax, oy, Ly);
     e = hipGetLastError();
   }
   hipError_t e2 = hipStreamSynchronize(s);
