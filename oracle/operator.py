@@ -181,6 +181,17 @@ def embed(B_of_offset, K, L):
     return E
 
 
+def spectrum_convolution(mask, H, x):
+    """Bare eq. 9 product of one component with a given circulant spectrum H
+    (array [Lz, Ly, Lx]): zero-pad x onto the L grid, FFT, multiply by H,
+    inverse FFT, crop to the non-empty voxels.  Used with spectra rebuilt from
+    Tucker factors (eq. 10) to check a compressed operator."""
+    P = voxel_coords(mask)
+    g = np.zeros(H.shape, dtype=np.complex128)
+    g[P[:, 2], P[:, 1], P[:, 0]] = np.asarray(x, dtype=np.complex128)
+    return np.fft.ifftn(H * np.fft.fftn(g))[P[:, 2], P[:, 1], P[:, 0]]
+
+
 def fft_matvec(mask, basis, x, fam, L, scale_conv=1.0, diag_c=None, dx=1.0):
     """y = Z x through eq. 9 with numpy FFTs: every block's kernel is embedded
     and transformed, each I^alpha is zero-padded to L, the products are summed
