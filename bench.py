@@ -33,6 +33,9 @@ KERNEL_NAMES_FP32 = {
 }
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+# the library is built without packed FP32 instructions: one FP32 FMA per lane
+# per clock, 256 CUs x 64 lanes x 2 FLOP x 2.4 GHz
+FP32_VALU_PEAK_TFLOPS = 78.6
 
 
 def log(msg):
@@ -74,12 +77,14 @@ def measured_traffic(kernel_name):
     return 1024.0 * (fk * float(meta["fetch_factor"]) + wk * float(meta["write_factor"]))
 
 
-def pass_bytes(p, nvec, cs, ts, K, nzp):
+def pass_bytes(p, nvec, cs, ts, K, nzp, nd):
     """Algorithmic HBM bytes of each kernel for one launch over nvec vectors.
 
     X  : read compact x, write the x-transformed planes (nzp * Ky * Lx)
     Y  : read those, write nzp * Ly * Lx
-    Z  : read and write nzp * Ly * Lx, read the spectrum once (Lx Ly Lz)
+    Z  : read and write nzp * Ly * Lx, read the kernel once: the z-space
+         kernel at the nd distinct plane offsets (direct z step), else the
+         spectrum (Lx Ly Lz)
     Yi : read nzp * Ly * Lx, write nzp * Ky * Lx
     Xi : read nzp * Ky * Lx and compact x and c/dx, write compact y
     """
@@ -91,41 +96,121 @@ def pass_bytes(p, nvec, cs, ts, K, nzp):
     return {
         "pass_x": nvec * (v + a),
         "pass_y": nvec * (a + b),
-        "pass_z_mul": nvec * 2 * b + Lx * Ly * (p.Kz if nzp <= 32 else Lz) * ts,
+        "pass_z_mul": nvec * 2 * b + Lx * Ly * (nd if nzp <= 32 else Lz) * ts,
         "pass_yi": nvec * (b + a),
         "pass_xi": nvec * (a + 3 * v),
     }
 
 
-def cpu_baseline(mask, dx, x, fidx, freqs, sigma0, lam, budget_s=20.0):
-    """The oracle's dense row sum, timed on a bounded sample of observer voxels
-    (each gives all components of all right-hand sides)."""
-    from oracle import green
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_worker(workload, nrhs, sample_rows, budget_s):
+    """Child process of the CPU baselines (started before the GPU is touched;
+    stdin/stdout carry the handshake).  Builds the oracle's M0 table for the
+    grid (untimed, while the GPU sections run), prints READY, waits for GO on
+    stdin, then times
+      * the oracle's dense row sum (``operator.dense_rows`` and the product
+        with the right-hand sides, as ``operator.dense_matvec`` does) on a
+        seeded sample of observer rows, extrapolated to full products;
+      * a plain FP64 FFT product (eq. 9 with the same circulant embedding,
+        ``scipy.fft`` on every host core) for one right-hand side,
+    and prints one JSON line with both."""
+    import scipy.fft as sfft
+    import workloads as wl
     from oracle import operator as op
+    cfg = wl.WORKLOADS[workload]
+    mask = cfg["mask"]()
+    Kz, Ky, Kx = mask.shape
+    dx, freqs, sigma0, lam = cfg["dx"], cfg["freqs"], cfg["sigma0"], cfg["lam"]
+    nf = len(freqs)
+    fidx = [r % nf for r in range(nrhs)]
+    x = wl.random_currents(cfg["seed"], (nrhs, 3, int(mask.sum())))
     P = op.voxel_coords(mask)
     K = P.shape[0]
-    nrhs = x.shape[0]
+    fam = op.FamilyCache(Kx, Ky, Kz)
+    t = time.perf_counter()
+    fam.table("M0")
+    t_table = time.perf_counter() - t
+    L = [2 * k for k in (Kx, Ky, Kz)]
+    t = time.perf_counter()
+    H = sfft.fftn(op.embed(lambda o: fam.values("M0", o), (Kx, Ky, Kz), L), workers=-1).real
+    t_spec = time.perf_counter() - t
+    print("READY", flush=True)
+    sys.stdin.readline()
+    cores = len(os.sched_getaffinity(0))
+    # dense row sum: rows (beta, l) for every right-hand side, grouped by frequency
     rng = np.random.default_rng(7)
-    rows = rng.choice(K, size=64, replace=False)
+    rows = rng.choice(3 * K, size=sample_rows, replace=False)
+    X = x.reshape(nrhs, 3 * K)
     done = 0
     t0 = time.perf_counter()
     while done < len(rows) and time.perf_counter() - t0 < budget_s:
-        l = rows[done]
-        Tl = green.family_values("M0", P - P[l])
-        for r in range(nrhs):
-            f = fidx[r]
-            w = 2 * np.pi * freqs[f]
-            c = op.material_c(freqs[f], sigma0, lam)
-            for b in range(3):
-                _ = 1j * w * op.MU0 * dx * (Tl @ x[r, b]) + c / dx * x[r, b, l]
+        row = rows[done:done + 1]
+        for f in range(nf):
+            sel = [r for r in range(nrhs) if fidx[r] == f]
+            s = 1j * 2 * np.pi * freqs[f] * op.MU0 * dx
+            c = op.material_c(freqs[f], sigma0, lam) * np.ones(K)
+            Zr = op.dense_rows(mask, 3, row, fam, s, c, dx)
+            _ = X[sel] @ Zr.T
         done += 1
     dt = time.perf_counter() - t0
-    cores = len(os.sched_getaffinity(0))
-    # one observer voxel = 3 * nrhs of the 3K outputs of nrhs matvecs
-    mv_per_s = done * nrhs / K / dt
-    return {"value": mv_per_s, "unit": "matvecs/s", "cores": cores, "kind": "oracle",
-            "sample": f"{done} observer voxels x 3 components x {nrhs} RHS of the dense O(N^2) row sum "
-                      f"(K={K}), {dt:.1f} s; numpy threads={os.environ.get('OMP_NUM_THREADS', 'default')}"}
+    dense = {"value": nrhs * done / (3 * K) / dt, "unit": "matvecs/s", "cores": cores, "kind": "oracle",
+             "sample": f"{done} of the {3 * K} operator rows (each for all {nrhs} RHS at their {nf} frequencies) "
+                       f"of the oracle's dense O(N^2) row sum, {dt:.1f} s, extrapolated to whole products; "
+                       f"the M0 table ({Kx}x{Ky}x{Kz} offsets, {t_table:.0f} s) built before timing",
+             "cpu_model": cpu_model()}
+    # FFT product, FP64, one right-hand side (three components)
+    s = 1j * 2 * np.pi * freqs[fidx[0]] * op.MU0 * dx
+    c = op.material_c(freqs[fidx[0]], sigma0, lam)
+    nrep = 0
+    t0 = time.perf_counter()
+    while nrep < 2:
+        y = np.empty((3, K), dtype=np.complex128)
+        for a in range(3):
+            g = np.zeros((L[2], L[1], L[0]), dtype=np.complex128)
+            g[P[:, 2], P[:, 1], P[:, 0]] = x[0, a]
+            G = sfft.fftn(g, workers=-1)
+            G *= H
+            y[a] = s * sfft.ifftn(G, workers=-1)[P[:, 2], P[:, 1], P[:, 0]] + c / dx * x[0, a]
+        nrep += 1
+    dt_fft = time.perf_counter() - t0
+    fftb = {"value": nrep / dt_fft, "unit": "matvecs/s", "cores": cores, "kind": "scipy.fft FP64",
+            "sample": f"{nrep} products of one RHS (3 components): zero-pad to {L[0]}x{L[1]}x{L[2]}, "
+                      f"3 forward and 3 inverse FFTs, spectrum product, crop, diagonal; scipy.fft workers = all "
+                      f"{cores} cores; spectrum built before timing ({t_spec:.0f} s)",
+            "cpu_model": cpu_model()}
+    print(json.dumps({"dense": dense, "fft": fftb}), flush=True)
+
+
+class CpuBaseline:
+    """Runs cpu_worker in a child process started before the GPU is used."""
+
+    def __init__(self, workload, nrhs, sample_rows=2048, budget_s=20.0):
+        import subprocess
+        self.p = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", workload,
+                                   "--nrhs", str(nrhs), "--cpu-rows", str(sample_rows),
+                                   "--cpu-budget", str(budget_s)],
+                                  stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True)
+
+    def result(self):
+        line = self.p.stdout.readline()
+        if not line.startswith("READY"):
+            self.p.kill()
+            raise RuntimeError(f"cpu baseline worker failed: {line!r}")
+        self.p.stdin.write("GO\n")
+        self.p.stdin.flush()
+        out = self.p.stdout.readline()
+        self.p.wait()
+        return json.loads(out)
 
 
 def bench_basis5(args, cfg, mask, fidx, dev):
@@ -186,9 +271,9 @@ def bench_basis5(args, cfg, mask, fidx, dev):
     # pencil, i.e. 48 flops per (pencil, RHS, observer plane, source plane)
     zflops = 48.0 * nrhs * Lx * Ly * nzp * nzp
     zms = res["fp32"]["kernels_ms_per_step"]["pass_z_mul"]
-    by = pass_bytes(p, 5 * nrhs, 8, 4, K, nzp)
     zs = np.nonzero(mask.reshape(mask.shape[0], -1).any(axis=1))[0]
     nd = len({abs(int(a) - int(b)) for a in zs for b in zs})
+    by = pass_bytes(p, 5 * nrhs, 8, 4, K, nzp, nd)
     by["pass_z_mul"] = 5 * nrhs * 2 * nzp * Ly * Lx * 8 + 7 * nd * Lx * Ly * 4
     return {"workload": f"same grid and RHS, piecewise-linear basis: 5 components, K={K}, "
                         f"7 integral families, Tucker tol {args.tol:g}",
@@ -196,7 +281,7 @@ def bench_basis5(args, cfg, mask, fidx, dev):
             **res, "rel_err_fp32_vs_fp64": rel,
             "adjoint": {"fp32": adj32, "fp64": adj64, "rel_diff_vs_forward_fp64": adj_sym},
             "z_step_fp32": {"ms": zms, "tflops": zflops / (zms * 1e-3) / 1e12,
-                            "alu_frac": zflops / (zms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+                            "alu_frac": zflops / (zms * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS,
                             "hbm_gbs": by["pass_z_mul"] / (zms * 1e-3) / 1e9}}
 
 
@@ -283,29 +368,34 @@ def bench_tucker_sweep(args):
 def bench_bend_study(args):
     """Self-convergence of the 90-degree bend inductance (Sec. III.C geometry:
     2 x 2 mm square section, 10 mm arms, lambda = 0.45 mm, sigma0 = 0) with the
-    piecewise-linear basis at dx = 0.5, 0.4, 0.25, 0.2, 0.1 mm; the finest
-    grid is the reference."""
+    piecewise-linear basis at dx = 0.5, 0.4, 0.25, 0.2, 0.1, 0.05 and
+    0.025 mm (the paper's two finest; their 40 and 80 planes take the z FFT
+    step); the finest grid is the reference."""
     import torch
     import paper_2105_08627_amd as svh
     import workloads as wl
     f = 1e3
     res = []
-    for dx_mm in (0.5, 0.4, 0.25, 0.2, 0.1):
+    for dx_mm in (0.5, 0.4, 0.25, 0.2, 0.1, 0.05, 0.025):
         mask, ports = wl.square_bend(int(round(2.0 / dx_mm)), int(round(10.0 / dx_mm)))
+        t = time.perf_counter()
         p = svh.Problem(mask, dx_mm * 1e-3, basis=5)
         p.set_material([f], 0.0, 0.45e-3)
         p.setup_tensors()
         p.tucker_compress(1e-8)
         p.set_ports(ports)
+        t_setup = time.perf_counter() - t
         t = time.perf_counter()
         X, Y, info = p.solve(0, rre=1e-8, restart=50, maxit=2000)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         L = float(p.port_inductance(0, Y)[1][0, 0])
-        res.append({"dx_mm": dx_mm, "K": p.K, "N": p.N, "L_nH": L * 1e9, "iterations": info["iterations"],
-                    "solve_s": dt, "relres": info["relres"]})
+        nz = int(np.count_nonzero(mask.reshape(mask.shape[0], -1).any(axis=1)))
+        res.append({"dx_mm": dx_mm, "grid": list(mask.shape[::-1]), "occupied_planes": nz, "K": p.K, "N": p.N,
+                    "L_nH": L * 1e9, "iterations": info["iterations"], "setup_s": t_setup, "solve_s": dt,
+                    "relres": info["relres"]})
         log(f"[bench] bend {res[-1]}")
-        del p
+        del p, X
     ref = res[-1]["L_nH"]
     for r in res:
         r["rel_diff_vs_finest"] = abs(r["L_nH"] - ref) / abs(ref)
@@ -378,6 +468,50 @@ def bench_solve_strips_over_ground(args):
             **res, "admittance_rel_diff_fp32_refined_vs_fp64": float(np.abs(Yir - Y64).max() / np.abs(Y64).max())}
 
 
+def bench_c5_solve(args):
+    """Port solve of the 256 x 256 x 128 stack with its 8 port-gap vias
+    (five components, so current turns the vias' corners; 52 occupied planes,
+    so the z FFT step), 8 ports in one batch, at the lowest and the highest of
+    the 8 frequencies: FP32 products inside FP64 refinement against plain
+    FP64, both to relative residual 1e-8, Tucker tol 1e-8."""
+    import torch
+    import paper_2105_08627_amd as svh
+    import workloads as wl
+    cfg = wl.WORKLOADS["c5_stack"]
+    mask, ports = wl.layered_stack_with_ports(cfg["seed"])
+    freqs = [cfg["freqs"][0], cfg["freqs"][-1]]
+    t = time.perf_counter()
+    p = svh.Problem(mask, cfg["dx"], basis=5)
+    p.set_material(freqs, cfg["sigma0"], cfg["lam"])
+    p.setup_tensors()
+    ranks, _ = p.tucker_compress(1e-8)
+    p.set_ports(ports)
+    t_setup = time.perf_counter() - t
+    log(f"[bench] c5 solve: K={p.K} N={p.N} ports={len(ports)} setup {t_setup:.1f}s")
+    rows = []
+    for fi, f in enumerate(freqs):
+        res = {"frequency_hz": f}
+        for name, refine in (("fp32_refined", True), ("fp64", False)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            X, Y, info = p.solve(fi, rre=1e-8, restart=50, maxit=2000, refine=refine, check=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res[name] = {"seconds": dt, "Y": Y, **{k: info[k] for k in ("iterations", "inner_iterations",
+                                                                         "refinement_steps", "relres", "converged")}}
+            log(f"[bench] c5 solve f={f:.3g} {name}: {dt:.2f}s {info['iterations']} its, "
+                f"inner {info['inner_iterations']}, relres {info['relres']:.2e}")
+            del X
+        Y64, Yir = res["fp64"].pop("Y"), res["fp32_refined"].pop("Y")
+        res["admittance_rel_diff_fp32_refined_vs_fp64"] = float(np.abs(Yir - Y64).max() / np.abs(Y64).max())
+        Z, L = p.port_inductance(fi, Y64)
+        res["port_self_inductance_pH"] = (np.diag(L) * 1e12).tolist()
+        rows.append(res)
+    return {"workload": f"stack with 8 port-gap vias, {mask.shape[2]}x{mask.shape[1]}x{mask.shape[0]}, K={p.K}, "
+                        f"five components, N={p.N} per port, 8 ports, rre 1e-8, Tucker tol 1e-8",
+            "setup_s": t_setup, "tucker_ranks": ranks.tolist(), "rows": rows}
+
+
 def bench_gradient(p, f):
     """Gradient of the full port-inductance matrix with respect to every
     voxel's lambda^-2 (addition 3): forward solve, adjoint solve (transpose),
@@ -423,42 +557,13 @@ def bench_adjoint(p, x, fidx, steps):
     return y, {"ms_per_step": dt * 1e3 / steps, "matvecs_per_s": x.shape[0] * steps / dt}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c5_stack")
-    ap.add_argument("--nrhs", type=int, default=64)
-    ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--fp64-steps", type=int, default=5)
-    ap.add_argument("--no-solve", action="store_true")
-    ap.add_argument("--no-basis5", action="store_true")
-    ap.add_argument("--tucker-sweep", action="store_true", help="ranks, CR and CO vs domain size (Figs. 2-3)")
-    ap.add_argument("--bend-study", action="store_true", help="90-degree bend inductance vs voxel size")
-    ap.add_argument("--table2", default="",
-                    help="comma-separated cube edges (voxels) for the Toeplitz-store experiment, e.g. 100,200")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is not built "
-                                   "(--gpus must be 1)"}))
-        sys.exit(2)
-
+def bench_matvec(args, dev):
+    """The headline section: the batched product on the stack (or the
+    workload named), FP32 and FP64, adjoint, roofline; then the same grid with
+    five components."""
     import torch
     import paper_2105_08627_amd as svh
     import workloads as wl
-
-    dev = torch.device("cuda:0")
-    if args.copy_probe:
-        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
     cfg = wl.WORKLOADS[args.workload]
     mask = cfg["mask"]()
     dx, freqs, sigma0, lam = cfg["dx"], cfg["freqs"], cfg["sigma0"], cfg["lam"]
@@ -470,6 +575,7 @@ def main():
     p = svh.Problem(mask, dx)
     p.set_material(freqs, sigma0, lam)
     p.setup_tensors()
+    p.set_zstep(args.zstep)
     t_setup = time.perf_counter() - t
     t = time.perf_counter()
     ranks, terr = p.tucker_compress(args.tol)
@@ -535,7 +641,9 @@ def main():
     mv32 = nrhs * args.steps / dt32
     mv64 = nrhs * args.fp64_steps / dt64
     nvec = 3 * nrhs
-    by32 = pass_bytes(p, nvec, 8, 4, K, nzp)
+    zocc = np.flatnonzero(mask.reshape(mask.shape[0], -1).any(axis=1))
+    nd = len({abs(int(a) - int(b)) for a in zocc for b in zocc})
+    by32 = pass_bytes(p, nvec, 8, 4, K, nzp, nd)
     per_call = {k: v / args.steps for k, v in prof32.items()}
     dom = max(by32, key=lambda k: per_call[k])
     ach = by32[dom] / (per_call[dom] * 1e-3) / 1e9
@@ -545,8 +653,6 @@ def main():
     d1, d2, d3 = ranks
     Lx, Ly, Lz = p.L
     # the direct z step restores the distinct plane offsets only
-    zocc = np.flatnonzero(mask.reshape(mask.shape[0], -1).any(axis=1))
-    nd = len({abs(int(a) - int(b)) for a in zocc for b in zocc})
     tflops = 2.0 * (Lx * d1 * d2 * d3 + Lx * Ly * d2 * d3 + Lx * Ly * (nd if nzp <= 32 else Lz) * d3)
     tk_ms = per_call["tucker_restore"]
     out = {
@@ -581,6 +687,56 @@ def main():
     }
     if not args.no_basis5:
         out["basis5"] = bench_basis5(args, cfg, mask, fidx, dev)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c5_stack")
+    ap.add_argument("--nrhs", type=int, default=64)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-basis5", action="store_true")
+    ap.add_argument("--tucker-sweep", action="store_true", help="ranks, CR and CO vs domain size (Figs. 2-3)")
+    ap.add_argument("--bend-study", action="store_true", help="90-degree bend inductance vs voxel size")
+    ap.add_argument("--c5-solve", action="store_true",
+                    help="port solve of the stack with its 8 port-gap vias (five components)")
+    ap.add_argument("--no-matvec", action="store_true", help="skip the matvec sections (with --c5-solve etc.)")
+    ap.add_argument("--table2", default="",
+                    help="comma-separated cube edges (voxels) for the Toeplitz-store experiment, e.g. 100,200")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--zstep", default="auto", choices=["auto", "fft", "direct", "fused"])
+    ap.add_argument("--cpu-worker", default="", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-rows", type=int, default=2048, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.cpu_worker:
+        cpu_worker(args.cpu_worker, args.nrhs, args.cpu_rows, args.cpu_budget)
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is not built "
+                                   "(--gpus must be 1)"}))
+        sys.exit(2)
+    # the CPU baselines' child process starts before anything touches the GPU
+    cpu = None if args.no_cpu else CpuBaseline(args.workload, args.nrhs)
+
+    import torch
+
+    dev = torch.device("cuda:0")
+    if args.copy_probe:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    out = {} if args.no_matvec else bench_matvec(args, dev)
     if not args.no_solve:
         out["solve"] = bench_solve(args)
         out["solve_strips_over_ground"] = bench_solve_strips_over_ground(args)
@@ -590,9 +746,14 @@ def main():
         out["tucker_sweep"] = bench_tucker_sweep(args)
     if args.bend_study:
         out["bend_study"] = bench_bend_study(args)
-    if not args.no_cpu:
-        log("[bench] cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(mask, dx, x64_h, fidx, freqs, sigma0, lam)
+    if args.c5_solve:
+        out["c5_solve"] = bench_c5_solve(args)
+    if cpu is not None:
+        log("[bench] cpu baselines (oracle row sum, scipy.fft product) ...")
+        cb = cpu.result()
+        out["cpu_baseline"] = cb["dense"]
+        out["cpu_fft_baseline"] = cb["fft"]
+        log(f"[bench] cpu {cb}")
     print(json.dumps(out), flush=True)
 
 

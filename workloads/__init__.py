@@ -220,6 +220,38 @@ def layered_stack(seed, Kx=256, Ky=256, Kz=128):
     return m
 
 
+def _stack_with_ports(seed, Kx, Ky, Kz):
+    g = rng(seed)
+    m = np.zeros((Kz, Ky, Kx), dtype=np.uint8)
+    strips = []
+    for i in range(8):
+        y = 8 + i * (Ky - 16) // 8
+        length = int(g.integers(60, 121))
+        x = int(g.integers(4, Kx - length - 4))
+        strips.append((y, x, length))
+    keep = [r for y, x, n in strips for r in ((y, y + 4, x, x + 4), (y, y + 4, x + n - 4, x + n))]
+    ground_with_holes(g, m, 4, 12, 64, 4, 16, keep)
+    manhattan_layer(g, m, 40, 48, 0.20)
+    manhattan_layer(g, m, 80, 88, 0.20)
+    feet = []
+    for y, x, length in strips:
+        m[40:48, y:y + 4, x:x + length] = 1          # port trace in the lower wiring layer
+        m[12:40, y:y + 4, x:x + 4] = 1               # shorted via down to the ground plane
+        m[13:40, y:y + 4, x + length - 4:x + length] = 1  # port via, gap at z = 12
+        feet.append((slice(y, y + 4), slice(x + length - 4, x + length)))
+    return m, [_gap_port(m, ys, xs, 13, 11) for ys, xs in feet]
+
+
+def layered_stack_with_ports(seed, Kx=256, Ky=256, Kz=128):
+    """The three-layer stack with 8 ports: 8 traces (width 4, length 60-120)
+    in the lower wiring layer, each shorted to the ground plane by a via at
+    one end and ending in a via with a one-voxel port gap above the ground at
+    the other (the ground's holes keep clear of the via footprints).  The
+    other traces float; every floating piece is a conductor region of its
+    own."""
+    return _stack_with_ports(seed, Kx, Ky, Kz)
+
+
 def strip_array(nstrip=16, length=256, width=4, thick=4, gap=4):
     """Parallel x-directed strips (coupled lines), one port per strip: + terminal
     on the -x end faces, - terminal on the +x end faces.  Returns (mask, ports)
@@ -270,4 +302,7 @@ WORKLOADS = {
     "c5_stack": dict(K=(256, 256, 128), dx=0.5e-6, sigma0=1e7, lam=90e-9,
                      freqs=list(1e9 * 50.0 ** (np.arange(8) / 7.0)), nrhs=8,
                      mask=lambda: layered_stack(1004), seed=1004),
+    # dense in z (every plane occupied): exercises the padded z-FFT step
+    "cube128": dict(K=(128, 128, 128), dx=1e-6, sigma0=1e7, lam=90e-9, freqs=[10e9], nrhs=8,
+                    mask=lambda: full_box(128, 128, 128), seed=1005),
 }
