@@ -302,6 +302,16 @@ svh_status svh_set_ports(svh_problem* p, int nports, const int32_t* plus_ptr, co
 #define SVH_SCHUR_AMG 1
 svh_status svh_set_schur_precond(svh_problem* p, int kind);
 
+/* Relative residual tolerance of the conjugate-gradient solve of the Schur
+ * complement inside the preconditioner (eqs. 13-15).  The outer method is
+ * flexible GMRES, which admits an inexact preconditioner, so a loose inner
+ * tolerance trades inner steps for outer ones.  0 (default): min(1e-8, rre)
+ * in FP64 solves, min(1e-8, 1e-2 x the inner target) in the refinement's
+ * inner solves.  EINVAL unless 0 <= tol < 1.  Setting SVH_VERBOSE=1 in the
+ * environment makes svh_solve print one progress line per GMRES cycle and
+ * refinement step on stderr. */
+svh_status svh_set_schur_tol(svh_problem* p, double tol);
+
 /* Unknowns per port column N = C K + M and node count M (after svh_set_ports). */
 svh_status svh_solve_sizes(const svh_problem* p, int* N, int* M);
 

@@ -23,7 +23,7 @@ EXPORTED = [
     "svh_create", "svh_get_sizes", "svh_set_material", "svh_setup_tensors", "svh_green_toeplitz",
     "svh_get_toeplitz", "svh_get_family", "svh_set_green_method", "svh_toeplitz_store_build",
     "svh_set_toeplitz_store", "svh_toeplitz_store_restore", "svh_green_tables", "svh_tucker_compress", "svh_workspace_bytes", "svh_matvec", "svh_matvec_noalloc",
-    "svh_set_zstep", "svh_autotune", "svh_set_ports", "svh_solve_sizes", "svh_solve_workspace_bytes", "svh_solve", "svh_set_graphs", "svh_set_schur_precond", "svh_matvec_adjoint", "svh_port_gradient", "svh_port_inductance", "svh_gradient_contract", "svh_profile_enable", "svh_profile_read", "svh_last_error", "svh_destroy",
+    "svh_set_zstep", "svh_autotune", "svh_set_ports", "svh_solve_sizes", "svh_solve_workspace_bytes", "svh_solve", "svh_set_graphs", "svh_set_schur_precond", "svh_set_schur_tol", "svh_matvec_adjoint", "svh_port_gradient", "svh_port_inductance", "svh_gradient_contract", "svh_profile_enable", "svh_profile_read", "svh_last_error", "svh_destroy",
 ]
 PROF_NAMES = ["tucker_restore", "pass_x", "pass_y", "pass_z_mul", "pass_yi", "pass_xi"]
 
@@ -74,6 +74,7 @@ def lib():
     L.svh_set_ports.argtypes = [vp, i32, vp, vp, vp, vp]
     L.svh_set_graphs.argtypes = [vp, i32]
     L.svh_set_schur_precond.argtypes = [vp, i32]
+    L.svh_set_schur_tol.argtypes = [vp, dbl]
     L.svh_matvec_adjoint.argtypes = [vp, i32, i32, vp, vp, vp, vp, sz, vp]
     L.svh_port_gradient.argtypes = [vp, i32, vp, vp, vp, vp]
     L.svh_port_inductance.argtypes = [vp, i32, vp, vp, vp]
@@ -389,6 +390,10 @@ class Problem:
     def set_schur_precond(self, kind):
         """'amg' (default) or 'jacobi' preconditioning of the Schur-complement CG."""
         self._check(lib().svh_set_schur_precond(self._h, {"jacobi": 0, "amg": 1}[kind]), "svh_set_schur_precond")
+
+    def set_schur_tol(self, tol):
+        """Relative tolerance of the inner Schur-complement CG (0: the default)."""
+        self._check(lib().svh_set_schur_tol(self._h, float(tol)), "svh_set_schur_tol")
 
     def set_graphs(self, enable):
         self._check(lib().svh_set_graphs(self._h, int(enable)), "svh_set_graphs")

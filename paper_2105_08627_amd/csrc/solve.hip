@@ -16,10 +16,13 @@
 // currents (component-major, as for svh_matvec) then one potential per node.
 // Dirichlet (port and grounded) node entries are kept at zero.
 #include <algorithm>
-#include <numeric>
+#include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <numeric>
 #include <vector>
 
 #include "host_math.h"
@@ -505,6 +508,20 @@ namespace svh {
 
 namespace {
 
+// Progress lines of the solver on stderr (svh_problem::verbose, or the
+// SVH_VERBOSE environment variable at the first solve).
+bool verbose(svh_problem* p) {
+  if (p->verbose < 0) {
+    const char* e = std::getenv("SVH_VERBOSE");
+    p->verbose = (e && *e && *e != '0') ? 1 : 0;
+  }
+  return p->verbose > 0;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 svh_status sfail(svh_problem* p, svh_status st, const std::string& m) {
   p->err = m;
   return st;
@@ -622,6 +639,7 @@ struct Ctx {
   int nr, CK, M, fidx, transpose;
   long long N;
   bool op32 = false;      // apply Z in FP32 (refinement inner solves)
+  double t0 = 0;          // start of the solve (progress lines)
   hipGraphExec_t pcg_graph = nullptr;  // 16 PCG iterations, replayed
   hipGraph_t pcg_g = nullptr;
 };
@@ -1034,6 +1052,14 @@ svh_status fgmres(Ctx& c, const double2* B, double2* X, const std::vector<double
     ++fs.restarts;
     ++cycles;
     SCHK(hipStreamSynchronize(c.s));
+    if (verbose(p)) {
+      double worst = 0;
+      for (int r = 0; r < nr; ++r)
+        if (bnorm[r] > 0) worst = std::max(worst, std::abs(g[r][jdone]) / bnorm[r]);
+      std::fprintf(stderr, "[svh] fgmres cycle %d (%s): %d steps, estimate %.3e, inner CG steps %d, %.2f s\n",
+                   cycles, c.op32 ? "fp32 operator" : "fp64", fs.total, worst, fs.inner, now_s() - c.t0);
+      std::fflush(stderr);
+    }
   }
   return SVH_ENOTCONV;
 }
@@ -1194,9 +1220,16 @@ svh_status svh_solve(svh_problem* p, svh_prec prec, int freq_idx, double rre, in
   c.N = (long long)c.CK + c.M;
   c.fidx = freq_idx;
   c.transpose = transpose ? 1 : 0;
+  c.t0 = now_s();
   carve(p, restart, prec, static_cast<char*>((void*)(((uintptr_t)ws + 255) & ~(uintptr_t)255)), &c.w);
   svh_status st = prepare_diag(p, freq_idx);
   if (st != SVH_OK) return st;
+  if (verbose(p)) {
+    std::fprintf(stderr, "[svh] solve: N = %lld per port, %d ports, %s, multigrid levels %zu, set-up %.2f s\n",
+                 c.N, c.nr, prec == SVH_FP64 ? "fp64" : "fp32 operator + fp64 refinement", p->amg.size(),
+                 now_s() - c.t0);
+    std::fflush(stderr);
+  }
   const int nr = c.nr;
   const long long NN = c.N * nr;
   double2* X = static_cast<double2*>(x_dev);
@@ -1209,7 +1242,7 @@ svh_status svh_solve(svh_problem* p, svh_prec prec, int freq_idx, double rre, in
   std::vector<double> relres(nr, 1.0);
   if (prec == SVH_FP64) {
     c.op32 = false;
-    st = fgmres(c, c.w.Rhs, X, bnorm, rre, restart, maxit, std::min(1e-8, rre), fs);
+    st = fgmres(c, c.w.Rhs, X, bnorm, rre, restart, maxit, p->schur_tol > 0 ? p->schur_tol : std::min(1e-8, rre), fs);
     if (st != SVH_OK && st != SVH_ENOTCONV) return finish(c, st);
   } else {
     // iterative refinement: FP64 residual, FP32 operator in the inner solve
@@ -1231,13 +1264,22 @@ svh_status svh_solve(svh_problem* p, svh_prec prec, int freq_idx, double rre, in
       for (int r = 0; r < nr; ++r)
         if (rn[r] > 0) need = std::min(need, rre * bnorm[r] / rn[r]);
       const double tin = std::max(inner, need);
-      st = fgmres(c, c.w.Rr, c.w.D, rn, tin, restart, maxit - fs.total, std::min(1e-8, tin * 1e-2), fs, 1);
+      st = fgmres(c, c.w.Rr, c.w.D, rn, tin, restart, maxit - fs.total,
+                  p->schur_tol > 0 ? p->schur_tol : std::min(1e-8, tin * 1e-2), fs, 1);
       if (st != SVH_OK && st != SVH_ENOTCONV) return finish(c, st);
       hipLaunchKernelGGL(k_add, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, c.w.D, X);
       c.op32 = false;
       if ((st = apply_K(c, X, c.w.Rr)) != SVH_OK) return finish(c, st);
       hipLaunchKernelGGL(k_resid, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, c.w.Rhs, c.w.Rr);
       if ((st = norms(c, c.w.Rr, rn)) != SVH_OK) return finish(c, st);
+      if (verbose(p)) {
+        double worst = 0;
+        for (int r = 0; r < nr; ++r)
+          if (bnorm[r] > 0) worst = std::max(worst, rn[r] / bnorm[r]);
+        std::fprintf(stderr, "[svh] refinement step %d: fp64 residual %.3e, %.2f s\n", ir_steps + 1, worst,
+                     now_s() - c.t0);
+        std::fflush(stderr);
+      }
     }
   }
   // true FP64 residual
@@ -1368,6 +1410,13 @@ svh_status svh_set_schur_precond(svh_problem* p, int kind) {
   if (kind != SVH_SCHUR_JACOBI && kind != SVH_SCHUR_AMG) return sfail(p, SVH_EINVAL, "set_schur_precond: unknown kind");
   if (kind != p->schur_precond) p->diag_freq = -2;  // rebuilt at the next solve
   p->schur_precond = kind;
+  return SVH_OK;
+}
+
+svh_status svh_set_schur_tol(svh_problem* p, double tol) {
+  if (!p) return SVH_EINVAL;
+  if (!(tol >= 0) || !(tol < 1)) return sfail(p, SVH_EINVAL, "set_schur_tol: need 0 <= tol < 1");
+  p->schur_tol = tol;
   return SVH_OK;
 }
 

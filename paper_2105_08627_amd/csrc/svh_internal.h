@@ -184,6 +184,8 @@ struct svh_problem {
   };
   std::vector<AmgDev> amg;
   double* d_amg_cinv = nullptr;
+  double schur_tol = 0;               // inner Schur CG relative tolerance (0: min(1e-8, rre))
+  int verbose = -1;                   // solver progress on stderr (-1: read SVH_VERBOSE at the first solve)
   bool use_graphs = true;             // replay the captured PCG iteration block
   hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
   // per-kernel timing: one event set per enqueued chunk while enabled
