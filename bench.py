@@ -462,10 +462,16 @@ def bench_solve_strips_over_ground(args):
                                                                      "refinement_steps", "relres")}}
         log(f"[bench] strips-over-ground solve {name}: {dt:.2f}s {info['iterations']} its, "
             f"inner {info['inner_iterations']}, relres {info['relres']:.2e}")
+        del X
+    # reference admittance: FP64 to relative residual 1e-11 (untimed)
+    _, Yref, iref = p.solve(0, rre=1e-11, restart=50, maxit=3000)
     Y64, Yir = res["fp64"].pop("Y"), res["fp32_refined"].pop("Y")
+    for name, Yv in (("fp64", Y64), ("fp32_refined", Yir)):
+        res[name]["admittance_rel_err_vs_reference"] = float(np.abs(Yv - Yref).max() / np.abs(Yref).max())
     return {"workload": f"strips over a ground slab with 16 holes, {mask.shape[2]}x{mask.shape[1]}x{mask.shape[0]}, "
                         f"K={p.K}, five components, N={p.N} per port, 16 ports, rre 1e-8, Tucker tol 1e-6",
-            **res, "admittance_rel_diff_fp32_refined_vs_fp64": float(np.abs(Yir - Y64).max() / np.abs(Y64).max())}
+            **res, "admittance_rel_diff_fp32_refined_vs_fp64": float(np.abs(Yir - Y64).max() / np.abs(Y64).max()),
+            "reference": f"FP64 solve to relative residual {iref['relres']:.1e} ({iref['iterations']} iterations)"}
 
 
 def bench_c5_solve(args):

@@ -305,11 +305,11 @@ svh_status svh_set_schur_precond(svh_problem* p, int kind);
 /* Relative residual tolerance of the conjugate-gradient solve of the Schur
  * complement inside the preconditioner (eqs. 13-15).  The outer method is
  * flexible GMRES, which admits an inexact preconditioner, so a loose inner
- * tolerance trades inner steps for outer ones.  0 (default): min(1e-8, rre)
- * in FP64 solves, min(1e-8, 1e-2 x the inner target) in the refinement's
- * inner solves.  EINVAL unless 0 <= tol < 1.  Setting SVH_VERBOSE=1 in the
- * environment makes svh_solve print one progress line per GMRES cycle and
- * refinement step on stderr. */
+ * tolerance trades inner steps for outer ones.  0 (default): rre clamped to
+ * [1e-12, 1e-8] in FP64 solves; 1e-4 in the refinement's inner solves, whose
+ * conjugate gradients run in FP32.  EINVAL unless 0 <= tol < 1.  Setting
+ * SVH_VERBOSE=1 in the environment makes svh_solve print one progress line
+ * per GMRES cycle and refinement step on stderr. */
 svh_status svh_set_schur_tol(svh_problem* p, double tol);
 
 /* Unknowns per port column N = C K + M and node count M (after svh_set_ports). */
@@ -333,10 +333,13 @@ size_t svh_solve_workspace_bytes(const svh_problem* p, svh_prec prec, int restar
  * Y = |diag Z| applied through eqs. 13-15, its Schur complement solved by
  * conjugate gradients to a relative 1e-8 or rre, whichever is smaller).
  * prec: SVH_FP64, or SVH_FP32_IR: refinement steps x += d with the residual
- *   b - K x formed in FP64 and d from an inner flexible GMRES (relative
- *   tolerance max(1e-6, rre)) whose Z products run in FP32 (Tucker
- *   restoration, Krylov vectors, orthogonalisation and preconditioner stay
- *   FP64).  freq_idx: frequency slot of the material.  rre: relative
+ *   b - K x formed in FP64 and d from one cycle of an inner flexible GMRES
+ *   (relative tolerance max(1e-6, rre)) whose Z products and Schur-complement
+ *   conjugate gradients run in FP32 (Tucker restoration accumulation, Krylov
+ *   vectors and orthogonalisation stay FP64).  The Arnoldi steps run without
+ *   host synchronisation (Hessenberg columns, Givens rotations and back
+ *   substitution on the device) and are replayed from captured HIP graphs
+ *   (svh_set_graphs).  freq_idx: frequency slot of the material.  rre: relative
  * residual target (the paper uses 1e-8).  maxit: cap on GMRES steps.
  * transpose != 0 solves K^T x = [b; 0] instead (adjoint system).
  * x_dev: nports columns of N complex doubles (currents, component-major as in
@@ -352,8 +355,10 @@ svh_status svh_solve(svh_problem* p, svh_prec prec, int freq_idx, double rre, in
                      int transpose, void* x_dev, double* Y_host, svh_solve_info* info, void* ws_dev,
                      size_t ws_bytes, void* stream);
 
-/* Replay the conjugate-gradient iteration block of the preconditioner from a
- * captured HIP graph (default 1) or launch it kernel by kernel (0). */
+/* Replay each Arnoldi step of svh_solve (preconditioner with its fixed
+ * number of conjugate-gradient steps, operator, Gram-Schmidt, Givens) from a
+ * HIP graph captured once per Krylov column and solve (default 1), or launch
+ * the same kernels one by one (0); both give bitwise the same result. */
 svh_status svh_set_graphs(svh_problem* p, int enable);
 
 /* y = Z^T x (transpose, not conjugate transpose), same arguments and layout

@@ -6,11 +6,15 @@
 // port excitations in lockstep.  The preconditioner is the sparse saddle
 // matrix of eq. 12 with Y = |diag Z|, applied through its Schur complement
 // (eqs. 13-15): e = d - A Y^-1 c, S b = e with S = A Y^-1 A^T (real, SPD on
-// the free nodes), a = Y^-1 (c + A^T b).  S b = e is solved by Jacobi-
-// preconditioned conjugate gradients on the device; since that inner solve
-// is inexact the outer method is the flexible variant.  Gram-Schmidt runs
-// twice (CGS2) with all inner products in FP64 on the device; only the
-// Hessenberg column (a few scalars per port) crosses to the host per step.
+// the free nodes), a = Y^-1 (c + A^T b).  S b = e is solved by conjugate
+// gradients on the device, preconditioned by an aggregation multigrid (or
+// Jacobi), in FP64 (FP32 in the inner solves of the refinement); since that
+// inner solve is inexact the outer method is the flexible variant.
+// Gram-Schmidt runs twice (CGS2) with all inner products in FP64; the
+// Hessenberg columns, Givens rotations and back substitution stay on the
+// device, so an Arnoldi step needs no host synchronisation and is replayed
+// from a captured graph; the host reads the residual estimates every few
+// steps.
 //
 // Vector layout: per port one column of N = C*K + M complex doubles,
 // currents (component-major, as for svh_matvec) then one potential per node.
@@ -73,11 +77,41 @@ __global__ void k_saddle_fix(int nrhs, long long N, int CK, int M, const int* __
 }
 
 // ------------------------------------------------------- preconditioner --
+// The Schur solve works on complex vectors of element type V: double2 in FP64
+// solves, float2 in the inner solves of the refinement (their preconditioner
+// only has to be approximate); the sparse values stay FP64 and each product
+// is rounded to V.
+__device__ __forceinline__ float2 vadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 vadd(double2 a, double2 b) { return zadd(a, b); }
+__device__ __forceinline__ float2 vsub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 vsub(double2 a, double2 b) { return zsub(a, b); }
+__device__ __forceinline__ float2 vscale(float2 a, double s) {
+  const float f = (float)s;
+  return make_float2(a.x * f, a.y * f);
+}
+__device__ __forceinline__ double2 vscale(double2 a, double s) { return zscale(a, s); }
+template <class V> __device__ __forceinline__ V vzero();
+template <> __device__ __forceinline__ float2 vzero<float2>() { return make_float2(0.f, 0.f); }
+template <> __device__ __forceinline__ double2 vzero<double2>() { return make_double2(0.0, 0.0); }
+template <class V> __device__ __forceinline__ V vfrom(double2 a);
+template <> __device__ __forceinline__ float2 vfrom<float2>(double2 a) { return make_float2((float)a.x, (float)a.y); }
+template <> __device__ __forceinline__ double2 vfrom<double2>(double2 a) { return a; }
+__device__ __forceinline__ double2 vto2(float2 a) { return make_double2(a.x, a.y); }
+__device__ __forceinline__ double2 vto2(double2 a) { return a; }
+
+// Work of a conjugate-gradient step is skipped once every right-hand side
+// has reached its tolerance (*skip set by k_pcg_start / k_pcg_beta), so a
+// fixed number of steps can be enqueued (and replayed from a graph) with only
+// the steps that are needed doing work.
+#define SKIP_IF_DONE(skip) \
+  if ((skip) && *(skip)) return
+
 // e = d - A Y^-1 c (free rows; transpose: d + A Y^-1 c), into node vector e
+template <class V>
 __global__ void k_pre_rhs(int nrhs, long long N, int CK, int M, const int* __restrict__ rptr,
                           const int* __restrict__ rcol, const double* __restrict__ rval,
                           const uint8_t* __restrict__ freem, const double* __restrict__ ydiag,
-                          const double2* __restrict__ in, double2* __restrict__ e, int transpose) {
+                          const double2* __restrict__ in, V* __restrict__ e, int transpose) {
   GRID_STRIDE(i, (long long)M * nrhs) {
     const long long r = i / M;
     const int m = (int)(i % M);
@@ -88,7 +122,7 @@ __global__ void k_pre_rhs(int nrhs, long long N, int CK, int M, const int* __res
       const double2 d = c[CK + m];
       acc = transpose ? zadd(d, acc) : zsub(d, acc);
     }
-    e[r * M + m] = acc;
+    e[r * M + m] = vfrom<V>(acc);
   }
 }
 
@@ -102,69 +136,73 @@ constexpr int kRowRhs = 8;
 // acc[j] += sgn * sum_q a[q] * x[off[j] + c[q]] over q in [q0, q1), four
 // entries at a time so that their index loads and gathers are in flight
 // together (the additions keep the entry order)
-template <int SGN>
+template <int SGN, class V>
 __device__ __forceinline__ void row_gather(int q0, int q1, const int* __restrict__ c, const double* __restrict__ a,
-                                           const double2* __restrict__ x, const long long* off, double2* acc) {
+                                           const V* __restrict__ x, const long long* off, V* acc) {
   int q = q0;
   for (; q + 4 <= q1; q += 4) {
     const int c0 = c[q], c1 = c[q + 1], c2 = c[q + 2], c3 = c[q + 3];
     const double a0 = SGN * a[q], a1 = SGN * a[q + 1], a2 = SGN * a[q + 2], a3 = SGN * a[q + 3];
 #pragma unroll
     for (int j = 0; j < kRowRhs; ++j) {
-      const double2 x0 = x[off[j] + c0], x1 = x[off[j] + c1], x2 = x[off[j] + c2], x3 = x[off[j] + c3];
-      acc[j] = zadd(acc[j], zscale(x0, a0));
-      acc[j] = zadd(acc[j], zscale(x1, a1));
-      acc[j] = zadd(acc[j], zscale(x2, a2));
-      acc[j] = zadd(acc[j], zscale(x3, a3));
+      const V x0 = x[off[j] + c0], x1 = x[off[j] + c1], x2 = x[off[j] + c2], x3 = x[off[j] + c3];
+      acc[j] = vadd(acc[j], vscale(x0, a0));
+      acc[j] = vadd(acc[j], vscale(x1, a1));
+      acc[j] = vadd(acc[j], vscale(x2, a2));
+      acc[j] = vadd(acc[j], vscale(x3, a3));
     }
   }
   for (; q < q1; ++q) {
     const int cq = c[q];
     const double aq = SGN * a[q];
 #pragma unroll
-    for (int j = 0; j < kRowRhs; ++j) acc[j] = zadd(acc[j], zscale(x[off[j] + cq], aq));
+    for (int j = 0; j < kRowRhs; ++j) acc[j] = vadd(acc[j], vscale(x[off[j] + cq], aq));
   }
 }
 
 // u = Y^-1 A^T v (basis-sized), v a node vector with zero Dirichlet entries
+template <class V>
 __global__ void k_s_half(int nrhs, int CK, int M, const int* __restrict__ cptr, const int* __restrict__ crow,
                          const double* __restrict__ cval, const double* __restrict__ ydiag,
-                         const double2* __restrict__ v, double2* __restrict__ u) {
+                         const V* __restrict__ v, V* __restrict__ u, const int* __restrict__ skip) {
+  SKIP_IF_DONE(skip);
   const int nchunk = (nrhs + kRowRhs - 1) / kRowRhs;
   GRID_STRIDE(i, (long long)CK * nchunk) {
     const int b = (int)(i % CK);
     const int r0 = (int)(i / CK) * kRowRhs;
     const int last = nrhs - 1 - r0;  // >= 0
     long long off[kRowRhs];
-    double2 acc[kRowRhs];
+    V acc[kRowRhs];
 #pragma unroll
     for (int j = 0; j < kRowRhs; ++j) {
       off[j] = (long long)(r0 + min(j, last)) * M;
-      acc[j] = make_double2(0, 0);
+      acc[j] = vzero<V>();
     }
     row_gather<1>(cptr[b], cptr[b + 1], crow, cval, v, off, acc);
     const double yi = 1.0 / ydiag[b];
 #pragma unroll
     for (int j = 0; j < kRowRhs; ++j)
-      if (j <= last) u[(long long)(r0 + j) * CK + b] = zscale(acc[j], yi);
+      if (j <= last) u[(long long)(r0 + j) * CK + b] = vscale(acc[j], yi);
   }
 }
 
 // q = A u on free nodes (S v = A Y^-1 A^T v)
+template <class V>
 __global__ void k_s_full(int nrhs, int CK, int M, const int* __restrict__ rptr, const int* __restrict__ rcol,
                          const double* __restrict__ rval, const uint8_t* __restrict__ freem,
-                         const double2* __restrict__ u, double2* __restrict__ q) {
+                         const V* __restrict__ u, V* __restrict__ q, const int* __restrict__ skip) {
+  SKIP_IF_DONE(skip);
   const int nchunk = (nrhs + kRowRhs - 1) / kRowRhs;
   GRID_STRIDE(i, (long long)M * nchunk) {
     const int m = (int)(i % M);
     const int r0 = (int)(i / M) * kRowRhs;
     const int last = nrhs - 1 - r0;  // >= 0
     long long off[kRowRhs];
-    double2 acc[kRowRhs];
+    V acc[kRowRhs];
 #pragma unroll
     for (int j = 0; j < kRowRhs; ++j) {
       off[j] = (long long)(r0 + min(j, last)) * CK;
-      acc[j] = make_double2(0, 0);
+      acc[j] = vzero<V>();
     }
     if (freem[m]) row_gather<1>(rptr[m], rptr[m + 1], rcol, rval, u, off, acc);
 #pragma unroll
@@ -174,39 +212,45 @@ __global__ void k_s_full(int nrhs, int CK, int M, const int* __restrict__ rptr, 
 }
 
 // a = Y^-1 (c + A^T b) (transpose: Y^-1 (c - A^T b)); out = [a; b]
+template <class V>
 __global__ void k_pre_out(int nrhs, long long N, int CK, int M, const int* __restrict__ cptr,
                           const int* __restrict__ crow, const double* __restrict__ cval,
                           const double* __restrict__ ydiag, const double2* __restrict__ in,
-                          const double2* __restrict__ bsol, double2* __restrict__ out, int transpose) {
+                          const V* __restrict__ bsol, double2* __restrict__ out, int transpose) {
   const long long per = (long long)CK + M;
   GRID_STRIDE(i, per * nrhs) {
     const long long r = i / per, idx = i % per;
-    const double2* br = bsol + r * M;
+    const V* br = bsol + r * M;
     if (idx < CK) {
       double2 acc = make_double2(0, 0);
-      for (int q = cptr[idx]; q < cptr[idx + 1]; ++q) acc = zadd(acc, zscale(br[crow[q]], cval[q]));
+      for (int q = cptr[idx]; q < cptr[idx + 1]; ++q) acc = zadd(acc, zscale(vto2(br[crow[q]]), cval[q]));
       const double2 c = in[r * N + idx];
       out[r * N + idx] = zscale(transpose ? zsub(c, acc) : zadd(c, acc), 1.0 / ydiag[idx]);
     } else {
-      out[r * N + idx] = br[idx - CK];
+      out[r * N + idx] = vto2(br[idx - CK]);
     }
   }
 }
 
 // ------------------------------------------------------------ reductions --
-// part[g][blk] = sum over the block's chunk of conj(X_g) * Y_g, where pair g
-// = (i, r) reads X at X + i * xs_i + r * xs_r and Y at Y + r * ys_r.
-__global__ void __launch_bounds__(256) k_mdot(long long n, int nrhs, const double2* __restrict__ X, long long xs_i,
-                                              long long xs_r, const double2* __restrict__ Y, long long ys_r,
-                                              double2* __restrict__ part, int conj_x) {
+// part[g][blk] = sum over the block's chunk of conj(X_g) * Y_g (FP64 sums),
+// where pair g = (i, r) reads X at X + i * xs_i + r * xs_r and Y at
+// Y + r * ys_r.
+template <class V>
+__global__ void __launch_bounds__(256) k_mdot(long long n, int nrhs, const V* __restrict__ X, long long xs_i,
+                                              long long xs_r, const V* __restrict__ Y, long long ys_r,
+                                              double2* __restrict__ part, int conj_x, const int* __restrict__ skip) {
+  SKIP_IF_DONE(skip);
   __shared__ double2 sh[256];
   const int g = blockIdx.y;
   const int i = g / nrhs, r = g % nrhs;
-  const double2* xp = X + (long long)i * xs_i + (long long)r * xs_r;
-  const double2* yp = Y + (long long)r * ys_r;
+  const V* xp = X + (long long)i * xs_i + (long long)r * xs_r;
+  const V* yp = Y + (long long)r * ys_r;
   double2 acc = make_double2(0, 0);
-  for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < n; k += (long long)gridDim.x * 256)
-    acc = zadd(acc, conj_x ? zcmul(xp[k], yp[k]) : zmul(xp[k], yp[k]));
+  for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < n; k += (long long)gridDim.x * 256) {
+    const double2 xv = vto2(xp[k]), yv = vto2(yp[k]);
+    acc = zadd(acc, conj_x ? zcmul(xv, yv) : zmul(xv, yv));
+  }
   sh[threadIdx.x] = acc;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
@@ -231,56 +275,100 @@ __global__ void __launch_bounds__(256) k_psum(int nb, const double2* __restrict_
 }
 
 // ------------------------------------------------------------------ PCG --
+// Per right-hand side state on the device (one wavefront, nrhs <= 64):
+// thr2 = itol^2 rho0 (a side is done once its rho = r^T D^-1 r falls to it),
+// ist[0] = every side done (the skip flag), ist[1] = applications that ended
+// with a side short of its tolerance, ist[2 + r] = side r done; steps counts
+// the conjugate-gradient steps that did work.
+
 // r = e, b = 0, z = D^-1 r, p = z
+template <class V>
 __global__ void k_pcg_init(long long n, int M, const double* __restrict__ sdiag, const uint8_t* __restrict__ freem,
-                           const double2* __restrict__ e, double2* __restrict__ r, double2* __restrict__ z,
-                           double2* __restrict__ p, double2* __restrict__ b) {
+                           const V* __restrict__ e, V* __restrict__ r, V* __restrict__ z, V* __restrict__ p,
+                           V* __restrict__ b) {
   GRID_STRIDE(i, n) {
     const int m = (int)(i % M);
-    const double2 v = e[i];
+    const V v = e[i];
     r[i] = v;
-    const double2 zz = freem[m] ? zscale(v, 1.0 / sdiag[m]) : make_double2(0, 0);
+    const V zz = freem[m] ? vscale(v, 1.0 / sdiag[m]) : vzero<V>();
     z[i] = zz;
     p[i] = zz;
-    b[i] = make_double2(0, 0);
+    b[i] = vzero<V>();
   }
 }
 
-// alpha = rho / Re(p^H q) per right-hand side (0 when converged or degenerate)
-__global__ void k_pcg_alpha(int nrhs, const double2* __restrict__ rho, const double2* __restrict__ pq,
-                            double* __restrict__ alpha) {
+// thresholds from rho0 and the tolerance itol2 = itol^2 (device scalar)
+__global__ void k_pcg_start(int nrhs, const double2* __restrict__ rho, const double* __restrict__ itol2,
+                            double* __restrict__ thr2, int* __restrict__ ist) {
   const int r = threadIdx.x;
-  if (r < nrhs) alpha[r] = (pq[r].x > 0 && rho[r].x > 0) ? rho[r].x / pq[r].x : 0.0;
+  const bool done = r >= nrhs || !(rho[r].x > 0);
+  if (r < nrhs) {
+    thr2[r] = itol2[0] * rho[r].x;
+    ist[2 + r] = done ? 1 : 0;
+  }
+  const unsigned long long open = __ballot(!done);
+  if (r == 0) ist[0] = open == 0ull ? 1 : 0;
+}
+
+// alpha = rho / Re(p^H q) per right-hand side (0 when done or degenerate)
+__global__ void k_pcg_alpha(int nrhs, const double2* __restrict__ rho, const double2* __restrict__ pq,
+                            double* __restrict__ alpha, const int* __restrict__ ist) {
+  const int r = threadIdx.x;
+  if (r < nrhs) alpha[r] = (!ist[2 + r] && pq[r].x > 0 && rho[r].x > 0) ? rho[r].x / pq[r].x : 0.0;
 }
 
 // b += alpha p, r -= alpha q, z = D^-1 r
+template <class V>
 __global__ void k_pcg_update(long long n, int M, const double* __restrict__ sdiag, const uint8_t* __restrict__ freem,
-                             const double* __restrict__ alpha, const double2* __restrict__ p,
-                             const double2* __restrict__ q, double2* __restrict__ b, double2* __restrict__ r,
-                             double2* __restrict__ z) {
+                             const double* __restrict__ alpha, const V* __restrict__ p, const V* __restrict__ q,
+                             V* __restrict__ b, V* __restrict__ r, V* __restrict__ z, const int* __restrict__ skip) {
+  SKIP_IF_DONE(skip);
   GRID_STRIDE(i, n) {
     const int m = (int)(i % M);
     const double a = alpha[i / M];
-    b[i] = zadd(b[i], zscale(p[i], a));
-    const double2 rr = zsub(r[i], zscale(q[i], a));
+    b[i] = vadd(b[i], vscale(p[i], a));
+    const V rr = vsub(r[i], vscale(q[i], a));
     r[i] = rr;
-    z[i] = freem[m] ? zscale(rr, 1.0 / sdiag[m]) : make_double2(0, 0);
+    z[i] = freem[m] ? vscale(rr, 1.0 / sdiag[m]) : vzero<V>();
   }
 }
 
-// beta = rho_new / rho; rho = rho_new
+// beta = rho_new / rho, rho = rho_new, and the sides that reach their
+// threshold are done (beta = 0 for sides already done)
 __global__ void k_pcg_beta(int nrhs, double2* __restrict__ rho, const double2* __restrict__ rho_new,
-                           double* __restrict__ beta) {
+                           double* __restrict__ beta, const double* __restrict__ thr2, int* __restrict__ ist,
+                           long long* __restrict__ steps) {
+  if (ist[0]) return;
   const int r = threadIdx.x;
+  bool done = true;
   if (r < nrhs) {
-    beta[r] = rho[r].x > 0 ? rho_new[r].x / rho[r].x : 0.0;
-    rho[r] = rho_new[r];
+    done = ist[2 + r] != 0;
+    if (!done) {
+      beta[r] = rho[r].x > 0 ? rho_new[r].x / rho[r].x : 0.0;
+      rho[r] = rho_new[r];
+      done = !(rho_new[r].x > thr2[r]);
+      if (done) ist[2 + r] = 1;
+    } else {
+      beta[r] = 0.0;
+    }
+  }
+  const unsigned long long open = __ballot(!done);
+  if (r == 0) {
+    ist[0] = open == 0ull ? 1 : 0;
+    steps[0] += 1;
   }
 }
 
-__global__ void k_pcg_dir(long long n, int M, const double* __restrict__ beta, const double2* __restrict__ z,
-                          double2* __restrict__ p) {
-  GRID_STRIDE(i, n) p[i] = zadd(z[i], zscale(p[i], beta[i / M]));
+template <class V>
+__global__ void k_pcg_dir(long long n, int M, const double* __restrict__ beta, const V* __restrict__ z,
+                          V* __restrict__ p, const int* __restrict__ skip) {
+  SKIP_IF_DONE(skip);
+  GRID_STRIDE(i, n) p[i] = vadd(z[i], vscale(p[i], beta[i / M]));
+}
+
+// end of one application: count it if a side is short of its tolerance
+__global__ void k_pcg_end(int* __restrict__ ist) {
+  if (threadIdx.x == 0 && !ist[0]) ist[1] += 1;
 }
 
 // ------------------------------------------------ multigrid V-cycle (S) --
@@ -292,21 +380,25 @@ __global__ void k_pcg_dir(long long n, int M, const double* __restrict__ beta, c
 constexpr double kAmgOmega = 0.7;
 constexpr double kAmgAlpha = 1.8;
 
-__global__ void k_amg_smooth0(int nrhs, int n, const double* __restrict__ wdinv, const double2* __restrict__ b,
-                              double2* __restrict__ x) {
-  GRID_STRIDE(i, (long long)n * nrhs) x[i] = zscale(b[i], wdinv[i % n]);
+template <class V>
+__global__ void k_amg_smooth0(int nrhs, int n, const double* __restrict__ wdinv, const V* __restrict__ b,
+                              V* __restrict__ x, const int* __restrict__ skip) {
+  SKIP_IF_DONE(skip);
+  GRID_STRIDE(i, (long long)n * nrhs) x[i] = vscale(b[i], wdinv[i % n]);
 }
 // r = b - A x, one row for up to kRowRhs right-hand sides per thread.
+template <class V>
 __global__ void k_amg_resid(int nrhs, int n, const int* __restrict__ rptr, const int* __restrict__ col,
-                            const double* __restrict__ val, const double2* __restrict__ b,
-                            const double2* __restrict__ x, double2* __restrict__ r) {
+                            const double* __restrict__ val, const V* __restrict__ b, const V* __restrict__ x,
+                            V* __restrict__ r, const int* __restrict__ skip) {
+  SKIP_IF_DONE(skip);
   const int nchunk = (nrhs + kRowRhs - 1) / kRowRhs;
   GRID_STRIDE(i, (long long)n * nchunk) {
     const int row = (int)(i % n);
     const int r0 = (int)(i / n) * kRowRhs;
     const int last = nrhs - 1 - r0;  // >= 0
     long long off[kRowRhs];
-    double2 acc[kRowRhs];
+    V acc[kRowRhs];
 #pragma unroll
     for (int j = 0; j < kRowRhs; ++j) {
       off[j] = (long long)(r0 + min(j, last)) * n;
@@ -322,60 +414,75 @@ __global__ void k_amg_resid(int nrhs, int n, const int* __restrict__ rptr, const
 // with one thread per row: one wavefront per row instead.  Lane t takes
 // right-hand side t % 16 of the current group of 16 and the row's entries
 // t / 16, t / 16 + 4, ...; the four partial sums meet through lane exchanges.
+template <class V>
 __global__ void k_amg_resid_w(int nrhs, int n, const int* __restrict__ rptr, const int* __restrict__ col,
-                              const double* __restrict__ val, const double2* __restrict__ b,
-                              const double2* __restrict__ x, double2* __restrict__ r) {
+                              const double* __restrict__ val, const V* __restrict__ b, const V* __restrict__ x,
+                              V* __restrict__ r, const int* __restrict__ skip) {
+  SKIP_IF_DONE(skip);
   const int lane = threadIdx.x & 63, rl = lane & 15, g = lane >> 4;
   const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
   for (long long row = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; row < n; row += nwaves) {
     const int q0 = rptr[row], q1 = rptr[row + 1];
     for (int r0 = 0; r0 < nrhs; r0 += 16) {
       const long long off = (long long)min(r0 + rl, nrhs - 1) * n;
-      double2 acc = make_double2(0, 0);
-      for (int q = q0 + g; q < q1; q += 4) acc = zadd(acc, zscale(x[off + col[q]], val[q]));
+      V acc = vzero<V>();
+      for (int q = q0 + g; q < q1; q += 4) acc = vadd(acc, vscale(x[off + col[q]], val[q]));
       acc.x += __shfl_xor(acc.x, 16);
       acc.y += __shfl_xor(acc.y, 16);
       acc.x += __shfl_xor(acc.x, 32);
       acc.y += __shfl_xor(acc.y, 32);
-      if (g == 0 && r0 + rl < nrhs) r[off + row] = zsub(b[off + row], acc);
+      if (g == 0 && r0 + rl < nrhs) r[off + row] = vsub(b[off + row], acc);
     }
   }
 }
 constexpr int kWaveRowLevel = 32768;  // levels with fewer rows take a wavefront per row
 
-__global__ void k_amg_jacobi(int nrhs, int n, const double* __restrict__ wdinv, const double2* __restrict__ r,
-                             double2* __restrict__ x) {
-  GRID_STRIDE(i, (long long)n * nrhs) x[i] = zadd(x[i], zscale(r[i], wdinv[i % n]));
+template <class V>
+__global__ void k_amg_jacobi(int nrhs, int n, const double* __restrict__ wdinv, const V* __restrict__ r,
+                             V* __restrict__ x, const int* __restrict__ skip) {
+  SKIP_IF_DONE(skip);
+  GRID_STRIDE(i, (long long)n * nrhs) x[i] = vadd(x[i], vscale(r[i], wdinv[i % n]));
 }
 // bc[I] = sum of r over the members of aggregate I
+template <class V>
 __global__ void k_amg_restrict(int nrhs, int nf, int nc, const int* __restrict__ mptr, const int* __restrict__ mem,
-                               const double2* __restrict__ r, double2* __restrict__ bc) {
+                               const V* __restrict__ r, V* __restrict__ bc, const int* __restrict__ skip) {
+  SKIP_IF_DONE(skip);
   GRID_STRIDE(i, (long long)nc * nrhs) {
     const long long rf = (i / nc) * nf;
     const int I = (int)(i % nc);
-    double2 acc = make_double2(0, 0);
-    for (int k = mptr[I]; k < mptr[I + 1]; ++k) acc = zadd(acc, r[rf + mem[k]]);
+    V acc = vzero<V>();
+    for (int k = mptr[I]; k < mptr[I + 1]; ++k) acc = vadd(acc, r[rf + mem[k]]);
     bc[i] = acc;
   }
 }
 // x += alpha P xc (rows left out of the coarse level have agg < 0)
-__global__ void k_amg_prolong(int nrhs, int nf, int nc, const int* __restrict__ agg, const double2* __restrict__ xc,
-                              double2* __restrict__ x) {
+template <class V>
+__global__ void k_amg_prolong(int nrhs, int nf, int nc, const int* __restrict__ agg, const V* __restrict__ xc,
+                              V* __restrict__ x, const int* __restrict__ skip) {
+  SKIP_IF_DONE(skip);
   GRID_STRIDE(i, (long long)nf * nrhs) {
     const int a = agg[i % nf];
-    if (a >= 0) x[i] = zadd(x[i], zscale(xc[(i / nf) * nc + a], kAmgAlpha));
+    if (a >= 0) x[i] = vadd(x[i], vscale(xc[(i / nf) * nc + a], kAmgAlpha));
   }
 }
 // x = Cinv b on the coarsest level (dense, row-major)
-__global__ void k_amg_coarse(int nrhs, int n, const double* __restrict__ cinv, const double2* __restrict__ b,
-                             double2* __restrict__ x) {
+template <class V>
+__global__ void k_amg_coarse(int nrhs, int n, const double* __restrict__ cinv, const V* __restrict__ b,
+                             V* __restrict__ x, const int* __restrict__ skip) {
+  SKIP_IF_DONE(skip);
   GRID_STRIDE(i, (long long)n * nrhs) {
     const long long base = (i / n) * n;
     const double* row = cinv + (long long)(i % n) * n;
     double2 acc = make_double2(0, 0);
-    for (int j = 0; j < n; ++j) acc = zadd(acc, zscale(b[base + j], row[j]));
-    x[i] = acc;
+    for (int j = 0; j < n; ++j) acc = zadd(acc, zscale(vto2(b[base + j]), row[j]));
+    x[i] = vfrom<V>(acc);
   }
+}
+
+template <class V>
+__global__ void k_vcopy(long long n, const V* __restrict__ a, V* __restrict__ b) {
+  GRID_STRIDE(i, n) b[i] = a[i];
 }
 
 // ---------------------------------------------------------------- GMRES --
@@ -413,6 +520,87 @@ __global__ void k_combine(long long N, int nrhs, int nj, const double2* __restri
     double2 acc = x[k];
     for (int j = 0; j < nj; ++j) acc = zadd(acc, zmul(coef[j * nrhs + r], Zk[(long long)j * zs_j + r * N + n]));
     x[k] = acc;
+  }
+}
+
+// ------------------------------------------- Hessenberg / Givens (device) --
+// One wavefront, thread r = right-hand side r (nrhs <= 64).  H is stored per
+// side as [restart + 1][restart], the rotations as cs [restart] (real) and sn
+// [restart] (complex), the rotated right-hand side g as [restart + 1].
+__device__ __forceinline__ double zabs(double2 a) { return hypot(a.x, a.y); }
+__device__ __forceinline__ double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 zdiv(double2 a, double2 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+// start of a cycle: g = (||w||, 0, ...), residual estimate ||w||
+__global__ void k_givens_init(int nrhs, int restart, const double2* __restrict__ nrm2, double2* __restrict__ g,
+                              double* __restrict__ est) {
+  const int r = threadIdx.x;
+  if (r >= nrhs) return;
+  const double b = sqrt(fmax(nrm2[r].x, 0.0));
+  double2* gr = g + (long long)r * (restart + 1);
+  gr[0] = make_double2(b, 0.0);
+  for (int i = 1; i <= restart; ++i) gr[i] = make_double2(0.0, 0.0);
+  est[r] = b;
+}
+
+// column j from the Gram-Schmidt coefficients h[i * nrhs + r] (i <= j) and
+// ||w||^2 (nrm2[r].x): earlier rotations applied, a new rotation zeroing the
+// subdiagonal, g rotated; est[r] = |g[j + 1]|, the residual norm estimate.
+__global__ void k_givens(int nrhs, int j, int restart, const double2* __restrict__ h,
+                         const double2* __restrict__ nrm2, double2* __restrict__ H, double* __restrict__ cs,
+                         double2* __restrict__ sn, double2* __restrict__ g, double* __restrict__ est) {
+  const int r = threadIdx.x;
+  if (r >= nrhs) return;
+  double2* Hr = H + (long long)r * (restart + 1) * restart;
+  double* csr = cs + (long long)r * restart;
+  double2* snr = sn + (long long)r * restart;
+  double2* gr = g + (long long)r * (restart + 1);
+  for (int i = 0; i <= j; ++i) Hr[i * restart + j] = h[i * nrhs + r];
+  const double hj1 = sqrt(fmax(nrm2[r].x, 0.0));
+  for (int i = 0; i < j; ++i) {
+    const double2 a = Hr[i * restart + j], b = Hr[(i + 1) * restart + j];
+    Hr[i * restart + j] = zadd(zscale(a, csr[i]), zmul(snr[i], b));
+    Hr[(i + 1) * restart + j] = zsub(zscale(b, csr[i]), zmul(zconj(snr[i]), a));
+  }
+  const double2 a = Hr[j * restart + j];
+  const double aa = zabs(a);
+  double c;
+  double2 sv, rr;
+  if (aa == 0) {
+    c = 0;
+    sv = make_double2(1.0, 0.0);
+    rr = make_double2(hj1, 0.0);
+  } else {
+    const double rho = hypot(aa, hj1);
+    const double2 ph = zscale(a, 1.0 / aa);
+    c = aa / rho;
+    sv = zscale(ph, hj1 / rho);
+    rr = zscale(ph, rho);
+  }
+  csr[j] = c;
+  snr[j] = sv;
+  Hr[j * restart + j] = rr;
+  const double2 gj = gr[j];
+  gr[j] = zscale(gj, c);
+  gr[j + 1] = zscale(zmul(zconj(sv), gj), -1.0);
+  est[r] = zabs(gr[j + 1]);
+}
+
+// y = H^-1 g over the first nj columns (back substitution), coef[i * nrhs + r] = y_i
+__global__ void k_backsolve(int nrhs, int nj, int restart, const double2* __restrict__ H,
+                            const double2* __restrict__ g, double2* __restrict__ coef) {
+  const int r = threadIdx.x;
+  if (r >= nrhs) return;
+  const double2* Hr = H + (long long)r * (restart + 1) * restart;
+  const double2* gr = g + (long long)r * (restart + 1);
+  for (int i = nj - 1; i >= 0; --i) {
+    double2 acc = gr[i];
+    for (int k = i + 1; k < nj; ++k) acc = zsub(acc, zmul(Hr[i * restart + k], coef[k * nrhs + r]));
+    const double2 d = Hr[i * restart + i];
+    coef[i * nrhs + r] = zabs(d) > 0 ? zdiv(acc, d) : make_double2(0.0, 0.0);
   }
 }
 
@@ -559,13 +747,14 @@ int nblocks(long long n) {
 int resid_blocks(int n, int nrhs) { return nblocks((long long)n * ((nrhs + kRowRhs - 1) / kRowRhs)); }
 
 // r = b - A x on one multigrid level (wavefront per row on small levels)
-void amg_resid(const svh_problem::AmgDev& L, int nr, const double2* b, const double2* x, double2* r, hipStream_t s) {
+template <class V>
+void amg_resid(const svh_problem::AmgDev& L, int nr, const V* b, const V* x, V* r, const int* skip, hipStream_t s) {
   if (L.n < kWaveRowLevel)
-    hipLaunchKernelGGL(k_amg_resid_w, dim3(nblocks(64LL * L.n)), dim3(256), 0, s, nr, L.n, L.rptr, L.col, L.val, b, x,
-                       r);
+    hipLaunchKernelGGL(k_amg_resid_w<V>, dim3(nblocks(64LL * L.n)), dim3(256), 0, s, nr, L.n, L.rptr, L.col, L.val, b,
+                       x, r, skip);
   else
-    hipLaunchKernelGGL(k_amg_resid, dim3(resid_blocks(L.n, nr)), dim3(256), 0, s, nr, L.n, L.rptr, L.col, L.val, b, x,
-                       r);
+    hipLaunchKernelGGL(k_amg_resid<V>, dim3(resid_blocks(L.n, nr)), dim3(256), 0, s, nr, L.n, L.rptr, L.col, L.val,
+                       b, x, r, skip);
 }
 
 constexpr int kDotBlocks = 256;
@@ -573,7 +762,10 @@ constexpr int kDotBlocks = 256;
 struct SolveWs {
   double2 *V, *Zk, *W, *Rhs, *E, *R, *Zp, *P, *Q, *Bs, *U, *part, *h, *h2, *nrm, *rho, *rhon, *pq, *D, *Rr;
   float2 *x32, *y32;
-  double *alpha, *beta;
+  double *alpha, *beta, *thr2, *itol2, *est, *cs;
+  double2 *H, *sn, *g;
+  int* ist;
+  long long* steps;
   void *mv, *mv32;
   size_t mv_bytes, mv32_bytes;
 };
@@ -612,6 +804,15 @@ size_t carve(const svh_problem* p, int restart, svh_prec prec, char* ws, SolveWs
   char* pq = take((size_t)nr * z);
   char* alpha = take((size_t)nr * sizeof(double));
   char* beta = take((size_t)nr * sizeof(double));
+  char* thr2 = take((size_t)nr * sizeof(double));
+  char* itol2 = take(sizeof(double));
+  char* est = take((size_t)nr * sizeof(double));
+  char* cs = take((size_t)nr * restart * sizeof(double));
+  char* H = take((size_t)nr * (restart + 1) * restart * z);
+  char* sn = take((size_t)nr * restart * z);
+  char* g = take((size_t)nr * (restart + 1) * z);
+  char* ist = take((size_t)(2 + nr) * sizeof(int));
+  char* steps = take(sizeof(long long));
   char* D = ir ? take((size_t)nr * N * z) : nullptr;
   char* Rr = ir ? take((size_t)nr * N * z) : nullptr;
   char* x32 = ir ? take((size_t)nr * CK * sizeof(float2)) : nullptr;
@@ -625,7 +826,10 @@ size_t carve(const svh_problem* p, int restart, svh_prec prec, char* ws, SolveWs
     w->E = (double2*)E; w->R = (double2*)R; w->Zp = (double2*)Zp; w->P = (double2*)P; w->Q = (double2*)Q;
     w->Bs = (double2*)Bs; w->U = (double2*)U; w->part = (double2*)part; w->h = (double2*)h;
     w->h2 = (double2*)h2; w->nrm = (double2*)nrm; w->rho = (double2*)rho; w->rhon = (double2*)rhon;
-    w->pq = (double2*)pq; w->alpha = (double*)alpha; w->beta = (double*)beta; w->mv = mv; w->mv_bytes = mvb;
+    w->pq = (double2*)pq; w->alpha = (double*)alpha; w->beta = (double*)beta; w->thr2 = (double*)thr2;
+    w->itol2 = (double*)itol2; w->est = (double*)est; w->cs = (double*)cs; w->H = (double2*)H;
+    w->sn = (double2*)sn; w->g = (double2*)g; w->ist = (int*)ist; w->steps = (long long*)steps;
+    w->mv = mv; w->mv_bytes = mvb;
     w->D = (double2*)D; w->Rr = (double2*)Rr; w->x32 = (float2*)x32; w->y32 = (float2*)y32;
     w->mv32 = mv32; w->mv32_bytes = mvb32;
   }
@@ -638,22 +842,32 @@ struct Ctx {
   SolveWs w;
   int nr, CK, M, fidx, transpose;
   long long N;
-  bool op32 = false;      // apply Z in FP32 (refinement inner solves)
+  int restart = 0;
+  bool op32 = false;      // FP32 operator and FP32 Schur CG (refinement inner solves)
   double t0 = 0;          // start of the solve (progress lines)
-  hipGraphExec_t pcg_graph = nullptr;  // 16 PCG iterations, replayed
-  hipGraph_t pcg_g = nullptr;
+  // per mode (0: FP64, 1: refinement inner solve): conjugate-gradient steps
+  // per preconditioner application (0: not measured yet), the tolerance they
+  // were measured for, and the captured Arnoldi steps (one graph per column)
+  int msteps[2] = {0, 0};
+  double itol[2] = {-1, -1};
+  double itol2_host = 0;
+  std::vector<hipGraphExec_t> graphs[2];
+  int short_seen = 0;     // applications short of their tolerance, as last read
 };
 
-// out = sum over chunks of conj(X_(i,r)) Y_r into dst[(i * nr + r)]
-void mdot(Ctx& c, long long n, int ni, const double2* X, long long xs_i, long long xs_r, const double2* Y,
-          long long ys_r, double2* dst, hipStream_t s) {
-  hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks, ni * c.nr), dim3(256), 0, s, n, c.nr, X, xs_i, xs_r, Y, ys_r,
-                     c.w.part, 1);
-  hipLaunchKernelGGL(k_psum, dim3(ni * c.nr), dim3(256), 0, s, kDotBlocks, c.w.part, dst);
+void drop_graphs(Ctx& c, int mode) {
+  for (hipGraphExec_t& g : c.graphs[mode])
+    if (g) (void)hipGraphExecDestroy(g);
+  c.graphs[mode].clear();
 }
-void mdot(Ctx& c, long long n, int ni, const double2* X, long long xs_i, long long xs_r, const double2* Y,
-          long long ys_r, double2* dst) {
-  mdot(c, n, ni, X, xs_i, xs_r, Y, ys_r, dst, c.s);
+
+// out = sum over chunks of conj(X_(i,r)) Y_r into dst[(i * nr + r)]
+template <class V>
+void mdot(Ctx& c, long long n, int ni, const V* X, long long xs_i, long long xs_r, const V* Y, long long ys_r,
+          double2* dst, hipStream_t s, const int* skip = nullptr) {
+  hipLaunchKernelGGL(k_mdot<V>, dim3(kDotBlocks, ni * c.nr), dim3(256), 0, s, n, c.nr, X, xs_i, xs_r, Y, ys_r,
+                     c.w.part, 1, skip);
+  hipLaunchKernelGGL(k_psum, dim3(ni * c.nr), dim3(256), 0, s, kDotBlocks, c.w.part, dst);
 }
 
 __global__ void k_to32(int nrhs, long long N, int CK, const double2* __restrict__ x, float2* __restrict__ x32) {
@@ -668,99 +882,98 @@ __global__ void k_from32(int nrhs, long long N, int CK, const float2* __restrict
     y[(i / CK) * N + i % CK] = make_double2(v.x, v.y);
   }
 }
+__global__ void k_ist_reset(int n, int* __restrict__ ist, long long* __restrict__ steps) {
+  const int i = threadIdx.x;
+  if (i < n) ist[i] = 0;
+  if (i == 0) steps[0] = 0;
+}
 
-// y = K x (batched columns of length N); the Z block in FP32 when c.op32
-svh_status apply_K(Ctx& c, const double2* x, double2* y) {
+// y = K x (batched columns of length N), enqueued on s; the Z block in FP32
+// when c.op32
+svh_status apply_K(Ctx& c, const double2* x, double2* y, hipStream_t s) {
   svh_problem* p = c.p;
   std::vector<int32_t> fi(c.nr, c.fidx);
   svh_status st;
   if (c.op32) {
     const long long n = (long long)c.CK * c.nr;
-    hipLaunchKernelGGL(k_to32, dim3(nblocks(n)), dim3(256), 0, c.s, c.nr, c.N, c.CK, x, c.w.x32);
-    st = matvec_impl(p, SVH_FP32, c.nr, fi.data(), c.w.x32, c.CK, c.w.y32, c.CK, c.w.mv32, c.w.mv32_bytes, c.s);
+    hipLaunchKernelGGL(k_to32, dim3(nblocks(n)), dim3(256), 0, s, c.nr, c.N, c.CK, x, c.w.x32);
+    st = matvec_impl(p, SVH_FP32, c.nr, fi.data(), c.w.x32, c.CK, c.w.y32, c.CK, c.w.mv32, c.w.mv32_bytes, s);
     if (st != SVH_OK) return st;
-    hipLaunchKernelGGL(k_from32, dim3(nblocks(n)), dim3(256), 0, c.s, c.nr, c.N, c.CK, c.w.y32, y);
+    hipLaunchKernelGGL(k_from32, dim3(nblocks(n)), dim3(256), 0, s, c.nr, c.N, c.CK, c.w.y32, y);
   } else {
-    st = matvec_impl(p, SVH_FP64, c.nr, fi.data(), x, c.N, y, c.N, c.w.mv, c.w.mv_bytes, c.s);
+    st = matvec_impl(p, SVH_FP64, c.nr, fi.data(), x, c.N, y, c.N, c.w.mv, c.w.mv_bytes, s);
     if (st != SVH_OK) return st;
   }
-  hipLaunchKernelGGL(k_saddle_fix, dim3(nblocks((c.CK + c.M) * (long long)c.nr)), dim3(256), 0, c.s, c.nr, c.N,
+  hipLaunchKernelGGL(k_saddle_fix, dim3(nblocks((c.CK + c.M) * (long long)c.nr)), dim3(256), 0, s, c.nr, c.N,
                      c.CK, c.M, p->d_cptr, p->d_crow, p->d_cval, p->d_rptr, p->d_rcol, p->d_rval, p->d_free, x, y,
                      c.transpose);
   SCHK(hipGetLastError());
   return SVH_OK;
 }
+svh_status apply_K(Ctx& c, const double2* x, double2* y) { return apply_K(c, x, y, c.s); }
 
-constexpr int kPcgBlock = 16;  // PCG iterations per convergence check (one graph replay)
+template <class V>
+void vcycle(Ctx& c, const V* b0, V* x0, const int* skip, hipStream_t s);
 
-// One block of kPcgBlock conjugate-gradient iterations on S b = e, enqueued on s.
-void vcycle(Ctx& c, const double2* b0, double2* x0, hipStream_t s);
-
-void pcg_block(Ctx& c, hipStream_t s) {
+// One conjugate-gradient step on S b = e for every right-hand side, enqueued
+// on s; a step that finds every side done does no work.
+template <class V>
+void pcg_step(Ctx& c, hipStream_t s) {
   svh_problem* p = c.p;
   const long long nM = (long long)c.M * c.nr;
-  for (int k = 0; k < kPcgBlock; ++k) {
-    hipLaunchKernelGGL(k_s_half, dim3(resid_blocks(c.CK, c.nr)), dim3(256), 0, s, c.nr, c.CK, c.M,
-                       p->d_cptr, p->d_crow, p->d_cval, p->d_ydiag, c.w.P, c.w.U);
-    hipLaunchKernelGGL(k_s_full, dim3(resid_blocks(c.M, c.nr)), dim3(256), 0, s, c.nr, c.CK, c.M, p->d_rptr, p->d_rcol,
-                       p->d_rval, p->d_free, c.w.U, c.w.Q);
-    mdot(c, c.M, 1, c.w.P, 0, c.M, c.w.Q, c.M, c.w.pq, s);
-    hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(256), 0, s, c.nr, c.w.rho, c.w.pq, c.w.alpha);
-    hipLaunchKernelGGL(k_pcg_update, dim3(nblocks(nM)), dim3(256), 0, s, nM, c.M, p->d_sdiag, p->d_free,
-                       c.w.alpha, c.w.P, c.w.Q, c.w.Bs, c.w.R, c.w.Zp);
-    if (!p->amg.empty()) vcycle(c, c.w.R, c.w.Zp, s);
-    mdot(c, c.M, 1, c.w.R, 0, c.M, c.w.Zp, c.M, c.w.rhon, s);
-    hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(256), 0, s, c.nr, c.w.rho, c.w.rhon, c.w.beta);
-    hipLaunchKernelGGL(k_pcg_dir, dim3(nblocks(nM)), dim3(256), 0, s, nM, c.M, c.w.beta, c.w.Zp, c.w.P);
-  }
+  const int* sk = c.w.ist;
+  V *P = (V*)c.w.P, *U = (V*)c.w.U, *Q = (V*)c.w.Q, *Bs = (V*)c.w.Bs, *R = (V*)c.w.R, *Zp = (V*)c.w.Zp;
+  hipLaunchKernelGGL(k_s_half<V>, dim3(resid_blocks(c.CK, c.nr)), dim3(256), 0, s, c.nr, c.CK, c.M, p->d_cptr,
+                     p->d_crow, p->d_cval, p->d_ydiag, P, U, sk);
+  hipLaunchKernelGGL(k_s_full<V>, dim3(resid_blocks(c.M, c.nr)), dim3(256), 0, s, c.nr, c.CK, c.M, p->d_rptr,
+                     p->d_rcol, p->d_rval, p->d_free, U, Q, sk);
+  mdot<V>(c, c.M, 1, P, 0, c.M, Q, c.M, c.w.pq, s, sk);
+  hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(64), 0, s, c.nr, c.w.rho, c.w.pq, c.w.alpha, c.w.ist);
+  hipLaunchKernelGGL(k_pcg_update<V>, dim3(nblocks(nM)), dim3(256), 0, s, nM, c.M, p->d_sdiag, p->d_free, c.w.alpha,
+                     P, Q, Bs, R, Zp, sk);
+  if (!p->amg.empty()) vcycle<V>(c, R, Zp, sk, s);
+  mdot<V>(c, c.M, 1, R, 0, c.M, Zp, c.M, c.w.rhon, s, sk);
+  hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(64), 0, s, c.nr, c.w.rho, c.w.rhon, c.w.beta, c.w.thr2, c.w.ist,
+                     c.w.steps);
+  hipLaunchKernelGGL(k_pcg_dir<V>, dim3(nblocks(nM)), dim3(256), 0, s, nM, c.M, c.w.beta, Zp, P, sk);
 }
 
-// Capture pcg_block once per solve call (all pointers are fixed workspace
-// buffers) on the problem's private stream; replays run on the caller's stream.
-svh_status pcg_graph(Ctx& c) {
-  svh_problem* p = c.p;
-  if (c.pcg_graph || !p->use_graphs) return SVH_OK;
-  if (!p->cap_stream) SCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
-  SCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-  pcg_block(c, p->cap_stream);
-  SCHK(hipStreamEndCapture(p->cap_stream, &c.pcg_g));
-  SCHK(hipGraphInstantiate(&c.pcg_graph, c.pcg_g, nullptr, nullptr, 0));
-  return SVH_OK;
-}
-
-// out = P in (eqs. 13-15), inner PCG to rel. tolerance itol; returns iterations
-svh_status apply_P(Ctx& c, const double2* in, double2* out, double itol, int imax, int& iters) {
+// out = P in (eqs. 12-15): e from in, S b = e by conjugate gradients to the
+// relative tolerance on the device (itol2), a and b to out.  m >= 0: exactly
+// m steps are enqueued (the steps after every side is done do no work), with
+// no host synchronisation; m < 0: steps in blocks of 8 until the device
+// reports every side done or -m steps ran (synchronises; *used = steps run).
+template <class V>
+svh_status apply_P(Ctx& c, const double2* in, double2* out, int m, hipStream_t s, int* used = nullptr) {
   svh_problem* p = c.p;
   const long long nM = (long long)c.M * c.nr;
-  hipLaunchKernelGGL(k_pre_rhs, dim3(nblocks(nM)), dim3(256), 0, c.s, c.nr, c.N, c.CK, c.M, p->d_rptr, p->d_rcol,
-                     p->d_rval, p->d_free, p->d_ydiag, in, c.w.E, c.transpose);
-  hipLaunchKernelGGL(k_pcg_init, dim3(nblocks(nM)), dim3(256), 0, c.s, nM, c.M, p->d_sdiag, p->d_free, c.w.E,
-                     c.w.R, c.w.Zp, c.w.P, c.w.Bs);
+  V *E = (V*)c.w.E, *R = (V*)c.w.R, *Zp = (V*)c.w.Zp, *P = (V*)c.w.P, *Bs = (V*)c.w.Bs;
+  hipLaunchKernelGGL(k_pre_rhs<V>, dim3(nblocks(nM)), dim3(256), 0, s, c.nr, c.N, c.CK, c.M, p->d_rptr, p->d_rcol,
+                     p->d_rval, p->d_free, p->d_ydiag, in, E, c.transpose);
+  hipLaunchKernelGGL(k_pcg_init<V>, dim3(nblocks(nM)), dim3(256), 0, s, nM, c.M, p->d_sdiag, p->d_free, E, R, Zp, P,
+                     Bs);
   if (!p->amg.empty()) {
-    vcycle(c, c.w.R, c.w.Zp, c.s);
-    hipLaunchKernelGGL(k_copy, dim3(nblocks(nM)), dim3(256), 0, c.s, nM, c.w.Zp, c.w.P);
+    vcycle<V>(c, R, Zp, nullptr, s);
+    hipLaunchKernelGGL(k_vcopy<V>, dim3(nblocks(nM)), dim3(256), 0, s, nM, Zp, P);
   }
-  mdot(c, c.M, 1, c.w.R, 0, c.M, c.w.Zp, c.M, c.w.rho);
-  std::vector<double2> rho0(c.nr), rhoc(c.nr);
-  SCHK(hipMemcpyAsync(rho0.data(), c.w.rho, sizeof(double2) * c.nr, hipMemcpyDeviceToHost, c.s));
-  SCHK(hipStreamSynchronize(c.s));
-  iters = 0;
-  bool any = false;
-  for (int r = 0; r < c.nr; ++r) any = any || rho0[r].x > 0;
-  svh_status st = pcg_graph(c);
-  if (st != SVH_OK) return st;
-  while (any && iters < imax) {
-    if (c.pcg_graph) SCHK(hipGraphLaunch(c.pcg_graph, c.s));
-    else pcg_block(c, c.s);
-    iters += kPcgBlock;
-    SCHK(hipMemcpyAsync(rhoc.data(), c.w.rho, sizeof(double2) * c.nr, hipMemcpyDeviceToHost, c.s));
-    SCHK(hipStreamSynchronize(c.s));
-    any = false;
-    for (int r = 0; r < c.nr; ++r)
-      if (rho0[r].x > 0 && std::sqrt(std::max(rhoc[r].x, 0.0) / rho0[r].x) > itol) any = true;
+  mdot<V>(c, c.M, 1, R, 0, c.M, Zp, c.M, c.w.rho, s);
+  hipLaunchKernelGGL(k_pcg_start, dim3(1), dim3(64), 0, s, c.nr, c.w.rho, c.w.itol2, c.w.thr2, c.w.ist);
+  if (m >= 0) {
+    for (int k = 0; k < m; ++k) pcg_step<V>(c, s);
+  } else {
+    int done = 0, k = 0;
+    while (k < -m) {
+      for (int q = 0; q < 8; ++q) pcg_step<V>(c, s);
+      k += 8;
+      SCHK(hipMemcpyAsync(&done, c.w.ist, sizeof(int), hipMemcpyDeviceToHost, s));
+      SCHK(hipStreamSynchronize(s));
+      if (done) break;
+    }
+    if (used) *used = k;
   }
-  hipLaunchKernelGGL(k_pre_out, dim3(nblocks((c.CK + c.M) * (long long)c.nr)), dim3(256), 0, c.s, c.nr, c.N, c.CK,
-                     c.M, p->d_cptr, p->d_crow, p->d_cval, p->d_ydiag, in, c.w.Bs, out, c.transpose);
+  hipLaunchKernelGGL(k_pcg_end, dim3(1), dim3(64), 0, s, c.w.ist);
+  hipLaunchKernelGGL(k_pre_out<V>, dim3(nblocks((c.CK + c.M) * (long long)c.nr)), dim3(256), 0, s, c.nr, c.N, c.CK,
+                     c.M, p->d_cptr, p->d_crow, p->d_cval, p->d_ydiag, in, Bs, out, c.transpose);
   SCHK(hipGetLastError());
   return SVH_OK;
 }
@@ -842,42 +1055,47 @@ svh_status build_amg(svh_problem* p, const std::vector<double>& yd) {
 // z = B r: one symmetric V-cycle (one damped-Jacobi sweep before and after
 // the scaled coarse correction; on the coarsest level its dense inverse, its
 // diagonal when it has no couplings, or damped Jacobi sweeps) per right-hand
-// side.
-void vcycle(Ctx& c, const double2* b0, double2* x0, hipStream_t s) {
+// side.  Level vectors are used as V arrays (FP32 ones fit in the FP64
+// allocation).
+template <class V>
+void vcycle(Ctx& c, const V* b0, V* x0, const int* skip, hipStream_t s) {
   svh_problem* p = c.p;
   const int nl = (int)p->amg.size(), nr = c.nr;
   for (int l = 0; l < nl; ++l) {
     auto& L = p->amg[l];
-    const double2* b = l ? L.b : b0;
-    double2* x = l ? L.x : x0;
+    const V* b = l ? (const V*)L.b : b0;
+    V* x = l ? (V*)L.x : x0;
+    V* r = (V*)L.r;
     const long long n = (long long)L.n * nr;
     if (l == nl - 1) {
       if (p->amg_coarse == kAmgCoarseDense) {
-        hipLaunchKernelGGL(k_amg_coarse, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, p->d_amg_cinv, b, x);
+        hipLaunchKernelGGL(k_amg_coarse<V>, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, p->d_amg_cinv, b, x, skip);
       } else {  // diagonal matrix (exact), or damped Jacobi sweeps
-        hipLaunchKernelGGL(k_amg_smooth0, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, b, x);
+        hipLaunchKernelGGL(k_amg_smooth0<V>, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, b, x, skip);
         for (int k = 1; k < (p->amg_coarse == kAmgCoarseJacobi ? kAmgCoarseSweeps : 1); ++k) {
-          amg_resid(L, nr, b, x, L.r, s);
-          hipLaunchKernelGGL(k_amg_jacobi, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, L.r, x);
+          amg_resid<V>(L, nr, b, x, r, skip, s);
+          hipLaunchKernelGGL(k_amg_jacobi<V>, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, r, x, skip);
         }
       }
       break;
     }
-    hipLaunchKernelGGL(k_amg_smooth0, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, b, x);
-    amg_resid(L, nr, b, x, L.r, s);
+    hipLaunchKernelGGL(k_amg_smooth0<V>, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, b, x, skip);
+    amg_resid<V>(L, nr, b, x, r, skip, s);
     auto& Cl = p->amg[l + 1];
-    hipLaunchKernelGGL(k_amg_restrict, dim3(nblocks((long long)Cl.n * nr)), dim3(256), 0, s, nr, L.n, Cl.n, L.mptr,
-                       L.mem, L.r, Cl.b);
+    hipLaunchKernelGGL(k_amg_restrict<V>, dim3(nblocks((long long)Cl.n * nr)), dim3(256), 0, s, nr, L.n, Cl.n,
+                       L.mptr, L.mem, r, (V*)Cl.b, skip);
   }
   for (int l = nl - 2; l >= 0; --l) {
     auto& L = p->amg[l];
     auto& Cl = p->amg[l + 1];
-    const double2* b = l ? L.b : b0;
-    double2* x = l ? L.x : x0;
+    const V* b = l ? (const V*)L.b : b0;
+    V* x = l ? (V*)L.x : x0;
+    V* r = (V*)L.r;
     const long long n = (long long)L.n * nr;
-    hipLaunchKernelGGL(k_amg_prolong, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, Cl.n, L.agg, Cl.x, x);
-    amg_resid(L, nr, b, x, L.r, s);
-    hipLaunchKernelGGL(k_amg_jacobi, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, L.r, x);
+    hipLaunchKernelGGL(k_amg_prolong<V>, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, Cl.n, L.agg, (const V*)Cl.x, x,
+                       skip);
+    amg_resid<V>(L, nr, b, x, r, skip, s);
+    hipLaunchKernelGGL(k_amg_jacobi<V>, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, r, x, skip);
   }
 }
 
@@ -915,37 +1133,20 @@ svh_status prepare_diag(svh_problem* p, int f) {
   return SVH_OK;
 }
 
-// complex Givens rotation zeroing b below a (b real >= 0)
-void givens(cd a, double b, double& cs, cd& sn, cd& r) {
-  const double aa = std::abs(a);
-  if (aa == 0) {
-    cs = 0;
-    sn = 1;
-    r = b;
-    return;
-  }
-  const double rho = std::sqrt(aa * aa + b * b);
-  cs = aa / rho;
-  sn = (a / aa) * b / rho;
-  r = (a / aa) * rho;
-}
-
 struct FgmresStats {
   int total = 0, inner = 0, restarts = 0;
 };
 
 svh_status finish(Ctx& c, svh_status st) {
-  if (c.pcg_graph) (void)hipGraphExecDestroy(c.pcg_graph);
-  if (c.pcg_g) (void)hipGraphDestroy(c.pcg_g);
-  c.pcg_graph = nullptr;
-  c.pcg_g = nullptr;
+  drop_graphs(c, 0);
+  drop_graphs(c, 1);
   return st;
 }
 
 // per-column 2-norms of a batch of N-vectors
 svh_status norms(Ctx& c, const double2* v, std::vector<double>& out) {
   svh_problem* p = c.p;
-  mdot(c, c.N, 1, v, 0, c.N, v, c.N, c.w.nrm);
+  mdot<double2>(c, c.N, 1, v, 0, c.N, v, c.N, c.w.nrm, c.s);
   std::vector<double2> h(c.nr);
   SCHK(hipMemcpyAsync(h.data(), c.w.nrm, sizeof(double2) * c.nr, hipMemcpyDeviceToHost, c.s));
   SCHK(hipStreamSynchronize(c.s));
@@ -954,19 +1155,98 @@ svh_status norms(Ctx& c, const double2* v, std::vector<double>& out) {
   return SVH_OK;
 }
 
+constexpr int kInnerMax = 20000;  // conjugate-gradient steps per application at most
+// default Schur CG tolerance of the refinement's inner solves, whose CG runs
+// in FP32 (about 1e-7 of rounding); the preconditioner of a flexible GMRES
+// need not be exact
+constexpr double kIrSchurTol = 1e-4;
+// Arnoldi steps between reads of the residual estimates, and every step once
+// the worst estimate is within kCheckNear of its target
+constexpr int kCheckEvery = 4;
+constexpr double kCheckNear = 30.0;
+
+// One Arnoldi step of column j, enqueued on s without host synchronisation
+// (unless probe != nullptr): Zk_j = P V_j with m inner steps, w = K Zk_j,
+// CGS2 against V_0..V_j, V_{j+1} = w / ||w||, and the Hessenberg column
+// rotated on the device (est = residual estimates).  probe: the inner solve
+// runs to its tolerance with host checks and *probe receives its steps.
+svh_status arnoldi_step(Ctx& c, int j, int m, hipStream_t s, int* probe = nullptr) {
+  svh_problem* p = c.p;
+  const int nr = c.nr;
+  const long long NN = c.N * nr, vs = NN;
+  svh_status st = c.op32 ? apply_P<float2>(c, c.w.V + j * vs, c.w.Zk + j * vs, probe ? -kInnerMax : m, s, probe)
+                         : apply_P<double2>(c, c.w.V + j * vs, c.w.Zk + j * vs, probe ? -kInnerMax : m, s, probe);
+  if (st != SVH_OK) return st;
+  if ((st = apply_K(c, c.w.Zk + j * vs, c.w.W, s)) != SVH_OK) return st;
+  mdot<double2>(c, c.N, j + 1, c.w.V, vs, c.N, c.w.W, c.N, c.w.h, s);
+  hipLaunchKernelGGL(k_cgs_update, dim3(nblocks(NN)), dim3(256), 0, s, c.N, nr, j + 1, c.w.V, vs, c.w.h, c.w.W);
+  mdot<double2>(c, c.N, j + 1, c.w.V, vs, c.N, c.w.W, c.N, c.w.h2, s);
+  hipLaunchKernelGGL(k_cgs_update, dim3(nblocks(NN)), dim3(256), 0, s, c.N, nr, j + 1, c.w.V, vs, c.w.h2, c.w.W);
+  hipLaunchKernelGGL(k_add_small, dim3(((j + 1) * nr + 255) / 256), dim3(256), 0, s, (j + 1) * nr, c.w.h, c.w.h2);
+  mdot<double2>(c, c.N, 1, c.w.W, 0, c.N, c.w.W, c.N, c.w.nrm, s);
+  hipLaunchKernelGGL(k_normalize, dim3(nblocks(NN)), dim3(256), 0, s, c.N, nr, c.w.nrm, c.w.W, c.w.V + (j + 1) * vs);
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, nr, j, c.restart, c.w.h, c.w.nrm, c.w.H, c.w.cs, c.w.sn,
+                     c.w.g, c.w.est);
+  SCHK(hipGetLastError());
+  return SVH_OK;
+}
+
+// The Arnoldi step of column j replayed from a graph captured on the
+// problem's private stream (all operands are fixed workspace buffers, so one
+// graph per column serves every cycle of the solve).
+svh_status graph_step(Ctx& c, int j) {
+  svh_problem* p = c.p;
+  const int mode = c.op32 ? 1 : 0;
+  std::vector<hipGraphExec_t>& gv = c.graphs[mode];
+  if ((int)gv.size() < c.restart) gv.resize(c.restart, nullptr);
+  if (!gv[j]) {
+    if (!p->cap_stream) SCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    SCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    const svh_status st = arnoldi_step(c, j, c.msteps[mode], p->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+    if (st != SVH_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    SCHK(e);
+    const hipError_t ei = hipGraphInstantiate(&gv[j], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    SCHK(ei);
+  }
+  SCHK(hipGraphLaunch(gv[j], c.s));
+  return SVH_OK;
+}
+
 // Right-preconditioned flexible GMRES(restart) on K X = B for every column,
 // starting from the X given; stops when every column's residual estimate is
-// below rre * bnorm[r] or after maxit steps.
+// below rre * bnorm[r] or after maxit steps.  The inner solve runs to the
+// relative tolerance itol: its step count per application is measured once
+// (with host checks), then every Arnoldi step is enqueued (or replayed from
+// its graph) without host synchronisation, and the residual estimates are
+// read every kCheckEvery steps.  When an application ends short of itol, the
+// step count doubles (up to kInnerMax) and the graphs are captured again.
 svh_status fgmres(Ctx& c, const double2* B, double2* X, const std::vector<double>& bnorm, double rre, int restart,
                   int maxit, double itol, FgmresStats& fs, int max_cycles = 1 << 30) {
   svh_problem* p = c.p;
   const int nr = c.nr;
+  const int mode = c.op32 ? 1 : 0;
   const long long NN = c.N * nr;
   const long long vs = NN;  // stride between Krylov vectors
-  const int imax = 20000;
+  const bool graphs = p->use_graphs && !p->prof;
   svh_status st;
+  if (itol != c.itol[mode]) {
+    c.itol[mode] = itol;
+    c.msteps[mode] = 0;
+    drop_graphs(c, mode);
+  }
+  c.itol2_host = itol * itol;
+  SCHK(hipMemcpyAsync(c.w.itol2, &c.itol2_host, sizeof(double), hipMemcpyHostToDevice, c.s));
   int steps = 0, cycles = 0;
   bool first = true;
+  std::vector<double> est(nr, 0.0);
+  int hist[2] = {0, 0};
+  long long inner = 0;
   while (steps < maxit && cycles < max_cycles) {
     if (first) {
       hipLaunchKernelGGL(k_copy, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, B, c.w.W);
@@ -983,84 +1263,59 @@ svh_status fgmres(Ctx& c, const double2* B, double2* X, const std::vector<double
       if (bnorm[r] > 0 && beta[r] > rre * bnorm[r]) done = false;
     if (done) return SVH_OK;
     hipLaunchKernelGGL(k_normalize, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, c.w.nrm, c.w.W, c.w.V);
-    std::vector<std::vector<cd>> H(nr, std::vector<cd>((size_t)(restart + 1) * restart, 0.0));
-    std::vector<std::vector<double>> cs(nr, std::vector<double>(restart, 0.0));
-    std::vector<std::vector<cd>> sn(nr, std::vector<cd>(restart, 0.0));
-    std::vector<std::vector<cd>> g(nr, std::vector<cd>(restart + 1, 0.0));
-    for (int r = 0; r < nr; ++r) g[r][0] = beta[r];
+    hipLaunchKernelGGL(k_givens_init, dim3(1), dim3(64), 0, c.s, nr, restart, c.w.nrm, c.w.g, c.w.est);
     int jdone = 0;
-    std::vector<double2> hcol((size_t)(restart + 2) * nr);
+    bool near = false;
     for (int j = 0; j < restart && steps < maxit; ++j) {
-      int it = 0;
-      if ((st = apply_P(c, c.w.V + j * vs, c.w.Zk + j * vs, itol, imax, it)) != SVH_OK) return st;
-      fs.inner += it;
-      if ((st = apply_K(c, c.w.Zk + j * vs, c.w.W)) != SVH_OK) return st;
-      // CGS2
-      mdot(c, c.N, j + 1, c.w.V, vs, c.N, c.w.W, c.N, c.w.h);
-      hipLaunchKernelGGL(k_cgs_update, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, j + 1, c.w.V, vs, c.w.h,
-                         c.w.W);
-      mdot(c, c.N, j + 1, c.w.V, vs, c.N, c.w.W, c.N, c.w.h2);
-      hipLaunchKernelGGL(k_cgs_update, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, j + 1, c.w.V, vs, c.w.h2,
-                         c.w.W);
-      hipLaunchKernelGGL(k_add_small, dim3(((j + 1) * nr + 255) / 256), dim3(256), 0, c.s, (j + 1) * nr, c.w.h,
-                         c.w.h2);
-      mdot(c, c.N, 1, c.w.W, 0, c.N, c.w.W, c.N, c.w.nrm);
-      hipLaunchKernelGGL(k_normalize, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, c.w.nrm, c.w.W,
-                         c.w.V + (j + 1) * vs);
-      SCHK(hipMemcpyAsync(hcol.data(), c.w.h, sizeof(double2) * (j + 1) * nr, hipMemcpyDeviceToHost, c.s));
-      SCHK(hipMemcpyAsync(hcol.data() + (size_t)(j + 1) * nr, c.w.nrm, sizeof(double2) * nr,
-                          hipMemcpyDeviceToHost, c.s));
-      SCHK(hipStreamSynchronize(c.s));
+      if (c.msteps[mode] == 0) {
+        int used = 0;
+        if ((st = arnoldi_step(c, j, 0, c.s, &used)) != SVH_OK) return st;
+        c.msteps[mode] = std::min(kInnerMax, (used + std::max(4, used / 4) + 3) / 4 * 4);
+      } else if (graphs) {
+        if ((st = graph_step(c, j)) != SVH_OK) return st;
+      } else {
+        if ((st = arnoldi_step(c, j, c.msteps[mode], c.s)) != SVH_OK) return st;
+      }
       ++steps;
       ++fs.total;
       jdone = j + 1;
-      bool all = true;
-      for (int r = 0; r < nr; ++r) {
-        std::vector<cd>& Hr = H[r];
-        for (int i = 0; i <= j; ++i)
-          Hr[(size_t)i * restart + j] = cd(hcol[(size_t)i * nr + r].x, hcol[(size_t)i * nr + r].y);
-        const double hj1 = std::sqrt(std::max(hcol[(size_t)(j + 1) * nr + r].x, 0.0));
-        for (int i = 0; i < j; ++i) {
-          const cd a = Hr[(size_t)i * restart + j], b = Hr[(size_t)(i + 1) * restart + j];
-          Hr[(size_t)i * restart + j] = cs[r][i] * a + sn[r][i] * b;
-          Hr[(size_t)(i + 1) * restart + j] = -std::conj(sn[r][i]) * a + cs[r][i] * b;
+      if (jdone % kCheckEvery == 0 || near || jdone == restart || steps >= maxit) {
+        SCHK(hipMemcpyAsync(est.data(), c.w.est, sizeof(double) * nr, hipMemcpyDeviceToHost, c.s));
+        SCHK(hipMemcpyAsync(hist, c.w.ist, sizeof(int) * 2, hipMemcpyDeviceToHost, c.s));
+        SCHK(hipMemcpyAsync(&inner, c.w.steps, sizeof(long long), hipMemcpyDeviceToHost, c.s));
+        SCHK(hipStreamSynchronize(c.s));
+        fs.inner = (int)inner;
+        if (hist[1] > c.short_seen) {
+          c.short_seen = hist[1];
+          if (c.msteps[mode] < kInnerMax) {
+            c.msteps[mode] = std::min(kInnerMax, (c.msteps[mode] * 3 / 2 + 3) / 4 * 4);
+            drop_graphs(c, mode);
+          }
         }
-        cd rr;
-        givens(Hr[(size_t)j * restart + j], hj1, cs[r][j], sn[r][j], rr);
-        Hr[(size_t)j * restart + j] = rr;
-        const cd gj = g[r][j];
-        g[r][j] = cs[r][j] * gj;
-        g[r][j + 1] = -std::conj(sn[r][j]) * gj;
-        if (bnorm[r] > 0 && std::abs(g[r][j + 1]) > rre * bnorm[r]) all = false;
+        double worst = 0;
+        for (int r = 0; r < nr; ++r)
+          if (bnorm[r] > 0) worst = std::max(worst, est[r] / (rre * bnorm[r]));
+        if (worst <= 1.0) break;
+        near = worst <= kCheckNear;
       }
-      if (all) break;
     }
     // y = H^-1 g, x += Zk y
-    std::vector<double2> coef((size_t)jdone * nr);
-    for (int r = 0; r < nr; ++r) {
-      std::vector<cd> y(jdone);
-      for (int i = jdone - 1; i >= 0; --i) {
-        cd acc = g[r][i];
-        for (int k = i + 1; k < jdone; ++k) acc -= H[r][(size_t)i * restart + k] * y[k];
-        const cd d = H[r][(size_t)i * restart + i];
-        y[i] = std::abs(d) > 0 ? acc / d : cd(0.0);
-      }
-      for (int i = 0; i < jdone; ++i) coef[(size_t)i * nr + r] = make_double2(y[i].real(), y[i].imag());
-    }
-    SCHK(hipMemcpyAsync(c.w.h2, coef.data(), sizeof(double2) * coef.size(), hipMemcpyHostToDevice, c.s));
+    hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, c.s, nr, jdone, restart, c.w.H, c.w.g, c.w.h2);
     hipLaunchKernelGGL(k_combine, dim3(nblocks(NN)), dim3(256), 0, c.s, c.N, nr, jdone, c.w.Zk, vs, c.w.h2, X);
+    SCHK(hipGetLastError());
     ++fs.restarts;
     ++cycles;
-    SCHK(hipStreamSynchronize(c.s));
     if (verbose(p)) {
       double worst = 0;
       for (int r = 0; r < nr; ++r)
-        if (bnorm[r] > 0) worst = std::max(worst, std::abs(g[r][jdone]) / bnorm[r]);
-      std::fprintf(stderr, "[svh] fgmres cycle %d (%s): %d steps, estimate %.3e, inner CG steps %d, %.2f s\n",
-                   cycles, c.op32 ? "fp32 operator" : "fp64", fs.total, worst, fs.inner, now_s() - c.t0);
+        if (bnorm[r] > 0) worst = std::max(worst, est[r] / bnorm[r]);
+      std::fprintf(stderr, "[svh] fgmres cycle %d (%s): %d steps, estimate %.3e, inner CG steps %d (%d per "
+                   "application), %.2f s\n", cycles, c.op32 ? "fp32 operator" : "fp64", fs.total, worst, fs.inner,
+                   c.msteps[mode], now_s() - c.t0);
       std::fflush(stderr);
     }
   }
+  SCHK(hipStreamSynchronize(c.s));
   return SVH_ENOTCONV;
 }
 
@@ -1220,8 +1475,10 @@ svh_status svh_solve(svh_problem* p, svh_prec prec, int freq_idx, double rre, in
   c.N = (long long)c.CK + c.M;
   c.fidx = freq_idx;
   c.transpose = transpose ? 1 : 0;
+  c.restart = restart;
   c.t0 = now_s();
   carve(p, restart, prec, static_cast<char*>((void*)(((uintptr_t)ws + 255) & ~(uintptr_t)255)), &c.w);
+  hipLaunchKernelGGL(k_ist_reset, dim3(1), dim3(128), 0, c.s, 2 + c.nr, c.w.ist, c.w.steps);
   svh_status st = prepare_diag(p, freq_idx);
   if (st != SVH_OK) return st;
   if (verbose(p)) {
@@ -1242,7 +1499,8 @@ svh_status svh_solve(svh_problem* p, svh_prec prec, int freq_idx, double rre, in
   std::vector<double> relres(nr, 1.0);
   if (prec == SVH_FP64) {
     c.op32 = false;
-    st = fgmres(c, c.w.Rhs, X, bnorm, rre, restart, maxit, p->schur_tol > 0 ? p->schur_tol : std::min(1e-8, rre), fs);
+    const double itol = p->schur_tol > 0 ? p->schur_tol : std::max(1e-12, std::min(1e-8, rre));
+    st = fgmres(c, c.w.Rhs, X, bnorm, rre, restart, maxit, itol, fs);
     if (st != SVH_OK && st != SVH_ENOTCONV) return finish(c, st);
   } else {
     // iterative refinement: FP64 residual, FP32 operator in the inner solve
@@ -1265,7 +1523,7 @@ svh_status svh_solve(svh_problem* p, svh_prec prec, int freq_idx, double rre, in
         if (rn[r] > 0) need = std::min(need, rre * bnorm[r] / rn[r]);
       const double tin = std::max(inner, need);
       st = fgmres(c, c.w.Rr, c.w.D, rn, tin, restart, maxit - fs.total,
-                  p->schur_tol > 0 ? p->schur_tol : std::min(1e-8, tin * 1e-2), fs, 1);
+                  p->schur_tol > 0 ? p->schur_tol : kIrSchurTol, fs, 1);
       if (st != SVH_OK && st != SVH_ENOTCONV) return finish(c, st);
       hipLaunchKernelGGL(k_add, dim3(nblocks(NN)), dim3(256), 0, c.s, NN, c.w.D, X);
       c.op32 = false;
