@@ -226,6 +226,8 @@ def bench_basis5(args, cfg, mask, fidx, dev):
     p = svh.Problem(mask, dx, basis=5)
     p.set_material(freqs, sigma0, lam)
     p.setup_tensors()
+    if args.zstep in ("auto", "fft", "direct"):
+        p.set_zstep(args.zstep)
     t_setup = time.perf_counter() - t
     t = time.perf_counter()
     ranks, terr = p.tucker_compress(args.tol)
@@ -486,6 +488,8 @@ def bench_c5_solve(args):
     cfg = wl.WORKLOADS["c5_stack"]
     mask, ports = wl.layered_stack_with_ports(cfg["seed"])
     freqs = [cfg["freqs"][0], cfg["freqs"][-1]]
+    if args.c5_freq >= 0:
+        freqs = [freqs[args.c5_freq]]
     t = time.perf_counter()
     p = svh.Problem(mask, cfg["dx"], basis=5)
     p.set_material(freqs, cfg["sigma0"], cfg["lam"])
@@ -713,6 +717,8 @@ def main():
     ap.add_argument("--c5-solve", action="store_true",
                     help="port solve of the stack with its 8 port-gap vias (five components)")
     ap.add_argument("--no-matvec", action="store_true", help="skip the matvec sections (with --c5-solve etc.)")
+    ap.add_argument("--c5-freq", type=int, default=-1,
+                    help="with --c5-solve: 0 = lowest frequency only, 1 = highest only (default both)")
     ap.add_argument("--table2", default="",
                     help="comma-separated cube edges (voxels) for the Toeplitz-store experiment, e.g. 100,200")
     ap.add_argument("--copy-probe", action="store_true",
