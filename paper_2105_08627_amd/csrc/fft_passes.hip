@@ -449,6 +449,141 @@ Geo make_geo(const svh_problem* p, size_t csize) {
   return g;
 }
 
+// FP32 variant of the coupled five-component z step for up to 24 occupied
+// planes with the kernel values in registers: thread (w, s, i) of a block of
+// W pencils x S j-sets x NZ rows keeps g_f(|z_i - z_j|) of its pencil for all
+// seven families and its j = s, s + S, ... (the z-odd family with its sign),
+// so the sum over j reads only the five staged components from LDS: 40 bytes
+// per 24 FMAs, against 96 bytes per 48 FMAs (and a quarter of the row slots
+// idle at 24 planes) when the kernel values are read from LDS.  The S partial
+// sums of a row meet through lane exchanges (S = 2 keeps 24 planes within the
+// register file).
+template <int NZ, int W, int S>
+__global__ void __launch_bounds__(W * S * NZ) k_zdirect5r(Geo geo, int Lx, int Ly, int nzp, int nd, int nrhs,
+                                                          int rpb, const uint8_t* __restrict__ qtab,
+                                                          const float* __restrict__ g5, float2* __restrict__ B) {
+  constexpr int NT = W * S * NZ;
+  constexpr int NF = 7;
+  constexpr int NJ = NZ / S;
+  // staged operands per (plane j, pencil w): Ix, Iy, Iz, u = I2D + I3D,
+  // w = I2D - I3D, I3D and two pad values (64 bytes, read as three 16-byte
+  // loads); the pencil pitch is 10 complex values (80 bytes) so that the
+  // 16-byte loads of neighbouring pencils fall into different banks
+  constexpr int PW = 10;
+  static_assert(NZ % S == 0 && (S == 1 || (S == 2 && W <= 32)), "j pairs are lanes t and t ^ W of one wave");
+  extern __shared__ unsigned char smem_raw[];
+  float2* xs = reinterpret_cast<float2*>(smem_raw);                    // [NZ][W][PW]
+  float* gs = reinterpret_cast<float*>(xs + (size_t)NZ * W * PW);      // [7][nd][W]
+  float2* raw = reinterpret_cast<float2*>(gs + (size_t)NF * nd * W);   // [5][NZ][W] staging of the loads
+  const int t = threadIdx.x;
+  const int ntile = (Lx + W - 1) / W;
+  const int bid = first_item();  // XCD-aware order of the (tile, ky) blocks
+  const int tile = bid % ntile, ky = bid / ntile;
+  const int kx0 = tile * W;
+  const int w = t % W, sj = (t / W) % S, i = t / (W * S);
+  const bool valid = kx0 + w < Lx && i < nzp && sj == 0;
+  for (int e = t; e < NF * nd * W; e += NT) {
+    const int ww = e % W, fq = e / W;
+    gs[e] = kx0 + ww < Lx ? g5[((size_t)fq * Ly + ky) * Lx + kx0 + ww] : 0.f;
+  }
+  __syncthreads();
+  float kr[NF][NJ];
+#pragma unroll
+  for (int jj = 0; jj < NJ; ++jj) {
+    const int j = sj + S * jj;
+    const bool on = i < nzp && j < nzp;
+    const uint32_t code = on ? qtab[i * 32 + j] : 0u;
+    const float* gq = gs + (code & 0x7fu) * W + w;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) kr[f][jj] = on ? gq[f * nd * W] : 0.f;
+    if (code & 0x80u) kr[3][jj] = -kr[3][jj];
+  }
+  const size_t plane = (size_t)geo.pb;
+  float2* base = B + (size_t)ky * geo.rp + kx0;
+  const int rbeg = blockIdx.y * rpb;
+  const int rend = min(nrhs, rbeg + rpb);
+  constexpr int NE = 5 * NZ * W;
+  constexpr int EPT = (NE + NT - 1) / NT;
+  constexpr int NP = NZ * W;  // (j, w) pairs
+  float2 pre[EPT];
+  auto fetch = [&](int rhs) {
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = t + NT * q;
+      const int ww = e % W, j = (e / W) % NZ, c = e / (W * NZ);
+      pre[q] = (e < NE && j < nzp && kx0 + ww < Lx)
+                   ? ld_stream(base + ((size_t)(rhs * 5 + c) * nzp + j) * plane + ww)
+                   : float2{0.f, 0.f};
+    }
+  };
+  if (rbeg < rend) fetch(rbeg);
+  for (int rhs = rbeg; rhs < rend; ++rhs) {
+    __syncthreads();  // previous right-hand side's readers are done with xs and raw
+#pragma unroll
+    for (int q = 0; q < EPT; ++q)
+      if (t + NT * q < NE) raw[t + NT * q] = pre[q];
+    __syncthreads();
+    if (rhs + 1 < rend) fetch(rhs + 1);
+    // the six operands of each (j, w)
+    for (int e = t; e < NP; e += NT) {
+      const int ww = e % W, j = e / W;
+      const float2 ix = raw[(0 * NZ + j) * W + ww], iy = raw[(1 * NZ + j) * W + ww];
+      const float2 iz = raw[(2 * NZ + j) * W + ww], i2 = raw[(3 * NZ + j) * W + ww];
+      const float2 i3 = raw[(4 * NZ + j) * W + ww];
+      float4* d = reinterpret_cast<float4*>(xs + ((size_t)j * W + ww) * PW);
+      d[0] = float4{ix.x, ix.y, iy.x, iy.y};
+      d[1] = float4{iz.x, iz.y, i2.x + i3.x, i2.y + i3.y};
+      d[2] = float4{i2.x - i3.x, i2.y - i3.y, i3.x, i3.y};
+    }
+    __syncthreads();
+    float a[24];
+#pragma unroll
+    for (int k = 0; k < 24; ++k) a[k] = 0.f;
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+      const int j = sj + S * jj;
+      const float4* q = reinterpret_cast<const float4*>(xs + ((size_t)j * W + w) * PW);
+      const float4 p0 = q[0], p1 = q[1], p2 = q[2];
+      const float2 ix = float2{p0.x, p0.y}, iy = float2{p0.z, p0.w};
+      const float2 iz = float2{p1.x, p1.y}, u = float2{p1.z, p1.w};
+      const float2 v = float2{p2.x, p2.y}, i3 = float2{p2.z, p2.w};
+      const float g0 = kr[0][jj], g1x = kr[1][jj], g1y = kr[2][jj], g1z = kr[3][jj];
+      const float g2x = kr[4][jj], g2y = kr[5][jj], g2z = kr[6][jj];
+      a[0] += g0 * ix.x;  a[1] += g0 * ix.y;
+      a[2] += g0 * iy.x;  a[3] += g0 * iy.y;
+      a[4] += g0 * iz.x;  a[5] += g0 * iz.y;
+      a[6] += g1x * u.x;  a[7] += g1x * u.y;
+      a[8] += g1x * ix.x; a[9] += g1x * ix.y;
+      a[10] += g1y * v.x; a[11] += g1y * v.y;
+      a[12] += g1y * iy.x; a[13] += g1y * iy.y;
+      a[14] += g1z * i3.x; a[15] += g1z * i3.y;
+      a[16] += g1z * iz.x; a[17] += g1z * iz.y;
+      a[18] += g2x * u.x; a[19] += g2x * u.y;
+      a[20] += g2y * v.x; a[21] += g2y * v.y;
+      a[22] += g2z * i3.x; a[23] += g2z * i3.y;
+    }
+    if constexpr (S == 2) {
+#pragma unroll
+      for (int k = 0; k < 24; ++k) a[k] += __shfl_xor(a[k], W);
+    }
+    if (!valid) continue;
+    // the same combination into the 17 blocks as k_zdirect5
+    const float2 yx = float2{a[0] - a[7], a[1] + a[6]};
+    const float2 yy = float2{a[2] + a[11], a[3] - a[10]};
+    const float2 yz = float2{a[4] - 2 * a[14], a[5] - 2 * a[15]};
+    const float2 y2 = float2{-(a[13] - a[9]) + a[18] + a[20], (a[12] - a[8]) + a[19] + a[21]};
+    const float2 y3 = float2{(a[9] + a[13]) + 2 * a[16] + a[18] - a[20] + 4 * a[22],
+                             -(a[8] + a[12]) + 2 * a[17] + a[19] - a[21] + 4 * a[23]};
+    float2* o = base + ((size_t)(rhs * 5) * nzp + i) * plane + w;
+    const size_t cs = (size_t)nzp * plane;
+    st_stream(o, yx);
+    st_stream(o + cs, yy);
+    st_stream(o + 2 * cs, yz);
+    st_stream(o + 3 * cs, y2);
+    st_stream(o + 4 * cs, y3);
+  }
+}
+
 // Direct z sum (occupied planes) or padded z FFT: the direct sum whenever it
 // applies (at most 32 occupied planes; with five components also at most 64
 // distinct plane offsets) unless the FFT is asked for.
@@ -550,12 +685,37 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     using I24 = std::integral_constant<int, 24>;
     using I32 = std::integral_constant<int, 32>;
     using RGmax = std::integral_constant<int, sizeof(T) == 8 ? 32 : 16>;
+    // FP32 with up to 24 planes: kernel values in registers (k_zdirect5r),
+    // 16 pencils x NZ rows per block (x 2 j-sets at 24 planes; 8 pencils per
+    // block measured slower, 15.7 against 12.8 ms on the stack)
+    auto gor = [&](auto nzt) -> hipError_t {
+      constexpr int NZc = decltype(nzt)::value, SJ = NZc > 16 ? 2 : 1, W = 16;
+      const int ntile = (Lx + W - 1) / W;
+      const int nblk = ntile * Ly;
+      int rpb = nrhs;
+      while (rpb > 1 && (long long)nblk * ((nrhs + rpb - 1) / rpb) < 4096) rpb = (rpb + 1) / 2;
+      dim3 grid(nblk, (nrhs + rpb - 1) / rpb);
+      const size_t sh = (size_t)NZc * W * 10 * sizeof(float2) + (size_t)7 * nd * W * sizeof(float) +
+                        (size_t)5 * NZc * W * sizeof(float2);
+      if (sh > (size_t)p->max_lds) return hipErrorInvalidConfiguration;
+      hipLaunchKernelGGL((k_zdirect5r<NZc, W, SJ>), grid, dim3(W * SJ * NZc), sh, s, geo, Lx, Ly, nzp, nd, nrhs, rpb,
+                         p->d_qtab, static_cast<const float*>(zhat), reinterpret_cast<float2*>(B));
+      return hipSuccess;
+    };
     hipError_t ez;
-    switch (NZ) {
-      case 8: ez = go(I8{}, I8{}); break;
-      case 16: ez = go(I16{}, I16{}); break;
-      case 24: ez = go(I24{}, RGmax{}); break;
-      default: ez = go(I32{}, RGmax{}); break;
+    if (sizeof(T) == 4 && NZ <= 24 && p->zdirect5_regs) {
+      switch (NZ) {
+        case 8: ez = gor(I8{}); break;
+        case 16: ez = gor(I16{}); break;
+        default: ez = gor(I24{}); break;
+      }
+    } else {
+      switch (NZ) {
+        case 8: ez = go(I8{}, I8{}); break;
+        case 16: ez = go(I16{}, I16{}); break;
+        case 24: ez = go(I24{}, RGmax{}); break;
+        default: ez = go(I32{}, RGmax{}); break;
+      }
     }
     if (ez != hipSuccess) return ez;
   } else if (zdirect) {
