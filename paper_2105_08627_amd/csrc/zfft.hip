@@ -4,8 +4,10 @@
 // every item of its share of the batch, so the spectrum values of its pencils
 // are read from HBM once per launch.
 //
-// Per item the occupied planes of the x/y-transformed data are loaded into an
-// LDS array indexed by z (coalesced runs of W x-adjacent values); the first
+// Per item the occupied planes of the x/y-transformed data are loaded into
+// LDS pencils indexed by z (coalesced runs of W x-adjacent values; a pencil's
+// threads are consecutive, so the stages of a pencil that fits in one
+// wavefront are ordered without block barriers); the first
 // forward stage reads the unoccupied positions as zeros, so nothing is
 // cleared.  The last forward stage, the spectrum product and the first
 // inverse stage run in registers (Stockham: the last forward stage leaves
@@ -37,14 +39,23 @@ namespace svh {
 
 namespace {
 
-// LDS pencils (element (n, w) at n * W + w); positions whose z plane is
-// empty read as zero.
+// LDS pencils in the pencil layout of Lds<C, false> (element (n, w) at
+// w * Lp + n + n / 8); positions whose z plane is empty read as zero.
 template <typename C> struct LdsOcc {
   C* base;
-  int W, w;
+  int Lp, w;
   const uint8_t* occ;
-  __device__ __forceinline__ C ld(int n) const { return occ[n] ? base[n * W + w] : C{0, 0}; }
+  __device__ __forceinline__ C ld(int n) const { return occ[n] ? base[w * Lp + n + (n >> 3)] : C{0, 0}; }
 };
+__device__ __forceinline__ int pencil_at(int w, int n, int Lp) { return w * Lp + n + (n >> 3); }
+
+// Ordering of the LDS stages of one pencil: the lanes of a pencil are
+// consecutive threads, so when the pencils do not straddle wavefronts
+// (threads per pencil divide 64) wavefront ordering suffices.
+template <bool WAVE> __device__ __forceinline__ void pencil_sync() {
+  if constexpr (WAVE) wave_sync();
+  else __syncthreads();
+}
 
 __device__ __forceinline__ int fold_index(int k, int L) { return k <= L / 2 ? k : L - k; }
 
@@ -117,22 +128,24 @@ template <typename T> struct ZfftArgs {
   const C* tw;           // z twiddles, length Lz
 };
 
-template <typename T, int NC, int R>
+template <typename T, int NC, int R, bool WAVE>
 __device__ __forceinline__ void zfft_items(const ZfftArgs<T>& a, int kx0, int ky, typename CT<T>::t* buf,
                                            const typename CT<T>::t* twl, const int* zl, const uint8_t* occ,
                                            const T* lspec) {
   typedef typename CT<T>::t C;
   constexpr int NB = NbMax<R>::v;
+  constexpr int SM = WAVE ? 2 : 1;  // ordering inside a stage
   const int t = threadIdx.x;
   const int W = a.W;
-  const int w = t % W, j0 = t / W;
   const int L = a.Lz, TP = a.pl.tp, LR = L / R;
+  const int w = t / TP, j0 = t % TP;  // a pencil's lanes are consecutive threads
+  const int Lp = pencil_pitch(L);
   const int ns = a.pl.ns;
   const int nthreads = blockDim.x;
   const size_t plane = (size_t)a.geo.pb;
   const int kx = kx0 + w;
-  Lds<C, true> lds{buf, W, 0, w};
-  LdsOcc<C> lin{buf, W, w, occ};
+  Lds<C, false> lds{buf, W, Lp, w};
+  LdsOcc<C> lin{buf, Lp, w, occ};
   // spectrum values of this thread's bins (NC = 1)
   T zv[12];
   if constexpr (NC == 1) {
@@ -147,28 +160,52 @@ __device__ __forceinline__ void zfft_items(const ZfftArgs<T>& a, int kx0, int ky
   }
   const int v0 = blockIdx.y * a.ipb;
   const int v1 = min(a.nitem, v0 + a.ipb);
+  // the planes of the next component vector are loaded into registers while
+  // the current one runs its stages (the first kPre elements of each thread;
+  // longer columns load the rest when they are staged)
+  constexpr int kPre = 8;
+  const int ne = a.nzp * W;
+  C pre[kPre];
+  auto col = [&](int vec) { return a.B + (size_t)vec * a.nzp * plane + (size_t)ky * a.geo.rp + kx0; };
+  auto fetch = [&](int vec) {
+    const C* src = col(vec);
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+      const int e = t + q * nthreads;
+      const int sl = e / W, ww = e % W;
+      pre[q] = (e < ne && kx0 + ww < a.Lx) ? ld_stream(src + (size_t)sl * plane + ww) : C{0, 0};
+    }
+  };
+  if (v0 < v1) fetch(v0 * NC);
   for (int item = v0; item < v1; ++item) {
     C V[NC][12];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const C* src = a.B + ((size_t)(item * NC + c) * a.nzp) * plane + (size_t)ky * a.geo.rp + kx0;
+      const int vec = item * NC + c;
       __syncthreads();  // the previous user of buf is done
-      for (int e = t; e < a.nzp * W; e += nthreads) {
+#pragma unroll
+      for (int q = 0; q < kPre; ++q) {
+        const int e = t + q * nthreads;
         const int sl = e / W, ww = e % W;
-        if (kx0 + ww < a.Lx) buf[zl[sl] * W + ww] = ld_stream(src + (size_t)sl * plane + ww);
+        if (e < ne && kx0 + ww < a.Lx) buf[pencil_at(ww, zl[sl], Lp)] = pre[q];
+      }
+      for (int e = t + kPre * nthreads; e < ne; e += nthreads) {
+        const int sl = e / W, ww = e % W;
+        if (kx0 + ww < a.Lx) buf[pencil_at(ww, zl[sl], Lp)] = ld_stream(col(vec) + (size_t)sl * plane + ww);
       }
       __syncthreads();
+      if (vec + 1 < v1 * NC) fetch(vec + 1);
       if (ns == 1) {
         last_forward<C, R>(L, j0, TP, lin, twl, V[c]);
       } else {
         int Ns = 1;
-        stage_any<C, -1, 1>(a.pl.r[0], L, Ns, j0, TP, lin, lds, twl);
+        stage_any<C, -1, SM>(a.pl.r[0], L, Ns, j0, TP, lin, lds, twl);
         Ns *= a.pl.r[0];
-        __syncthreads();
+        pencil_sync<WAVE>();
         for (int s = 1; s < ns - 1; ++s) {
-          stage_any<C, -1, 1>(a.pl.r[s], L, Ns, j0, TP, lds, lds, twl);
+          stage_any<C, -1, SM>(a.pl.r[s], L, Ns, j0, TP, lds, lds, twl);
           Ns *= a.pl.r[s];
-          __syncthreads();
+          pencil_sync<WAVE>();
         }
         last_forward<C, R>(L, j0, TP, lds, twl, V[c]);
       }
@@ -184,7 +221,7 @@ __device__ __forceinline__ void zfft_items(const ZfftArgs<T>& a, int kx0, int ky
         if constexpr (NC == 1) {
           V[0][q] = cscale(V[0][q], zv[q]);
         } else {
-          const T* sp = lspec + (size_t)(j + r * LR) * W + w;
+          const T* sp = lspec + (size_t)(j + r * LR) * W + w;  // [7][L][W]
           const size_t fs = (size_t)L * W;
           const T s0 = sp[0], s1x = sp[fs], s1y = sp[2 * fs], s1z = sp[3 * fs];
           const T s2x = sp[4 * fs], s2y = sp[5 * fs], s2z = sp[6 * fs];
@@ -207,17 +244,18 @@ __device__ __forceinline__ void zfft_items(const ZfftArgs<T>& a, int kx0, int ky
     for (int c = 0; c < NC; ++c) {
       __syncthreads();  // every thread has read buf (last forward stage / previous store)
       first_inverse<C, R>(L, j0, TP, V[c], lds);
-      __syncthreads();
+      pencil_sync<WAVE>();
       int Ns = R;
       for (int s = 1; s < ns; ++s) {
-        stage_any<C, +1, 1>(a.ipl.r[s], L, Ns, j0, TP, lds, lds, twl);
+        stage_any<C, +1, SM>(a.ipl.r[s], L, Ns, j0, TP, lds, lds, twl);
         Ns *= a.ipl.r[s];
-        __syncthreads();
+        pencil_sync<WAVE>();
       }
+      __syncthreads();  // every pencil's stages are done before the coalesced store
       C* dst = a.B + ((size_t)(item * NC + c) * a.nzp) * plane + (size_t)ky * a.geo.rp + kx0;
       for (int e = t; e < a.nzp * W; e += nthreads) {
         const int sl = e / W, ww = e % W;
-        if (kx0 + ww < a.Lx) st_stream(dst + (size_t)sl * plane + ww, buf[zl[sl] * W + ww]);
+        if (kx0 + ww < a.Lx) st_stream(dst + (size_t)sl * plane + ww, buf[pencil_at(ww, zl[sl], Lp)]);
       }
     }
   }
@@ -225,13 +263,13 @@ __device__ __forceinline__ void zfft_items(const ZfftArgs<T>& a, int kx0, int ky
 
 }  // namespace
 
-template <typename T, int NC>
+template <typename T, int NC, int R, bool WAVE>
 __global__ void __launch_bounds__(256) k_zfft(ZfftArgs<T> a) {
   typedef typename CT<T>::t C;
   extern __shared__ unsigned char smem_raw[];
   const int W = a.W, L = a.Lz;
-  C* buf = reinterpret_cast<C*>(smem_raw);               // [L][W]
-  C* twd = buf + (size_t)L * W;                          // [L]
+  C* buf = reinterpret_cast<C*>(smem_raw);               // W pencils of pitch Lp
+  C* twd = buf + (size_t)W * pencil_pitch(L);            // [L]
   T* lspec = reinterpret_cast<T*>(twd + L);              // NC = 5: [7][L][W]
   int* zl = reinterpret_cast<int*>(lspec + (NC == 5 ? (size_t)kNFam * L * W : 0));  // [nzp]
   uint8_t* occ = reinterpret_cast<uint8_t*>(zl + a.nzp);  // [L]
@@ -255,12 +293,7 @@ __global__ void __launch_bounds__(256) k_zfft(ZfftArgs<T> a) {
     }
   }
   const C* twl = lds_twiddles(twd, a.tw, L);  // synchronises
-  switch (a.pl.r[a.pl.ns - 1]) {
-    case 8: zfft_items<T, NC, 8>(a, kx0, ky, buf, twl, zl, occ, lspec); break;
-    case 4: zfft_items<T, NC, 4>(a, kx0, ky, buf, twl, zl, occ, lspec); break;
-    case 3: zfft_items<T, NC, 3>(a, kx0, ky, buf, twl, zl, occ, lspec); break;
-    default: zfft_items<T, NC, 2>(a, kx0, ky, buf, twl, zl, occ, lspec); break;
-  }
+  zfft_items<T, NC, R, WAVE>(a, kx0, ky, buf, twl, zl, occ, lspec);
 }
 
 // Pencils per block: 16 (FP32) or 8 (FP64) x-adjacent columns, fewer when
@@ -275,7 +308,7 @@ size_t zfft_lds_bytes(const svh_problem* p, size_t cs, int nc) {
   const FftPlan& pl = p->plan[2];
   const int W = zfft_width(pl, cs);
   const size_t ts = cs / 2;
-  return (size_t)W * pl.L * cs + (size_t)pl.L * cs + (nc == 5 ? (size_t)kNFam * pl.L * W * ts : 0) +
+  return (size_t)W * pencil_pitch(pl.L) * cs + (size_t)pl.L * cs + (nc == 5 ? (size_t)kNFam * pl.L * W * ts : 0) +
          p->zlist.size() * sizeof(int) + (size_t)pl.L;
 }
 
@@ -307,8 +340,33 @@ hipError_t launch_zfft(const svh_problem* p, int nvec, void* Bv, const void* spe
   const size_t sh = zfft_lds_bytes(p, sizeof(C), nc);
   if (sh > (size_t)p->max_lds) return hipErrorInvalidConfiguration;
   const int nt = a.W * a.pl.tp;
-  if (nc == 5) hipLaunchKernelGGL((k_zfft<T, 5>), grid, dim3(nt), sh, s, a);
-  else hipLaunchKernelGGL((k_zfft<T, 1>), grid, dim3(nt), sh, s, a);
+  // one kernel per (components, last radix, pencil ordering), so each gets
+  // its own register allocation
+  const bool wave = 64 % a.pl.tp == 0;
+  auto go = [&](auto nct, auto rt, auto wt) {
+    constexpr int NCc = decltype(nct)::value, Rc = decltype(rt)::value;
+    constexpr bool Wc = decltype(wt)::value;
+    hipLaunchKernelGGL((k_zfft<T, NCc, Rc, Wc>), grid, dim3(nt), sh, s, a);
+  };
+  auto by_r = [&](auto nct, auto wt) {
+    switch (a.pl.r[a.pl.ns - 1]) {
+      case 8: go(nct, std::integral_constant<int, 8>{}, wt); break;
+      case 4: go(nct, std::integral_constant<int, 4>{}, wt); break;
+      case 3: go(nct, std::integral_constant<int, 3>{}, wt); break;
+      default: go(nct, std::integral_constant<int, 2>{}, wt); break;
+    }
+  };
+  using N1 = std::integral_constant<int, 1>;
+  using N5 = std::integral_constant<int, 5>;
+  using WT = std::integral_constant<bool, true>;
+  using WF = std::integral_constant<bool, false>;
+  if (nc == 5) {
+    if (wave) by_r(N5{}, WT{});
+    else by_r(N5{}, WF{});
+  } else {
+    if (wave) by_r(N1{}, WT{});
+    else by_r(N1{}, WF{});
+  }
   return hipGetLastError();
 }
 
