@@ -120,6 +120,28 @@ def test_empty_planes_pruned(dev, zstep):
     assert np.all(err <= 1e-12), err
 
 
+@pytest.mark.parametrize("K,nplanes", [((3, 2, 128), 50), ((4, 3, 16), 16), ((2, 3, 8), 8), ((3, 3, 100), 90)])
+def test_z_fft_plans(dev, K, nplanes):
+    """The padded z FFT step over the z transform plans 8x8x4 (Lz = 256),
+    8x4, 8x2 and 8x8x3 (Lz = 200 -> 216), FP64 and FP32, against the oracle."""
+    g = np.random.default_rng(80 + nplanes)
+    mask = np.zeros(K[::-1], dtype=np.uint8)
+    for z in np.sort(g.choice(K[2], nplanes, replace=False)):
+        mask[z] = g.random((K[1], K[0])) < 0.7
+        mask[z, 0, 0] = 1
+    dx = 0.25e-6
+    p = _problem(mask, dx)
+    p.set_zstep("fft")
+    fidx = [0, -1]
+    x = wl.random_currents(90 + nplanes, (2, 3, p.K))
+    ref = _oracle(mask, dx, x, fidx)
+    e64 = _relerr(_run(p, x, fidx, dev, torch.complex128), ref)
+    e32 = _relerr(_run(p, x, fidx, dev, torch.complex64), ref)
+    print("z fft plans", K, p.L, e64, e32)
+    assert np.all(e64 <= 1e-12)
+    assert np.all(e32 <= 1e-5)
+
+
 @pytest.mark.parametrize("nplanes", [25, 32])
 @pytest.mark.parametrize("zstep", ["direct", "fused"])
 def test_direct_z_step_at_the_plane_limit(dev, zstep, nplanes):

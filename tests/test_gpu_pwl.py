@@ -132,6 +132,9 @@ FFT_CASES = MV_CASES[:6] + [
     ((4, 3, 40), 40, 0.6, 29),         # 40 planes: beyond the direct z step
     ((5, 6, 24), 24, 1.0, 30),         # every plane of a filled 5 x 6 x 24 box, L = 48 (radix 3)
     ((3, 2, 70), 37, 0.7, 32),         # 37 irregular planes of 70, L = 144
+    ((3, 2, 128), 50, 0.7, 37),        # Lz = 256: plan 8 x 8 x 4 (last radix 4)
+    ((4, 3, 16), 16, 0.8, 38),         # Lz = 32: plan 8 x 4
+    ((2, 3, 8), 8, 1.0, 39),           # Lz = 16: plan 8 x 2 (last radix 2)
 ]
 
 
