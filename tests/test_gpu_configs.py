@@ -10,7 +10,10 @@ oracle's equations.
              1e-4 p_k, solves to 1e-14) on 32 voxels drawn from those with
              |g| >= 3e-3 max |g| (ground, vias and strip): within 1e-3 of the
              gradient plus the difference quotient's own noise, 2e-14 L / h,
-             which is below a third of the relative term on each of them.
+             which is below a third of the relative term on each of them;
+  * stack    256x256x128, three layers with 8 port-gap vias, 8 ports in one
+             batch at 50 GHz, FP32 products and FP32 Schur CG inside FP64
+             refinement to 1e-6, Tucker tol 1e-8.
 
 A dense LU solve is out of reach at these sizes, so each solution is checked
 against what the oracle fixes at any size:
@@ -51,19 +54,19 @@ def _problem(mask, ports, basis, tol, lam=LAM):
     return p
 
 
-def _check_rows(p, mask, basis, I, tol, lam, nobs=2, seed=0):
+def _check_rows(p, mask, basis, I, tol, lam, nobs=2, seed=0, dx=DX, f=F):
     """Z I at sampled observer voxels against the oracle's row sums."""
     P = op.voxel_coords(mask)
     names = op.BASIS_SETS[basis]
-    w = 2 * np.pi * F
-    s = 1j * w * op.MU0 * DX
+    w = 2 * np.pi * f
+    s = 1j * w * op.MU0 * dx
     lamv = np.broadcast_to(np.asarray(lam, dtype=np.float64), (p.K,))
     ZI = p.matvec(torch.from_numpy(np.ascontiguousarray(I[None])).to("cuda"), [0]).cpu().numpy()[0]
     fams = green.FAMILIES if basis == 5 else ["M0"]
     for l in np.random.default_rng(seed).choice(p.K, size=nobs, replace=False):
         off = P - P[l]
         fam = {n: green.family_values(n, off) for n in fams}
-        c = op.material_c(F, S0, lamv[l])
+        c = op.material_c(f, S0, lamv[l])
         for b in range(basis):
             conv, mag = 0, 0
             for a in range(basis):
@@ -73,7 +76,7 @@ def _check_rows(p, mask, basis, I, tol, lam, nobs=2, seed=0):
                 row = sum(coef * fam[n] for coef, n in terms)
                 conv = conv + row @ I[a]
                 mag += np.sum(row ** 2) * np.mean(np.abs(I[a]) ** 2)
-            diag = sum(op.mass_coefficient(names[b], names[a]) * I[a, l] for a in range(basis)) * c / DX
+            diag = sum(op.mass_coefficient(names[b], names[a]) * I[a, l] for a in range(basis)) * c / dx
             ref = s * conv + diag
             scale = abs(s) * np.sqrt(mag) + abs(ref)
             e = abs(ZI[b, l] - ref) / scale
@@ -160,3 +163,34 @@ def test_bend_gradient_vs_central_differences():
 
 
 RRE_FD = 1e-14  # residual target of the finite-difference solves
+
+
+@pytest.mark.slow
+def test_stack_eight_port_solve_fp32_refined():
+    """The 256 x 256 x 128 three-layer stack with its 8 port-gap vias (five
+    components; 52 occupied planes, so the z FFT step), 8 ports in one batch
+    at 50 GHz, FP32 products and FP32 Schur CG inside FP64 refinement to
+    relative residual 1e-6: eq. 7 with the oracle's face fluxes for two
+    ports, the product at a sampled observer against the oracle's Green
+    rows, reciprocity and a passive inductance matrix."""
+    import paper_2105_08627_amd as svh
+    cfg = wl.WORKLOADS["c5_stack"]
+    mask, ports = wl.layered_stack_with_ports(cfg["seed"])
+    f, dx = cfg["freqs"][-1], cfg["dx"]
+    p = svh.Problem(mask, dx, basis=5)
+    p.set_material([f], S0, LAM)
+    p.setup_tensors()
+    p.tucker_compress(1e-8)
+    p.set_ports(ports)
+    X, Y, info = p.solve(0, rre=1e-6, restart=50, maxit=2000, refine=True)
+    print(f"[configs] stack K={p.K} N={p.N}: {info['iterations']} its, {info['refinement_steps']} refinement steps, "
+          f"relres {info['relres']:.2e}", flush=True)
+    assert info["converged"] and info["relres"] <= 1e-6
+    assert np.abs(Y - Y.T).max() <= 1e-4 * np.abs(Y).max()      # reciprocity, to the solve tolerance
+    _check_solution(p, mask, 5, ports, X, Y, 1e-6, [0, 5])
+    I = X[5, :5 * p.K].cpu().numpy().reshape(5, p.K)
+    _check_rows(p, mask, 5, I, 1e-8, LAM, nobs=1, seed=4, dx=dx, f=f)
+    L = np.linalg.inv(Y).imag / (2 * np.pi * f)
+    assert np.all(np.diag(L) > 0)
+    assert np.all(np.linalg.eigvalsh(0.5 * (L + L.T)) > 0)
+
