@@ -128,7 +128,8 @@ size_t vec_bytes_AB(const svh_problem* p, size_t csize) {
 }
 
 int chunk_rhs(const svh_problem* p, int nrhs) {
-  const int maxr = kMaxVecsPerChunk / p->C;
+  int maxr = kMaxVecsPerChunk / p->C;
+  if (p->C == 5 && maxr > 8) maxr -= maxr % 8;  // the five-component z step takes right-hand sides 8 at a time
   return std::max(1, std::min(nrhs, maxr));
 }
 

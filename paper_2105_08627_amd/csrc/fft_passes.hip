@@ -449,138 +449,182 @@ Geo make_geo(const svh_problem* p, size_t csize) {
   return g;
 }
 
-// FP32 variant of the coupled five-component z step for up to 24 occupied
-// planes with the kernel values in registers: thread (w, s, i) of a block of
-// W pencils x S j-sets x NZ rows keeps g_f(|z_i - z_j|) of its pencil for all
-// seven families and its j = s, s + S, ... (the z-odd family with its sign),
-// so the sum over j reads only the five staged components from LDS: 40 bytes
-// per 24 FMAs, against 96 bytes per 48 FMAs (and a quarter of the row slots
-// idle at 24 planes) when the kernel values are read from LDS.  The S partial
-// sums of a row meet through lane exchanges (S = 2 keeps 24 planes within the
-// register file).
-template <int NZ, int W, int S>
-__global__ void __launch_bounds__(W * S * NZ) k_zdirect5r(Geo geo, int Lx, int Ly, int nzp, int nd, int nrhs,
-                                                          int rpb, const uint8_t* __restrict__ qtab,
-                                                          const float* __restrict__ g5, float2* __restrict__ B) {
-  constexpr int NT = W * S * NZ;
+// FP32 coupled five-component z step on the matrix cores.  Per pencil the z
+// sum of each family is a real Toeplitz matrix T_f[i][j] = g_f(|z_i - z_j|)
+// (with the z-odd sign for M1z) applied to every right-hand side: a dense
+// (planes x planes) by (planes x columns) product, run as
+// v_mfma_f32_16x16x4f32 with T_f as the A operand and the staged operands of
+// 8 right-hand sides as the 16 B columns (column r: Re, r + 8: Im of
+// right-hand side r).  The 17 blocks of eq. 8 take 12 products per pencil
+// (the 2 of M1z and 4 of M2z folded into the staged kernel values): yx, yy,
+// yz and the z-even part of y3 accumulate their products directly (with
+// i u, -i w, -I3 formed per operand); R = M1x Ix, S = M1y Iy, P = M2x u,
+// Q = M2y w are accumulated apart and combined per element afterwards:
+//   y2 = i (S - R) + P + Q,   y3 += -i (R + S) + P - Q.
+// A block is 8 pencils (one wavefront each, 64-byte runs along x) x all
+// right-hand sides in batches of 8; operands and results pass through LDS.
+// The A operands are gathered from the block's kernel values in LDS at each
+// step (codes of the lane's (i, j) pairs held packed in registers), and the
+// two 16-row tiles run one after the other, so a wavefront holds 32
+// accumulators and four wavefronts fit on each SIMD.  Lane layout (wave64):
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; result register v
+// of lane l is D[4 (l / 16) + v][l % 16].
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+template <int NZ, int W>
+__global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4)))
+k_zdirect5m(Geo geo, int Lx, int Ly, int nzp, int nd, int nrhs, const uint8_t* __restrict__ qtab,
+            const float* __restrict__ g5, float2* __restrict__ B) {
+  constexpr int NT = W * 64;          // one wavefront per pencil
+  constexpr int RB = 8;               // right-hand sides per batch
+  constexpr int RT = (NZ + 15) / 16;  // 16-row tiles of observer planes
+  constexpr int KS = NZ / 4;          // 4-plane steps over source planes
+  constexpr int JS = W * RB * 2 + 16; // floats per (component, plane): consecutive planes 16 banks apart
   constexpr int NF = 7;
-  constexpr int NJ = NZ / S;
-  // staged operands per (plane j, pencil w): Ix, Iy, Iz, u = I2D + I3D,
-  // w = I2D - I3D, I3D and two pad values (64 bytes, read as three 16-byte
-  // loads); the pencil pitch is 10 complex values (80 bytes) so that the
-  // 16-byte loads of neighbouring pencils fall into different banks
-  constexpr int PW = 10;
-  static_assert(NZ % S == 0 && (S == 1 || (S == 2 && W <= 32)), "j pairs are lanes t and t ^ W of one wave");
-  extern __shared__ unsigned char smem_raw[];
-  float2* xs = reinterpret_cast<float2*>(smem_raw);                    // [NZ][W][PW]
-  float* gs = reinterpret_cast<float*>(xs + (size_t)NZ * W * PW);      // [7][nd][W]
-  float2* raw = reinterpret_cast<float2*>(gs + (size_t)NF * nd * W);   // [5][NZ][W] staging of the loads
-  const int t = threadIdx.x;
+  constexpr int EPT = 5 * NZ / 8;     // staged complex values per thread and batch
+  constexpr int NCW = (RT * KS + 3) / 4;
+  static_assert(NZ % 8 == 0 && NZ <= 24, "plane count");
+  extern __shared__ float zsm[];
+  float* xs = zsm;                           // [5][NZ][JS]: staged operands, then results
+  float* gs = xs + (size_t)5 * NZ * JS;      // [W][7 nd + 1] kernel values of the block's pencils
+  const int gp = NF * nd + 1;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int ntile = (Lx + W - 1) / W;
-  const int bid = first_item();  // XCD-aware order of the (tile, ky) blocks
+  const int bid = first_item();
   const int tile = bid % ntile, ky = bid / ntile;
   const int kx0 = tile * W;
-  const int w = t % W, sj = (t / W) % S, i = t / (W * S);
-  const bool valid = kx0 + w < Lx && i < nzp && sj == 0;
   for (int e = t; e < NF * nd * W; e += NT) {
-    const int ww = e % W, fq = e / W;
-    gs[e] = kx0 + ww < Lx ? g5[((size_t)fq * Ly + ky) * Lx + kx0 + ww] : 0.f;
+    const int ww = e % W, fs = e / W, f = fs / nd;
+    const float sc = f == 3 ? 2.f : f == 6 ? 4.f : 1.f;
+    gs[ww * gp + fs] = kx0 + ww < Lx ? sc * g5[((size_t)fs * Ly + ky) * Lx + kx0 + ww] : 0.f;
   }
-  __syncthreads();
-  float kr[NF][NJ];
+  // codes of this lane's (i, j) = (16 rt + l % 16, 4 ks + l / 16), four per word
+  uint32_t cw[NCW];
 #pragma unroll
-  for (int jj = 0; jj < NJ; ++jj) {
-    const int j = sj + S * jj;
-    const bool on = i < nzp && j < nzp;
-    const uint32_t code = on ? qtab[i * 32 + j] : 0u;
-    const float* gq = gs + (code & 0x7fu) * W + w;
+  for (int q = 0; q < NCW; ++q) cw[q] = 0u;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) kr[f][jj] = on ? gq[f * nd * W] : 0.f;
-    if (code & 0x80u) kr[3][jj] = -kr[3][jj];
-  }
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int i = 16 * rt + (lane & 15), j = 4 * ks + (lane >> 4), n = rt * KS + ks;
+      const uint32_t code = (i < nzp && j < nzp) ? qtab[i * 32 + j] : 0u;
+      cw[n >> 2] |= code << (8 * (n & 3));
+    }
+  const float* gw = gs + w * gp;
   const size_t plane = (size_t)geo.pb;
   float2* base = B + (size_t)ky * geo.rp + kx0;
-  const int rbeg = blockIdx.y * rpb;
-  const int rend = min(nrhs, rbeg + rpb);
-  constexpr int NE = 5 * NZ * W;
-  constexpr int EPT = (NE + NT - 1) / NT;
-  constexpr int NP = NZ * W;  // (j, w) pairs
-  float2 pre[EPT];
-  auto fetch = [&](int rhs) {
+  const int col = lane & 15, part = col >> 3;
+  const int bw = w * 16 + (col & 7) * 2;  // this lane's right-hand side and pencil within a plane row of xs
+  const float sg = part ? 1.f : -1.f;
+  // staging map: thread t moves pencil t % W of right-hand side (t / W) % 8 at
+  // planes t / 8W + 8 h of every component (q = c NZ / 8 + h): runs of W
+  // complex values along x
+  const int sw = t % W, sr = (t / W) & 7, sj = t / (8 * W);
+  const bool sx = kx0 + sw < Lx;
+  float* const xst = xs + sj * JS + sw * 16 + sr * 2;
+  const size_t cs = (size_t)nzp * plane;  // one component vector
+  float2 v[EPT];
+  for (int r0 = 0; r0 < nrhs; r0 += RB) {
+    // the codes are redefined here so that the A-operand addresses derived from
+    // them are formed at each step instead of being held across the batch loop
+#pragma unroll
+    for (int q = 0; q < NCW; ++q) asm volatile("" : "+v"(cw[q]));
+    // every load is issued unconditionally from a valid address (right-hand
+    // side and plane clamped; positions x >= Lx lie in the row padding) and
+    // zeros are selected when the values are staged, so that the loads of a
+    // batch are in flight together
+    {
+      const float2* src = base + (size_t)min(r0 + sr, nrhs - 1) * 5 * cs + sw;
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int c = q / (NZ / 8), h = q % (NZ / 8);
+        v[q] = src[c * cs + (size_t)min(sj + 8 * h, nzp - 1) * plane];
+      }
+    }
+    __syncthreads();  // the previous batch's results have left xs (and gs is written)
+    const bool sv = sx && r0 + sr < nrhs;
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
-      const int e = t + NT * q;
-      const int ww = e % W, j = (e / W) % NZ, c = e / (W * NZ);
-      pre[q] = (e < NE && j < nzp && kx0 + ww < Lx)
-                   ? ld_stream(base + ((size_t)(rhs * 5 + c) * nzp + j) * plane + ww)
-                   : float2{0.f, 0.f};
-    }
-  };
-  if (rbeg < rend) fetch(rbeg);
-  for (int rhs = rbeg; rhs < rend; ++rhs) {
-    __syncthreads();  // previous right-hand side's readers are done with xs and raw
-#pragma unroll
-    for (int q = 0; q < EPT; ++q)
-      if (t + NT * q < NE) raw[t + NT * q] = pre[q];
-    __syncthreads();
-    if (rhs + 1 < rend) fetch(rhs + 1);
-    // the six operands of each (j, w)
-    for (int e = t; e < NP; e += NT) {
-      const int ww = e % W, j = e / W;
-      const float2 ix = raw[(0 * NZ + j) * W + ww], iy = raw[(1 * NZ + j) * W + ww];
-      const float2 iz = raw[(2 * NZ + j) * W + ww], i2 = raw[(3 * NZ + j) * W + ww];
-      const float2 i3 = raw[(4 * NZ + j) * W + ww];
-      float4* d = reinterpret_cast<float4*>(xs + ((size_t)j * W + ww) * PW);
-      d[0] = float4{ix.x, ix.y, iy.x, iy.y};
-      d[1] = float4{iz.x, iz.y, i2.x + i3.x, i2.y + i3.y};
-      d[2] = float4{i2.x - i3.x, i2.y - i3.y, i3.x, i3.y};
+      const int c = q / (NZ / 8), h = q % (NZ / 8);
+      *reinterpret_cast<float2*>(xst + (c * NZ + 8 * h) * JS) =
+          (sv && sj + 8 * h < nzp) ? v[q] : float2{0.f, 0.f};
     }
     __syncthreads();
-    float a[24];
+    float o0[4][5];  // results of the first row tile, kept until every wavefront has read its operands
 #pragma unroll
-    for (int k = 0; k < 24; ++k) a[k] = 0.f;
+    for (int rt = 0; rt < RT; ++rt) {
+      f32x4_t yx = {0.f, 0.f, 0.f, 0.f}, yy = yx, yz = yx, y3 = yx, pr = yx, ps = yx, pp = yx, pq = yx;
 #pragma unroll
-    for (int jj = 0; jj < NJ; ++jj) {
-      const int j = sj + S * jj;
-      const float4* q = reinterpret_cast<const float4*>(xs + ((size_t)j * W + w) * PW);
-      const float4 p0 = q[0], p1 = q[1], p2 = q[2];
-      const float2 ix = float2{p0.x, p0.y}, iy = float2{p0.z, p0.w};
-      const float2 iz = float2{p1.x, p1.y}, u = float2{p1.z, p1.w};
-      const float2 v = float2{p2.x, p2.y}, i3 = float2{p2.z, p2.w};
-      const float g0 = kr[0][jj], g1x = kr[1][jj], g1y = kr[2][jj], g1z = kr[3][jj];
-      const float g2x = kr[4][jj], g2y = kr[5][jj], g2z = kr[6][jj];
-      a[0] += g0 * ix.x;  a[1] += g0 * ix.y;
-      a[2] += g0 * iy.x;  a[3] += g0 * iy.y;
-      a[4] += g0 * iz.x;  a[5] += g0 * iz.y;
-      a[6] += g1x * u.x;  a[7] += g1x * u.y;
-      a[8] += g1x * ix.x; a[9] += g1x * ix.y;
-      a[10] += g1y * v.x; a[11] += g1y * v.y;
-      a[12] += g1y * iy.x; a[13] += g1y * iy.y;
-      a[14] += g1z * i3.x; a[15] += g1z * i3.y;
-      a[16] += g1z * iz.x; a[17] += g1z * iz.y;
-      a[18] += g2x * u.x; a[19] += g2x * u.y;
-      a[20] += g2y * v.x; a[21] += g2y * v.y;
-      a[22] += g2z * i3.x; a[23] += g2z * i3.y;
+      for (int ks = 0; ks < KS; ++ks) {
+        // one step's LDS reads at a time: keeps the wavefront within 128 registers
+        __builtin_amdgcn_sched_barrier(0);
+        const int n = rt * KS + ks;
+        const uint32_t code = (cw[n >> 2] >> (8 * (n & 3))) & 0xffu;
+        const float* ga = gw + (code & 0x7fu);
+        const float a0 = ga[0], a1 = ga[nd], a2 = ga[2 * nd], a4 = ga[4 * nd], a5 = ga[5 * nd], a6 = ga[6 * nd];
+        const float a3 = (code & 0x80u) ? -ga[3 * nd] : ga[3 * nd];
+        const float* xj = xs + (4 * ks + (lane >> 4)) * JS + bw;
+        const float ix = xj[0 * NZ * JS + part], iy = xj[1 * NZ * JS + part], iz = xj[2 * NZ * JS + part];
+        const float2 p2 = *reinterpret_cast<const float2*>(xj + 3 * NZ * JS);
+        const float2 p3 = *reinterpret_cast<const float2*>(xj + 4 * NZ * JS);
+        const float i2 = part ? p2.y : p2.x, i2s = part ? p2.x : p2.y;
+        const float i3 = part ? p3.y : p3.x, i3s = part ? p3.x : p3.y;
+        const float u = i2 + i3, wv = i2 - i3;
+        const float iu = sg * (i2s + i3s);    // i u
+        const float miw = -sg * (i2s - i3s); // -i w
+        yx = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, ix, yx, 0, 0, 0);
+        yy = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, iy, yy, 0, 0, 0);
+        yz = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, iz, yz, 0, 0, 0);
+        pr = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, ix, pr, 0, 0, 0);
+        ps = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, iy, ps, 0, 0, 0);
+        y3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, iz, y3, 0, 0, 0);
+        pp = __builtin_amdgcn_mfma_f32_16x16x4f32(a4, u, pp, 0, 0, 0);
+        pq = __builtin_amdgcn_mfma_f32_16x16x4f32(a5, wv, pq, 0, 0, 0);
+        yx = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, iu, yx, 0, 0, 0);
+        yy = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, miw, yy, 0, 0, 0);
+        yz = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, -i3, yz, 0, 0, 0);
+        y3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a6, i3, y3, 0, 0, 0);
+      }
+      float res[4][5];
+#pragma unroll
+      for (int vr = 0; vr < 4; ++vr) {
+        const float d = ps[vr] - pr[vr], sm = pr[vr] + ps[vr];
+        const float ds = __shfl_xor(d, 8), ss = __shfl_xor(sm, 8);  // the other part of the same element
+        res[vr][0] = yx[vr];
+        res[vr][1] = yy[vr];
+        res[vr][2] = yz[vr];
+        res[vr][3] = sg * ds + pp[vr] + pq[vr];
+        res[vr][4] = y3[vr] - sg * ss + pp[vr] - pq[vr];
+      }
+      if (rt == 0) {
+#pragma unroll
+        for (int vr = 0; vr < 4; ++vr)
+#pragma unroll
+          for (int c = 0; c < 5; ++c) o0[vr][c] = res[vr][c];
+      }
+      if (rt == RT - 1) {
+        __syncthreads();  // every wavefront has read its operands
+#pragma unroll
+        for (int r2 = 0; r2 < RT; ++r2)
+#pragma unroll
+          for (int vr = 0; vr < 4; ++vr) {
+            const int i = 16 * r2 + 4 * (lane >> 4) + vr;
+            if (i < nzp) {
+              float* o = xs + i * JS + bw + part;
+#pragma unroll
+              for (int c = 0; c < 5; ++c) o[c * NZ * JS] = r2 == rt ? res[vr][c] : o0[vr][c];
+            }
+          }
+      }
     }
-    if constexpr (S == 2) {
+    __syncthreads();
+    float2* dst = base + (size_t)(r0 + sr) * 5 * cs + (size_t)sj * plane + sw;
 #pragma unroll
-      for (int k = 0; k < 24; ++k) a[k] += __shfl_xor(a[k], W);
+    for (int q = 0; q < EPT; ++q) {
+      const int c = q / (NZ / 8), h = q % (NZ / 8);
+      if (sv && sj + 8 * h < nzp)
+        dst[c * cs + (size_t)(8 * h) * plane] = *reinterpret_cast<const float2*>(xst + (c * NZ + 8 * h) * JS);
     }
-    if (!valid) continue;
-    // the same combination into the 17 blocks as k_zdirect5
-    const float2 yx = float2{a[0] - a[7], a[1] + a[6]};
-    const float2 yy = float2{a[2] + a[11], a[3] - a[10]};
-    const float2 yz = float2{a[4] - 2 * a[14], a[5] - 2 * a[15]};
-    const float2 y2 = float2{-(a[13] - a[9]) + a[18] + a[20], (a[12] - a[8]) + a[19] + a[21]};
-    const float2 y3 = float2{(a[9] + a[13]) + 2 * a[16] + a[18] - a[20] + 4 * a[22],
-                             -(a[8] + a[12]) + 2 * a[17] + a[19] - a[21] + 4 * a[23]};
-    float2* o = base + ((size_t)(rhs * 5) * nzp + i) * plane + w;
-    const size_t cs = (size_t)nzp * plane;
-    st_stream(o, yx);
-    st_stream(o + cs, yy);
-    st_stream(o + 2 * cs, yz);
-    st_stream(o + 3 * cs, y2);
-    st_stream(o + 4 * cs, y3);
   }
 }
 
@@ -661,7 +705,8 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     const hipError_t ez = launch_zfft<T>(p, nvec, B, zhat, s);
     if (ez != hipSuccess) return ez;
   } else if (p->C == 5) {
-    // coupled five-component direct sum; double: 8 pencils x 32 row groups
+    // coupled five-component direct sum with the kernel values read from LDS
+    // (FP64, and FP32 at 25-32 planes); double: 8 pencils x 32 row groups
     // (one row each), float: 16 pencils x 16 row groups
     const int nd = (int)p->dzset.size();
     const int nrhs = nvec / 5;
@@ -685,29 +730,24 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     using I24 = std::integral_constant<int, 24>;
     using I32 = std::integral_constant<int, 32>;
     using RGmax = std::integral_constant<int, sizeof(T) == 8 ? 32 : 16>;
-    // FP32 with up to 24 planes: kernel values in registers (k_zdirect5r),
-    // 16 pencils x NZ rows per block (x 2 j-sets at 24 planes; 8 pencils per
-    // block measured slower, 15.7 against 12.8 ms on the stack)
-    auto gor = [&](auto nzt) -> hipError_t {
-      constexpr int NZc = decltype(nzt)::value, SJ = NZc > 16 ? 2 : 1, W = 16;
-      const int ntile = (Lx + W - 1) / W;
-      const int nblk = ntile * Ly;
-      int rpb = nrhs;
-      while (rpb > 1 && (long long)nblk * ((nrhs + rpb - 1) / rpb) < 4096) rpb = (rpb + 1) / 2;
-      dim3 grid(nblk, (nrhs + rpb - 1) / rpb);
-      const size_t sh = (size_t)NZc * W * 10 * sizeof(float2) + (size_t)7 * nd * W * sizeof(float) +
-                        (size_t)5 * NZc * W * sizeof(float2);
+    // FP32 with up to 24 planes: matrix-core Toeplitz products (k_zdirect5m),
+    // 8 pencils per block (32 planes would not fit its registers and LDS)
+    auto gom = [&](auto nzt) -> hipError_t {
+      constexpr int NZc = decltype(nzt)::value;
+      constexpr int W5 = 8;
+      const int nblk = ((Lx + W5 - 1) / W5) * Ly;
+      const size_t sh = (size_t)5 * NZc * (W5 * 16 + 16) * sizeof(float) + (size_t)W5 * (7 * nd + 1) * sizeof(float);
       if (sh > (size_t)p->max_lds) return hipErrorInvalidConfiguration;
-      hipLaunchKernelGGL((k_zdirect5r<NZc, W, SJ>), grid, dim3(W * SJ * NZc), sh, s, geo, Lx, Ly, nzp, nd, nrhs, rpb,
-                         p->d_qtab, static_cast<const float*>(zhat), reinterpret_cast<float2*>(B));
+      hipLaunchKernelGGL((k_zdirect5m<NZc, W5>), dim3(nblk), dim3(W5 * 64), sh, s, geo, Lx, Ly, nzp, nd, nrhs, p->d_qtab,
+                         static_cast<const float*>(zhat), reinterpret_cast<float2*>(B));
       return hipSuccess;
     };
     hipError_t ez;
-    if (sizeof(T) == 4 && NZ <= 24 && p->zdirect5_regs) {
+    if (sizeof(T) == 4 && NZ <= 24) {
       switch (NZ) {
-        case 8: ez = gor(I8{}); break;
-        case 16: ez = gor(I16{}); break;
-        default: ez = gor(I24{}); break;
+        case 8: ez = gom(I8{}); break;
+        case 16: ez = gom(I16{}); break;
+        default: ez = gom(I24{}); break;
       }
     } else {
       switch (NZ) {

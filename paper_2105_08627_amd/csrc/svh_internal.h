@@ -148,7 +148,6 @@ struct svh_problem {
   double2* d_twp64 = nullptr;
   float2* d_twp32 = nullptr;
   int zstep = 0;                // SVH_ZSTEP_AUTO / _FFT / _DIRECT / _FUSED
-  bool zdirect5_regs = true;    // FP32 five-component direct z step with register-resident kernel values
   int green = 0;                // SVH_GREEN_QUADRATURE (device) / SVH_GREEN_CLOSED_FORM (host, M0)
   // Toeplitz store (Algorithm 2): Tucker factors of the tables on a large
   // unit-voxel domain, read by svh_set_toeplitz_store; empty = not used
