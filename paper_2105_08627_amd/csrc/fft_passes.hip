@@ -470,23 +470,41 @@ Geo make_geo(const svh_problem* p, size_t csize) {
 // lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; result register v
 // of lane l is D[4 (l / 16) + v][l % 16].
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
 
-template <int NZ, int W>
-__global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4)))
+// 16 x 16 x 4 matrix-core step and its result layout for each precision
+template <typename T> struct Mfma16;
+template <> struct Mfma16<float> {
+  using v4 = f32x4_t;
+  __device__ static v4 mac(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+template <> struct Mfma16<double> {
+  using v4 = f64x4_t;
+  __device__ static v4 mac(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+
+template <typename T, int NZ, int W>
+__global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
 k_zdirect5m(Geo geo, int Lx, int Ly, int nzp, int nd, int nrhs, const uint8_t* __restrict__ qtab,
-            const float* __restrict__ g5, float2* __restrict__ B) {
+            const T* __restrict__ g5, typename CT<T>::t* __restrict__ B) {
+  using C = typename CT<T>::t;
+  using M = Mfma16<T>;
   constexpr int NT = W * 64;          // one wavefront per pencil
   constexpr int RB = 8;               // right-hand sides per batch
   constexpr int RT = (NZ + 15) / 16;  // 16-row tiles of observer planes
   constexpr int KS = NZ / 4;          // 4-plane steps over source planes
-  constexpr int JS = W * RB * 2 + 16; // floats per (component, plane): consecutive planes 16 banks apart
+  // values per (component, plane) row of xs: the pad puts consecutive planes
+  // 64 (FP32) or 32 (FP64) bytes apart in the bank cycle
+  constexpr int JS = W * RB * 2 + (sizeof(T) == 4 ? 16 : 8);
   constexpr int NF = 7;
   constexpr int EPT = 5 * NZ / 8;     // staged complex values per thread and batch
   constexpr int NCW = (RT * KS + 3) / 4;
   static_assert(NZ % 8 == 0 && NZ <= 24, "plane count");
-  extern __shared__ float zsm[];
-  float* xs = zsm;                           // [5][NZ][JS]: staged operands, then results
-  float* gs = xs + (size_t)5 * NZ * JS;      // [W][7 nd + 1] kernel values of the block's pencils
+  extern __shared__ __align__(16) unsigned char zsm_raw[];
+  T* xs = reinterpret_cast<T*>(zsm_raw);    // [5][NZ][JS]: staged operands, then results
+  T* gs = xs + (size_t)5 * NZ * JS;         // [W][7 nd + 1] kernel values of the block's pencils
   const int gp = NF * nd + 1;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int ntile = (Lx + W - 1) / W;
@@ -495,8 +513,8 @@ k_zdirect5m(Geo geo, int Lx, int Ly, int nzp, int nd, int nrhs, const uint8_t* _
   const int kx0 = tile * W;
   for (int e = t; e < NF * nd * W; e += NT) {
     const int ww = e % W, fs = e / W, f = fs / nd;
-    const float sc = f == 3 ? 2.f : f == 6 ? 4.f : 1.f;
-    gs[ww * gp + fs] = kx0 + ww < Lx ? sc * g5[((size_t)fs * Ly + ky) * Lx + kx0 + ww] : 0.f;
+    const T sc = f == 3 ? T(2) : f == 6 ? T(4) : T(1);
+    gs[ww * gp + fs] = kx0 + ww < Lx ? sc * g5[((size_t)fs * Ly + ky) * Lx + kx0 + ww] : T(0);
   }
   // codes of this lane's (i, j) = (16 rt + l % 16, 4 ks + l / 16), four per word
   uint32_t cw[NCW];
@@ -510,20 +528,20 @@ k_zdirect5m(Geo geo, int Lx, int Ly, int nzp, int nd, int nrhs, const uint8_t* _
       const uint32_t code = (i < nzp && j < nzp) ? qtab[i * 32 + j] : 0u;
       cw[n >> 2] |= code << (8 * (n & 3));
     }
-  const float* gw = gs + w * gp;
+  const T* gw = gs + w * gp;
   const size_t plane = (size_t)geo.pb;
-  float2* base = B + (size_t)ky * geo.rp + kx0;
+  C* base = B + (size_t)ky * geo.rp + kx0;
   const int col = lane & 15, part = col >> 3;
   const int bw = w * 16 + (col & 7) * 2;  // this lane's right-hand side and pencil within a plane row of xs
-  const float sg = part ? 1.f : -1.f;
+  const T sg = part ? T(1) : T(-1);
   // staging map: thread t moves pencil t % W of right-hand side (t / W) % 8 at
   // planes t / 8W + 8 h of every component (q = c NZ / 8 + h): runs of W
   // complex values along x
   const int sw = t % W, sr = (t / W) & 7, sj = t / (8 * W);
   const bool sx = kx0 + sw < Lx;
-  float* const xst = xs + sj * JS + sw * 16 + sr * 2;
+  T* const xst = xs + sj * JS + sw * 16 + sr * 2;
   const size_t cs = (size_t)nzp * plane;  // one component vector
-  float2 v[EPT];
+  C v[EPT];
   for (int r0 = 0; r0 < nrhs; r0 += RB) {
     // the codes are redefined here so that the A-operand addresses derived from
     // them are formed at each step instead of being held across the batch loop
@@ -534,7 +552,7 @@ k_zdirect5m(Geo geo, int Lx, int Ly, int nzp, int nd, int nrhs, const uint8_t* _
     // zeros are selected when the values are staged, so that the loads of a
     // batch are in flight together
     {
-      const float2* src = base + (size_t)min(r0 + sr, nrhs - 1) * 5 * cs + sw;
+      const C* src = base + (size_t)min(r0 + sr, nrhs - 1) * 5 * cs + sw;
 #pragma unroll
       for (int q = 0; q < EPT; ++q) {
         const int c = q / (NZ / 8), h = q % (NZ / 8);
@@ -546,50 +564,49 @@ k_zdirect5m(Geo geo, int Lx, int Ly, int nzp, int nd, int nrhs, const uint8_t* _
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       const int c = q / (NZ / 8), h = q % (NZ / 8);
-      *reinterpret_cast<float2*>(xst + (c * NZ + 8 * h) * JS) =
-          (sv && sj + 8 * h < nzp) ? v[q] : float2{0.f, 0.f};
+      *reinterpret_cast<C*>(xst + (c * NZ + 8 * h) * JS) = (sv && sj + 8 * h < nzp) ? v[q] : C{T(0), T(0)};
     }
     __syncthreads();
-    float o0[4][5];  // results of the first row tile, kept until every wavefront has read its operands
+    T o0[4][5];  // results of the first row tile, kept until every wavefront has read its operands
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
-      f32x4_t yx = {0.f, 0.f, 0.f, 0.f}, yy = yx, yz = yx, y3 = yx, pr = yx, ps = yx, pp = yx, pq = yx;
+      typename M::v4 yx = {T(0), T(0), T(0), T(0)}, yy = yx, yz = yx, y3 = yx, pr = yx, ps = yx, pp = yx, pq = yx;
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        // one step's LDS reads at a time: keeps the wavefront within 128 registers
+        // one step's LDS reads at a time: keeps the register count at the occupancy target
         __builtin_amdgcn_sched_barrier(0);
         const int n = rt * KS + ks;
         const uint32_t code = (cw[n >> 2] >> (8 * (n & 3))) & 0xffu;
-        const float* ga = gw + (code & 0x7fu);
-        const float a0 = ga[0], a1 = ga[nd], a2 = ga[2 * nd], a4 = ga[4 * nd], a5 = ga[5 * nd], a6 = ga[6 * nd];
-        const float a3 = (code & 0x80u) ? -ga[3 * nd] : ga[3 * nd];
-        const float* xj = xs + (4 * ks + (lane >> 4)) * JS + bw;
-        const float ix = xj[0 * NZ * JS + part], iy = xj[1 * NZ * JS + part], iz = xj[2 * NZ * JS + part];
-        const float2 p2 = *reinterpret_cast<const float2*>(xj + 3 * NZ * JS);
-        const float2 p3 = *reinterpret_cast<const float2*>(xj + 4 * NZ * JS);
-        const float i2 = part ? p2.y : p2.x, i2s = part ? p2.x : p2.y;
-        const float i3 = part ? p3.y : p3.x, i3s = part ? p3.x : p3.y;
-        const float u = i2 + i3, wv = i2 - i3;
-        const float iu = sg * (i2s + i3s);    // i u
-        const float miw = -sg * (i2s - i3s); // -i w
-        yx = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, ix, yx, 0, 0, 0);
-        yy = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, iy, yy, 0, 0, 0);
-        yz = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, iz, yz, 0, 0, 0);
-        pr = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, ix, pr, 0, 0, 0);
-        ps = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, iy, ps, 0, 0, 0);
-        y3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, iz, y3, 0, 0, 0);
-        pp = __builtin_amdgcn_mfma_f32_16x16x4f32(a4, u, pp, 0, 0, 0);
-        pq = __builtin_amdgcn_mfma_f32_16x16x4f32(a5, wv, pq, 0, 0, 0);
-        yx = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, iu, yx, 0, 0, 0);
-        yy = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, miw, yy, 0, 0, 0);
-        yz = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, -i3, yz, 0, 0, 0);
-        y3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a6, i3, y3, 0, 0, 0);
+        const T* ga = gw + (code & 0x7fu);
+        const T a0 = ga[0], a1 = ga[nd], a2 = ga[2 * nd], a4 = ga[4 * nd], a5 = ga[5 * nd], a6 = ga[6 * nd];
+        const T a3 = (code & 0x80u) ? -ga[3 * nd] : ga[3 * nd];
+        const T* xj = xs + (4 * ks + (lane >> 4)) * JS + bw;
+        const T ix = xj[0 * NZ * JS + part], iy = xj[1 * NZ * JS + part], iz = xj[2 * NZ * JS + part];
+        const C p2 = *reinterpret_cast<const C*>(xj + 3 * NZ * JS);
+        const C p3 = *reinterpret_cast<const C*>(xj + 4 * NZ * JS);
+        const T i2 = part ? p2.y : p2.x, i2s = part ? p2.x : p2.y;
+        const T i3 = part ? p3.y : p3.x, i3s = part ? p3.x : p3.y;
+        const T u = i2 + i3, wv = i2 - i3;
+        const T iu = sg * (i2s + i3s);    // i u
+        const T miw = -sg * (i2s - i3s); // -i w
+        yx = M::mac(a0, ix, yx);
+        yy = M::mac(a0, iy, yy);
+        yz = M::mac(a0, iz, yz);
+        pr = M::mac(a1, ix, pr);
+        ps = M::mac(a2, iy, ps);
+        y3 = M::mac(a3, iz, y3);
+        pp = M::mac(a4, u, pp);
+        pq = M::mac(a5, wv, pq);
+        yx = M::mac(a1, iu, yx);
+        yy = M::mac(a2, miw, yy);
+        yz = M::mac(a3, -i3, yz);
+        y3 = M::mac(a6, i3, y3);
       }
-      float res[4][5];
+      T res[4][5];
 #pragma unroll
       for (int vr = 0; vr < 4; ++vr) {
-        const float d = ps[vr] - pr[vr], sm = pr[vr] + ps[vr];
-        const float ds = __shfl_xor(d, 8), ss = __shfl_xor(sm, 8);  // the other part of the same element
+        const T d = ps[vr] - pr[vr], sm = pr[vr] + ps[vr];
+        const T ds = __shfl_xor(d, 8), ss = __shfl_xor(sm, 8);  // the other part of the same element
         res[vr][0] = yx[vr];
         res[vr][1] = yy[vr];
         res[vr][2] = yz[vr];
@@ -608,9 +625,9 @@ k_zdirect5m(Geo geo, int Lx, int Ly, int nzp, int nd, int nrhs, const uint8_t* _
         for (int r2 = 0; r2 < RT; ++r2)
 #pragma unroll
           for (int vr = 0; vr < 4; ++vr) {
-            const int i = 16 * r2 + 4 * (lane >> 4) + vr;
+            const int i = 16 * r2 + M::row(lane, vr);
             if (i < nzp) {
-              float* o = xs + i * JS + bw + part;
+              T* o = xs + i * JS + bw + part;
 #pragma unroll
               for (int c = 0; c < 5; ++c) o[c * NZ * JS] = r2 == rt ? res[vr][c] : o0[vr][c];
             }
@@ -618,12 +635,12 @@ k_zdirect5m(Geo geo, int Lx, int Ly, int nzp, int nd, int nrhs, const uint8_t* _
       }
     }
     __syncthreads();
-    float2* dst = base + (size_t)(r0 + sr) * 5 * cs + (size_t)sj * plane + sw;
+    C* dst = base + (size_t)(r0 + sr) * 5 * cs + (size_t)sj * plane + sw;
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       const int c = q / (NZ / 8), h = q % (NZ / 8);
       if (sv && sj + 8 * h < nzp)
-        dst[c * cs + (size_t)(8 * h) * plane] = *reinterpret_cast<const float2*>(xst + (c * NZ + 8 * h) * JS);
+        dst[c * cs + (size_t)(8 * h) * plane] = *reinterpret_cast<const C*>(xst + (c * NZ + 8 * h) * JS);
     }
   }
 }
@@ -706,7 +723,7 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     if (ez != hipSuccess) return ez;
   } else if (p->C == 5) {
     // coupled five-component direct sum with the kernel values read from LDS
-    // (FP64, and FP32 at 25-32 planes); double: 8 pencils x 32 row groups
+    // (25-32 planes); double: 8 pencils x 32 row groups
     // (one row each), float: 16 pencils x 16 row groups
     const int nd = (int)p->dzset.size();
     const int nrhs = nvec / 5;
@@ -730,20 +747,22 @@ hipError_t launch_matvec_chunk(const svh_problem* p, int nvec, const EpiParams& 
     using I24 = std::integral_constant<int, 24>;
     using I32 = std::integral_constant<int, 32>;
     using RGmax = std::integral_constant<int, sizeof(T) == 8 ? 32 : 16>;
-    // FP32 with up to 24 planes: matrix-core Toeplitz products (k_zdirect5m),
-    // 8 pencils per block (32 planes would not fit its registers and LDS)
+    // up to 24 planes: matrix-core Toeplitz products (k_zdirect5m), 64-byte
+    // runs along x (8 pencils per block in FP32, 4 in FP64); 32 planes would
+    // not fit its registers and LDS
     auto gom = [&](auto nzt) -> hipError_t {
       constexpr int NZc = decltype(nzt)::value;
-      constexpr int W5 = 8;
+      constexpr int W5 = sizeof(T) == 4 ? 8 : 4;
+      constexpr int JS5 = W5 * 16 + (sizeof(T) == 4 ? 16 : 8);
       const int nblk = ((Lx + W5 - 1) / W5) * Ly;
-      const size_t sh = (size_t)5 * NZc * (W5 * 16 + 16) * sizeof(float) + (size_t)W5 * (7 * nd + 1) * sizeof(float);
+      const size_t sh = ((size_t)5 * NZc * JS5 + (size_t)W5 * (7 * nd + 1)) * sizeof(T);
       if (sh > (size_t)p->max_lds) return hipErrorInvalidConfiguration;
-      hipLaunchKernelGGL((k_zdirect5m<NZc, W5>), dim3(nblk), dim3(W5 * 64), sh, s, geo, Lx, Ly, nzp, nd, nrhs, p->d_qtab,
-                         static_cast<const float*>(zhat), reinterpret_cast<float2*>(B));
+      hipLaunchKernelGGL((k_zdirect5m<T, NZc, W5>), dim3(nblk), dim3(W5 * 64), sh, s, geo, Lx, Ly, nzp, nd, nrhs,
+                         p->d_qtab, static_cast<const T*>(zhat), B);
       return hipSuccess;
     };
     hipError_t ez;
-    if (sizeof(T) == 4 && NZ <= 24) {
+    if (NZ <= 24) {
       switch (NZ) {
         case 8: ez = gom(I8{}); break;
         case 16: ez = gom(I16{}); break;
