@@ -101,6 +101,7 @@ MV_CASES = [
     ((5, 4, 30), 24, 0.5, 26),         # 24 irregular planes, 24 x 24 block per pencil
     ((4, 4, 40), 32, 0.5, 27),         # 32 planes (largest direct z step)
     ((250, 3, 2), None, 0.3, 28),      # L = (512, 6, 4): one wavefront per x pencil
+    ((9, 6, 28), 21, 0.6, 33),         # 21 irregular planes: padded rows and source steps in both 16-row tiles
 ]
 
 
