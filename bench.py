@@ -729,6 +729,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-strips", action="store_true", help="skip the 16-strip solve (keep strips over ground)")
     ap.add_argument("--no-basis5", action="store_true")
     ap.add_argument("--tucker-sweep", action="store_true", help="ranks, CR and CO vs domain size (Figs. 2-3)")
     ap.add_argument("--bend-study", action="store_true", help="90-degree bend inductance vs voxel size")
@@ -768,7 +769,8 @@ def main():
         del a, b
     out = {} if args.no_matvec else bench_matvec(args, dev)
     if not args.no_solve:
-        out["solve"] = bench_solve(args)
+        if not args.no_strips:
+            out["solve"] = bench_solve(args)
         out["solve_strips_over_ground"] = bench_solve_strips_over_ground(args)
     if args.table2:
         out["table2"] = bench_table2(args)
