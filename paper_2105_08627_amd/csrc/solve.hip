@@ -466,17 +466,28 @@ __global__ void k_amg_prolong(int nrhs, int nf, int nc, const int* __restrict__ 
     if (a >= 0) x[i] = vadd(x[i], vscale(xc[(i / nf) * nc + a], kAmgAlpha));
   }
 }
-// x = Cinv b on the coarsest level (dense, row-major)
+// x = Cinv b on the coarsest level (dense, row-major): a wavefront per output
+// element, its lanes over the row and the partial sums joined by lane
+// exchanges (a thread per element left the few hundred outputs of this level
+// waiting on a chain of n loads each)
 template <class V>
 __global__ void k_amg_coarse(int nrhs, int n, const double* __restrict__ cinv, const V* __restrict__ b,
                              V* __restrict__ x, const int* __restrict__ skip) {
   SKIP_IF_DONE(skip);
-  GRID_STRIDE(i, (long long)n * nrhs) {
-    const long long base = (i / n) * n;
-    const double* row = cinv + (long long)(i % n) * n;
+  const int lane = threadIdx.x & 63;
+  const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
+  for (long long o = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); o < (long long)n * nrhs;
+       o += nw) {
+    const long long base = (o / n) * n;
+    const double* row = cinv + (o % n) * n;
     double2 acc = make_double2(0, 0);
-    for (int j = 0; j < n; ++j) acc = zadd(acc, zscale(vto2(b[base + j]), row[j]));
-    x[i] = vfrom<V>(acc);
+    for (int j = lane; j < n; j += 64) acc = zadd(acc, zscale(vto2(b[base + j]), row[j]));
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      acc.x += __shfl_xor(acc.x, m);
+      acc.y += __shfl_xor(acc.y, m);
+    }
+    if (lane == 0) x[o] = vfrom<V>(acc);
   }
 }
 
@@ -1069,7 +1080,7 @@ void vcycle(Ctx& c, const V* b0, V* x0, const int* skip, hipStream_t s) {
     const long long n = (long long)L.n * nr;
     if (l == nl - 1) {
       if (p->amg_coarse == kAmgCoarseDense) {
-        hipLaunchKernelGGL(k_amg_coarse<V>, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, p->d_amg_cinv, b, x, skip);
+        hipLaunchKernelGGL(k_amg_coarse<V>, dim3(nblocks(64 * n)), dim3(256), 0, s, nr, L.n, p->d_amg_cinv, b, x, skip);
       } else {  // diagonal matrix (exact), or damped Jacobi sweeps
         hipLaunchKernelGGL(k_amg_smooth0<V>, dim3(nblocks(n)), dim3(256), 0, s, nr, L.n, L.dinv, b, x, skip);
         for (int k = 1; k < (p->amg_coarse == kAmgCoarseJacobi ? kAmgCoarseSweeps : 1); ++k) {
