@@ -79,6 +79,10 @@ void dfree(T*& ptr) {
   ptr = nullptr;
 }
 
+// FFT length of an axis with K voxels: at least 2K - 1 (a linear convolution),
+// so an even length is at least 2K.  The x passes rely on this: with an even
+// radix the upper half of the first forward butterflies and of the last
+// inverse butterflies lies in the zero padding (positions >= L/2 >= K).
 int choose_length(int K) {
   if (supported_length(2 * K)) return 2 * K;
   for (int L = std::max(2, 2 * K - 1);; ++L)

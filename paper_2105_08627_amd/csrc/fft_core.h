@@ -110,6 +110,39 @@ template <int R, int DIR, typename C> __device__ __forceinline__ void dft(C* v) 
   else dft8<DIR>(v);
 }
 
+// Transform of R points (R even) whose upper half, inputs R/2 .. R-1, is zero:
+// the first layer of the radix-2 split reduces to copies.
+template <int R, int DIR, typename C> __device__ __forceinline__ void dft_lohalf(C* v) {
+  static_assert(R % 2 == 0, "even radix");
+  if constexpr (R == 2) {
+    v[1] = v[0];
+  } else if constexpr (R == 4) {
+    const C a0 = v[0], a2 = v[1], a3 = mul_i<DIR>(v[1]);
+    v[0] = cadd(a0, a2);
+    v[2] = csub(a0, a2);
+    v[1] = cadd(a0, a3);
+    v[3] = csub(a0, a3);
+  } else {
+    typedef decltype(v[0].x) T;
+    // 4-point transforms of (v0, v2, 0, 0) and (v1, v3, 0, 0)
+    const C ie = mul_i<DIR>(v[2]), io = mul_i<DIR>(v[3]);
+    const C e0 = cadd(v[0], v[2]), e2 = csub(v[0], v[2]), e1 = cadd(v[0], ie), e3 = csub(v[0], ie);
+    C o0 = cadd(v[1], v[3]), o2 = csub(v[1], v[3]), o1 = cadd(v[1], io), o3 = csub(v[1], io);
+    const T h = (T)0.70710678118654752440;
+    o1 = C{h * (o1.x - DIR * o1.y), h * (o1.y + DIR * o1.x)};
+    o2 = mul_i<DIR>(o2);
+    o3 = C{h * (-o3.x - DIR * o3.y), h * (-o3.y + DIR * o3.x)};
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1);
+    v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2);
+    v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3);
+    v[7] = csub(e3, o3);
+  }
+}
+
 template <int R> struct NbMax { static constexpr int v = R == 8 ? 1 : R == 4 ? 2 : R == 3 ? 3 : 4; };
 
 // LDS accessors.  Strided layout: element (n, w) at n * W + w.  Pencil
@@ -166,6 +199,11 @@ __device__ __forceinline__ void stage_r(int L, int Ns, int j0, int TP, const Src
                                         const C* __restrict__ tw) {
   constexpr int NB = NbMax<R>::v;
   constexpr bool SC = IsScatter<Dst>::value;
+  // A scatter destination takes the last stage (Ns R = L, outputs j + r L/R)
+  // of an x pencil padded to L >= 2 Kx: with an even radix the outputs
+  // r >= R/2 lie at L/2 or beyond, in the discarded padding, so only the
+  // first RS outputs of each butterfly are looked up and stored.
+  constexpr int RS = (SC && R % 2 == 0) ? R / 2 : R;
   const int LR = L / R;
   // scatter outputs: indices first, then (after the LDS reads) the operands
   // of the diagonal terms, global loads that overlap the butterflies
@@ -180,14 +218,14 @@ __device__ __forceinline__ void stage_r(int L, int Ns, int j0, int TP, const Src
 #pragma unroll
       for (int it = 0; it < NB; ++it)
 #pragma unroll
-        for (int r = 0; r < R; ++r) wd[it][r] = dst.row.word_u(wq + ((it * TP + r * Ns) >> 6));
+        for (int r = 0; r < RS; ++r) wd[it][r] = dst.row.word_u(wq + ((it * TP + r * Ns) >> 6));
     } else {
 #pragma unroll
       for (int it = 0; it < NB; ++it) {
         const int j = j0 + it * TP;
         const int base = (j / Ns) * Ns * R + j % Ns;
 #pragma unroll
-        for (int r = 0; r < R; ++r) wd[it][r] = dst.row.word(j < LR ? base + r * Ns : 0);
+        for (int r = 0; r < RS; ++r) wd[it][r] = dst.row.word(j < LR ? base + r * Ns : 0);
       }
     }
 #pragma unroll
@@ -195,7 +233,7 @@ __device__ __forceinline__ void stage_r(int L, int Ns, int j0, int TP, const Src
       const int j = j0 + it * TP;
       const int base = (j / Ns) * Ns * R + j % Ns;
 #pragma unroll
-      for (int r = 0; r < R; ++r) kk[it][r] = j < LR ? dst.row.index(base + r * Ns, wd[it][r]) : -1;
+      for (int r = 0; r < RS; ++r) kk[it][r] = j < LR ? dst.row.index(base + r * Ns, wd[it][r]) : -1;
     }
   }
   C v[NB][R];
@@ -234,7 +272,7 @@ __device__ __forceinline__ void stage_r(int L, int Ns, int j0, int TP, const Src
 #pragma unroll
     for (int it = 0; it < NB; ++it)
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
+      for (int r = 0; r < RS; ++r) {
         // last stage (n = j + r Ns): outputs r Ns + (it TP ..) wholly past Kx
         // (a uniform branch) are not stored, so they need no operands
         if (Ns * R == L && r * Ns + it * TP >= dst.row.Kx) dg[it][r] = DiagPair<C>{C{0, 0}, C{0, 0}};
@@ -261,7 +299,7 @@ __device__ __forceinline__ void stage_r(int L, int Ns, int j0, int TP, const Src
       const int base = (j / Ns) * Ns * R + k;
       if constexpr (SC) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) dst.put(kk[it][r], v[it][r], dg[it][r]);
+        for (int r = 0; r < RS; ++r) dst.put(kk[it][r], v[it][r], dg[it][r]);
       } else {
 #pragma unroll
         for (int r = 0; r < R; ++r) dst.st(base + r * Ns, v[it][r]);
@@ -310,6 +348,10 @@ __device__ __forceinline__ void load0_r(int L, int j0, int TP, const Src& src, C
   constexpr int NB = NbMax<R>::v;
   const int LR = L / R;
   if constexpr (IsGather<Src>::value) {
+    // An x pencil is zero-padded to at least twice its data (L >= 2 Kx for
+    // every even L), so with an even radix the rows r >= R/2, positions
+    // >= L/2, are zero padding: they are not looked up (RH rows are).
+    constexpr int RH = R % 2 == 0 ? R / 2 : R;
     // all occupancy lookups first, then all value loads
     int4 wd[NB * R];
     if constexpr (Src::kUniform) {
@@ -318,7 +360,7 @@ __device__ __forceinline__ void load0_r(int L, int j0, int TP, const Src& src, C
 #pragma unroll
       for (int it = 0; it < NB; ++it)
 #pragma unroll
-        for (int r = 0; r < R; ++r)
+        for (int r = 0; r < RH; ++r)
           wd[it * R + r] = r * LR + it * TP >= src.row.Kx ? int4{0, 0, 0, 0}
                                                           : src.row.word_u(wq + ((it * TP + r * LR) >> 6));
     } else {
@@ -326,7 +368,7 @@ __device__ __forceinline__ void load0_r(int L, int j0, int TP, const Src& src, C
       for (int it = 0; it < NB; ++it) {
         const int j = j0 + it * TP;
 #pragma unroll
-        for (int r = 0; r < R; ++r) wd[it * R + r] = src.row.word(j < LR ? j + r * LR : 0);
+        for (int r = 0; r < RH; ++r) wd[it * R + r] = src.row.word(j < LR ? j + r * LR : 0);
       }
     }
     int k[NB * R];
@@ -334,7 +376,7 @@ __device__ __forceinline__ void load0_r(int L, int j0, int TP, const Src& src, C
     for (int it = 0; it < NB; ++it) {
       const int j = j0 + it * TP;
 #pragma unroll
-      for (int r = 0; r < R; ++r) k[it * R + r] = j < LR ? src.row.index(j + r * LR, wd[it * R + r]) : -1;
+      for (int r = 0; r < RH; ++r) k[it * R + r] = j < LR ? src.row.index(j + r * LR, wd[it * R + r]) : -1;
     }
 #pragma unroll
     for (int it = 0; it < NB; ++it)
@@ -342,7 +384,7 @@ __device__ __forceinline__ void load0_r(int L, int j0, int TP, const Src& src, C
       for (int r = 0; r < R; ++r) {
         // rows r LR + (it TP ..) wholly in the zero padding (past Kx on every
         // lane: a uniform branch) load nothing
-        if (r * LR + it * TP >= src.row.Kx) v[it * R + r] = C{0, 0};
+        if (r >= RH || r * LR + it * TP >= src.row.Kx) v[it * R + r] = C{0, 0};
         else v[it * R + r] = src.at(k[it * R + r]);
       }
   } else {
@@ -356,7 +398,8 @@ __device__ __forceinline__ void load0_r(int L, int j0, int TP, const Src& src, C
     }
   }
 }
-template <typename C, int R, int DIR, class Dst>
+// LH: the inputs r >= R/2 are zero (the first stage of a gather source, R even).
+template <typename C, int R, int DIR, class Dst, bool LH = false>
 __device__ __forceinline__ void fin0_r(int L, int j0, int TP, C (&v)[12], const Dst& dst) {
   constexpr int NB = NbMax<R>::v;
   const int LR = L / R;
@@ -364,7 +407,8 @@ __device__ __forceinline__ void fin0_r(int L, int j0, int TP, C (&v)[12], const 
   for (int it = 0; it < NB; ++it) {
     const int j = j0 + it * TP;
     if (j < LR) {
-      dft<R, DIR>(&v[it * R]);
+      if constexpr (LH) dft_lohalf<R, DIR>(&v[it * R]);
+      else dft<R, DIR>(&v[it * R]);
 #pragma unroll
       for (int r = 0; r < R; ++r) dst.st(j * R + r, v[it * R + r]);
     }
@@ -463,16 +507,19 @@ __device__ __forceinline__ void fft_items_c(int j0, int nitems, const MkIn& mk_i
     if constexpr (WAVE) wave_sync();
     else __syncthreads();
   };
+  // a gather source with an even first radix leaves the upper half of every
+  // first-stage butterfly zero (load0_r)
+  constexpr bool LH = IsGather<decltype(mk_in(0))>::value && R0 % 2 == 0;
   C v[12];
   int item = first_item();
   if (item < nitems) load0_r<C, R0>(L, j0, TP, mk_in(item), v);
   for (; item < nitems; item += gridDim.x) {
     const int next = item + gridDim.x;
     if constexpr (P::ns == 1) {
-      fin0_r<C, R0, DIR>(L, j0, TP, v, mk_out(item));
+      fin0_r<C, R0, DIR, decltype(mk_out(item)), LH>(L, j0, TP, v, mk_out(item));
       if (next < nitems) load0_r<C, R0>(L, j0, TP, mk_in(next), v);
     } else {
-      fin0_r<C, R0, DIR>(L, j0, TP, v, lds);
+      fin0_r<C, R0, DIR, Lds<C, STRIDED>, LH>(L, j0, TP, v, lds);
       sync();
       if (next < nitems) load0_r<C, R0>(L, j0, TP, mk_in(next), v);
       constexpr int N1 = R0;
