@@ -16,7 +16,7 @@
 namespace svh {
 
 constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;  // H/m (mu = mu0, Sec. II.A)
-constexpr int kMaxVecsPerChunk = 256;  // component vectors per pass launch
+constexpr int kMaxVecsPerChunk = 320;  // component vectors per pass launch (64 RHS of five components)
 constexpr int kMaxStages = 8;
 constexpr int kMaxDirectPlanes = 32;  // direct z sum when at most this many planes are occupied
 // Piecewise-linear basis (eqs. 4-8): seven voxel-pair integral families
