@@ -169,6 +169,15 @@ template <class A, class = void> struct IsGather : std::false_type {};
 template <class A> struct IsGather<A, std::void_t<decltype(A::kGather)>> : std::true_type {};
 template <class A, class = void> struct IsScatter : std::false_type {};
 template <class A> struct IsScatter<A, std::void_t<decltype(A::kScatter)>> : std::true_type {};
+// Padding known at compile time.  LowHalf: a transform input whose positions
+// at L/2 or beyond are zero (a pencil zero-padded to at least twice its data:
+// every even FFT length is at least 2K), read by the first stage only.
+// DropUpper: a transform output whose positions at L/2 or beyond are
+// discarded (the crop of the inverse), written by the last stage only.
+template <class A, class = void> struct LowHalf : std::false_type {};
+template <class A> struct LowHalf<A, std::void_t<decltype(A::kLowHalf)>> : std::bool_constant<A::kLowHalf> {};
+template <class A, class = void> struct DropUpper : std::false_type {};
+template <class A> struct DropUpper<A, std::void_t<decltype(A::kDropUpper)>> : std::bool_constant<A::kDropUpper> {};
 
 // Twiddle table of a length-L transform copied into LDS at `dst` (after the
 // block's work area) once per block.  The stages then read twiddles from LDS,
@@ -199,11 +208,14 @@ __device__ __forceinline__ void stage_r(int L, int Ns, int j0, int TP, const Src
                                         const C* __restrict__ tw) {
   constexpr int NB = NbMax<R>::v;
   constexpr bool SC = IsScatter<Dst>::value;
-  // A scatter destination takes the last stage (Ns R = L, outputs j + r L/R)
-  // of an x pencil padded to L >= 2 Kx: with an even radix the outputs
-  // r >= R/2 lie at L/2 or beyond, in the discarded padding, so only the
-  // first RS outputs of each butterfly are looked up and stored.
-  constexpr int RS = (SC && R % 2 == 0) ? R / 2 : R;
+  // A DropUpper destination takes the last stage (Ns R = L, outputs
+  // j + r L/R): with an even radix the outputs r >= R/2 lie at L/2 or beyond,
+  // in the discarded padding, so only the first RS outputs of each butterfly
+  // are looked up and stored.  A LowHalf source feeds the first stage (Ns = 1,
+  // no twiddles): with an even radix its rows r >= R/2 are zero, so only the
+  // first RH are read and the butterflies take half their inputs.
+  constexpr int RS = (DropUpper<Dst>::value && R % 2 == 0) ? R / 2 : R;
+  constexpr int RH = (LowHalf<Src>::value && !IsGather<Src>::value && R % 2 == 0) ? R / 2 : R;
   const int LR = L / R;
   // scatter outputs: indices first, then (after the LDS reads) the operands
   // of the diagonal terms, global loads that overlap the butterflies
@@ -264,7 +276,7 @@ __device__ __forceinline__ void stage_r(int L, int Ns, int j0, int TP, const Src
       const int j = j0 + it * TP;
       if (j < LR) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[it][r] = src.ld(j + r * LR);
+        for (int r = 0; r < R; ++r) v[it][r] = r < RH ? src.ld(j + r * LR) : C{0, 0};
       }
     }
   }
@@ -295,14 +307,15 @@ __device__ __forceinline__ void stage_r(int L, int Ns, int j0, int TP, const Src
           v[it][r] = cmul(v[it][r], t);
         }
       }
-      dft<R, DIR>(v[it]);
+      if constexpr (RH < R) dft_lohalf<R, DIR>(v[it]);
+      else dft<R, DIR>(v[it]);
       const int base = (j / Ns) * Ns * R + k;
       if constexpr (SC) {
 #pragma unroll
         for (int r = 0; r < RS; ++r) dst.put(kk[it][r], v[it][r], dg[it][r]);
       } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r) dst.st(base + r * Ns, v[it][r]);
+        for (int r = 0; r < RS; ++r) dst.st(base + r * Ns, v[it][r]);
       }
     }
   }
@@ -347,11 +360,10 @@ template <typename C, int R, class Src>
 __device__ __forceinline__ void load0_r(int L, int j0, int TP, const Src& src, C (&v)[12]) {
   constexpr int NB = NbMax<R>::v;
   const int LR = L / R;
+  // with an input zero at L/2 and beyond and an even radix, the rows
+  // r >= R/2 are zero padding: only the first RH rows are loaded
+  constexpr int RH = (LowHalf<Src>::value && R % 2 == 0) ? R / 2 : R;
   if constexpr (IsGather<Src>::value) {
-    // An x pencil is zero-padded to at least twice its data (L >= 2 Kx for
-    // every even L), so with an even radix the rows r >= R/2, positions
-    // >= L/2, are zero padding: they are not looked up (RH rows are).
-    constexpr int RH = R % 2 == 0 ? R / 2 : R;
     // all occupancy lookups first, then all value loads
     int4 wd[NB * R];
     if constexpr (Src::kUniform) {
@@ -393,12 +405,12 @@ __device__ __forceinline__ void load0_r(int L, int j0, int TP, const Src& src, C
       const int j = j0 + it * TP;
       if (j < LR) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[it * R + r] = src.ld(j + r * LR);
+        for (int r = 0; r < R; ++r) v[it * R + r] = r < RH ? src.ld(j + r * LR) : C{0, 0};
       }
     }
   }
 }
-// LH: the inputs r >= R/2 are zero (the first stage of a gather source, R even).
+// LH: the inputs r >= R/2 are zero (the first stage of a LowHalf source, R even).
 template <typename C, int R, int DIR, class Dst, bool LH = false>
 __device__ __forceinline__ void fin0_r(int L, int j0, int TP, C (&v)[12], const Dst& dst) {
   constexpr int NB = NbMax<R>::v;
@@ -507,9 +519,9 @@ __device__ __forceinline__ void fft_items_c(int j0, int nitems, const MkIn& mk_i
     if constexpr (WAVE) wave_sync();
     else __syncthreads();
   };
-  // a gather source with an even first radix leaves the upper half of every
+  // a LowHalf source with an even first radix leaves the upper half of every
   // first-stage butterfly zero (load0_r)
-  constexpr bool LH = IsGather<decltype(mk_in(0))>::value && R0 % 2 == 0;
+  constexpr bool LH = LowHalf<decltype(mk_in(0))>::value && R0 % 2 == 0;
   C v[12];
   int item = first_item();
   if (item < nitems) load0_r<C, R0>(L, j0, TP, mk_in(item), v);
@@ -643,6 +655,7 @@ template <class P> constexpr bool wave_pencils() {
 // (ld() does all three for other callers).
 template <typename C, bool UNI = false> struct XIn {
   static constexpr bool kGather = true;
+  static constexpr bool kLowHalf = true;  // positions >= L/2 >= Kx are padding
   static constexpr bool kUniform = UNI;
   const C* __restrict__ x;              // compact vector of this component
   XRow<UNI> row;
@@ -656,6 +669,7 @@ template <typename C, bool UNI = false> struct XIn {
 // output, split like XIn: a stage looks up all indices of its outputs first.
 template <typename C, typename T, bool UNI = false> struct XOut {
   static constexpr bool kScatter = true;
+  static constexpr bool kDropUpper = true;  // positions >= L/2 >= Kx are cropped
   static constexpr bool kUniform = UNI;
   C* __restrict__ y;                 // compact output of this component
   const C* __restrict__ x;           // compact input (diagonal term)

@@ -40,14 +40,23 @@ namespace svh {
 namespace {
 
 // LDS pencils in the pencil layout of Lds<C, false> (element (n, w) at
-// w * Lp + n + n / 8); positions whose z plane is empty read as zero.
+// w * Lp + n + n / 8); positions whose z plane is empty read as zero, and
+// so do all positions at Lz/2 or beyond (Lz >= 2 Kz), which the first stage
+// does not read.
 template <typename C> struct LdsOcc {
+  static constexpr bool kLowHalf = true;
   C* base;
   int Lp, w;
   const uint8_t* occ;
   __device__ __forceinline__ C ld(int n) const { return occ[n] ? base[w * Lp + n + (n >> 3)] : C{0, 0}; }
 };
 __device__ __forceinline__ int pencil_at(int w, int n, int Lp) { return w * Lp + n + (n >> 3); }
+// The same pencils as the destination of the last inverse stage: only planes
+// below Kz <= Lz/2 are stored afterwards, so outputs at Lz/2 or beyond are
+// not written.
+template <typename C> struct LdsCrop : Lds<C, false> {
+  static constexpr bool kDropUpper = true;
+};
 
 // Ordering of the LDS stages of one pencil: the lanes of a pencil are
 // consecutive threads, so when the pencils do not straddle wavefronts
@@ -247,7 +256,8 @@ __device__ __forceinline__ void zfft_items(const ZfftArgs<T>& a, int kx0, int ky
       pencil_sync<WAVE>();
       int Ns = R;
       for (int s = 1; s < ns; ++s) {
-        stage_any<C, +1, SM>(a.ipl.r[s], L, Ns, j0, TP, lds, lds, twl);
+        if (s < ns - 1) stage_any<C, +1, SM>(a.ipl.r[s], L, Ns, j0, TP, lds, lds, twl);
+        else stage_any<C, +1, SM>(a.ipl.r[s], L, Ns, j0, TP, lds, LdsCrop<C>{lds}, twl);
         Ns *= a.ipl.r[s];
         pencil_sync<WAVE>();
       }
